@@ -1,0 +1,472 @@
+"""Pins for the FP64 oracle: each check compares it with something other than
+itself -- dense matrices built tap by tap, brute-force spatial sums, closed
+forms and invariants the paper's equations imply.
+
+Dense helpers here are written independently of ``oracle`` (explicit loops,
+no FFT), so a dropped term, a wrong sign, a conjugation or a transposed
+operand in the oracle makes one of these fail.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+
+RNG = np.random.default_rng(12345)
+
+
+# ---------------------------------------------------------------- dense tools
+
+def conv_matrix(dk, grid):
+    """Dense D x D matrix of circular convolution with filter dk (corner
+    anchored): (D_k z)[p] = sum_m dk[m] z[(p - m) mod grid]."""
+    D = int(np.prod(grid))
+    A = np.zeros((D, D))
+    pts = list(itertools.product(*[range(g) for g in grid]))
+    idx = {p: i for i, p in enumerate(pts)}
+    for p in pts:
+        for m in itertools.product(*[range(s) for s in dk.shape]):
+            q = tuple((pi - mi) % g for pi, mi, g in zip(p, m, grid))
+            A[idx[p], idx[q]] += dk[m]
+    return A
+
+
+def dict_matrix(d, grid):
+    """Block matrix D of size JD x KD (Sec. 3.3): block (j, k) = conv(d[k, j])."""
+    K, J = d.shape[:2]
+    rows = []
+    for j in range(J):
+        rows.append(np.hstack([conv_matrix(d[k, j], grid) for k in range(K)]))
+    return np.vstack(rows)
+
+
+def brute_conv(d, z):
+    """Spatial brute-force sum_k d_jk * z_k for one image: z [K][*grid]."""
+    K, J = d.shape[:2]
+    grid = z.shape[1:]
+    out = np.zeros((J,) + grid)
+    for j in range(J):
+        for k in range(K):
+            for m in itertools.product(*[range(s) for s in d.shape[2:]]):
+                out[j] += d[k, j][m] * np.roll(z[k], shift=m, axis=tuple(range(len(grid))))
+    return out
+
+
+def dense_admm(x, Dm, beta, rho, iters, z=None, th=None):
+    """eq:Inference_solution with explicit matrices (one image, x of length JD)."""
+    KD = Dm.shape[1]
+    z = np.zeros(KD) if z is None else z.copy()
+    th = np.zeros(KD) if th is None else th.copy()
+    A = Dm @ Dm.T + np.eye(Dm.shape[0]) / rho
+    hist = []
+    for _ in range(iters):
+        lam = np.linalg.solve(A, Dm @ th + Dm @ z / rho - x / rho)
+        v = Dm.T @ lam
+        th_new = np.clip(v - z / rho, -beta, beta)
+        z_new = z + rho * (th_new - v)
+        hist.append(dict(lam=lam, r_pri=np.linalg.norm(th_new - v),
+                         r_dual=rho * np.linalg.norm(Dm @ (th_new - th)),
+                         z=z_new, th=th_new, z_prev=z, th_prev=th))
+        z, th = z_new, th_new
+    return z, th, hist
+
+
+def rand_filters(K, J, fs, rng=RNG):
+    d = rng.standard_normal((K, J) + fs)
+    return d / np.sqrt((d.reshape(K, -1) ** 2).sum(1)).reshape((K,) + (1,) * (d.ndim - 1))
+
+
+# ------------------------------------------------------------------ P1 / P13
+
+@pytest.mark.parametrize("grid,fs,J", [((8, 8), (3, 3), 1), ((16, 12), (5, 4), 1),
+                                        ((6, 8, 8), (2, 3, 3), 1), ((8, 8), (3, 3), 3)])
+def test_convolution_convention_bruteforce(grid, fs, J):
+    K = 3
+    d = rand_filters(K, J, fs)
+    z = RNG.standard_normal((2, K) + grid)
+    rec = oracle.reconstruct(d, z)
+    for n in range(2):
+        np.testing.assert_allclose(rec[n], brute_conv(d, z[n]), atol=1e-12, rtol=0)
+
+
+def test_objective_bruteforce():
+    grid, fs, K, J = (8, 10), (3, 3), 3, 2
+    d = rand_filters(K, J, fs)
+    z = RNG.standard_normal((2, K) + grid) * (RNG.random((2, K) + grid) < 0.3)
+    b = RNG.standard_normal((2, J) + grid)
+    beta = 0.7
+    per, tot = oracle.objective(b, d, z, beta)
+    for n in range(2):
+        res = b[n] - brute_conv(d, z[n])
+        ref = 0.5 * (res ** 2).sum() + beta * np.abs(z[n]).sum()
+        assert abs(per[n] - ref) <= 1e-12 * abs(ref)
+    assert abs(tot - per.sum()) <= 1e-12 * abs(tot)
+
+
+def test_parseval_scaling():
+    x = RNG.standard_normal((16, 8))
+    xh = np.fft.fftn(x)
+    assert abs((x ** 2).sum() - (np.abs(xh) ** 2).sum() / x.size) < 1e-12 * (x ** 2).sum()
+
+
+# ------------------------------------------------------------- P3 / P6 coding
+
+@pytest.mark.parametrize("J", [1, 2, 3])
+def test_coding_matches_dense_admm(J):
+    grid, fs, K = (6, 6), (3, 3), 2
+    d = rand_filters(K, J, fs)
+    b = RNG.standard_normal((1, J) + grid) * 2
+    beta, rho, T = 0.3, 1.7, 12
+    Dm = dict_matrix(d, grid)
+    z_ref, th_ref, hist = dense_admm(b[0].reshape(-1), Dm, beta, rho, T)
+    out = oracle.code(b, d, beta, rho, T)
+    np.testing.assert_allclose(out["z"][0].reshape(-1), z_ref, atol=1e-12)
+    np.testing.assert_allclose(out["theta"][0].reshape(-1), th_ref, atol=1e-12)
+    res_ref = np.array([[h["r_pri"], h["r_dual"]] for h in hist])
+    np.testing.assert_allclose(out["resid"][:, 0], res_ref, rtol=1e-10, atol=1e-13)
+    assert np.count_nonzero(out["z"]) > 0
+
+
+def test_coding_warm_start_matches_dense():
+    grid, fs, K, J = (6, 6), (3, 3), 3, 1
+    d = rand_filters(K, J, fs)
+    b = RNG.standard_normal((2, J) + grid) * 3
+    z0 = RNG.standard_normal((2, K) + grid) * (RNG.random((2, K) + grid) < 0.3)
+    th0 = np.clip(RNG.standard_normal((2, K) + grid), -0.4, 0.4)
+    beta, rho, T = 0.4, 0.9, 7
+    out = oracle.code(b, d, beta, rho, T, z0=z0, theta0=th0)
+    Dm = dict_matrix(d, grid)
+    for n in range(2):
+        z_ref, th_ref, _ = dense_admm(b[n].reshape(-1), Dm, beta, rho, T,
+                                      z0[n].reshape(-1), th0[n].reshape(-1))
+        np.testing.assert_allclose(out["z"][n].reshape(-1), z_ref, atol=1e-12)
+        np.testing.assert_allclose(out["theta"][n].reshape(-1), th_ref, atol=1e-12)
+
+
+def test_residual_identity_and_dual_sign():
+    """rho D (theta^i - theta^{i+1}) = lam^{i+1} + x - D z^{i+1}; at the fixed
+    point lam* = D z* - x (the dual optimum of eq:Inference_Dual)."""
+    grid, fs, K = (6, 6), (3, 3), 2
+    d = rand_filters(K, 1, fs)
+    x = RNG.standard_normal(36) * 2
+    Dm = dict_matrix(d, grid)
+    rho = 1.3
+    _, _, hist = dense_admm(x, Dm, 0.2, rho, 5000)
+    for h in hist[:20]:
+        lhs = rho * Dm @ (h["th_prev"] - h["th"])
+        rhs = h["lam"] + x - Dm @ h["z"]
+        np.testing.assert_allclose(lhs, rhs, atol=1e-12)
+    h = hist[-1]
+    np.testing.assert_allclose(h["lam"], Dm @ h["z"] - x, atol=1e-8)
+    # and the oracle reaches the same point
+    out = oracle.code(x.reshape(1, 1, *grid), d, 0.2, rho, 5000)
+    np.testing.assert_allclose(out["z"][0].reshape(-1), h["z"], atol=1e-10)
+
+
+def test_moreau_soft_threshold_form():
+    """z + rho (clip(v - z/rho, +-beta) - v) == soft(z - rho v, rho beta)."""
+    z = RNG.standard_normal(1000) * 3
+    v = RNG.standard_normal(1000) * 2
+    rho, beta = 2.5, 0.6
+    lhs = z + rho * (np.clip(v - z / rho, -beta, beta) - v)
+    np.testing.assert_allclose(lhs, oracle.soft(z - rho * v, rho * beta), atol=1e-12)
+    # soft threshold closed form on a few points
+    assert oracle.soft(np.array([3.0, -3.0, 0.5, -0.5]), 1.0).tolist() == [2.0, -2.0, 0.0, -0.0]
+
+
+@pytest.mark.parametrize("J", [1, 3])
+def test_implicit_theta_form_equals_literal(J):
+    grid, fs, K = (12, 12), (5, 5), 4
+    d = rand_filters(K, J, fs)
+    b = RNG.standard_normal((2, J) + grid) * 3
+    z0 = RNG.standard_normal((2, K) + grid) * (RNG.random((2, K) + grid) < 0.2)
+    th0 = np.clip(RNG.standard_normal((2, K) + grid), -0.5, 0.5)
+    lit = oracle.code(b, d, 0.5, 2.0, 30, z0=z0, theta0=th0)
+    imp = oracle.code_implicit(b, d, 0.5, 2.0, 30, z0=z0, theta0=th0)
+    np.testing.assert_allclose(imp["z"], lit["z"], atol=1e-11)
+    np.testing.assert_allclose(imp["theta"], lit["theta"], atol=1e-11)
+
+
+# ------------------------------------------------------- P7 / P8 convergence
+
+def test_kkt_at_convergence_and_residuals_vanish():
+    grid, fs, K = (16, 16), (5, 5), 4
+    d = rand_filters(K, 1, fs)
+    b = RNG.standard_normal((1, 1) + grid) * 3
+    beta, rho = 1.0, 1.0
+    out = oracle.code(b, d, beta, rho, 3000)
+    z = out["z"][0]
+    g = np.zeros_like(z)
+    Dm = dict_matrix(d, grid)
+    g = (Dm.T @ (b[0, 0].reshape(-1) - Dm @ z.reshape(-1))).reshape(z.shape)
+    on = z != 0
+    assert on.sum() > 0
+    np.testing.assert_allclose(g[on], beta * np.sign(z[on]), atol=1e-8)
+    assert np.abs(g[~on]).max() <= beta + 1e-8
+    r = out["resid"][:, 0]
+    assert r[-1, 0] < 1e-8 * max(1.0, r[0, 0]) and r[-1, 1] < 1e-8 * max(1.0, r[0, 1])
+
+
+def test_delta_filter_gives_soft_threshold():
+    """K = 1 with a corner delta filter makes D the identity, so the lasso
+    solution is soft(x, beta)."""
+    grid = (16, 16)
+    d = np.zeros((1, 1, 3, 3))
+    d[0, 0, 0, 0] = 1.0
+    b = RNG.standard_normal((2, 1) + grid) * 2
+    out = oracle.code(b, d, 0.8, 2.0, 200)
+    np.testing.assert_allclose(out["z"][:, 0], oracle.soft(b[:, 0], 0.8), atol=1e-12)
+
+
+# ---------------------------------------------------------------- P9 tensor
+
+def test_tensor_equal_channels_reduce_to_plain():
+    """J equal channels x_j = x with d_jk = d_k / sqrt(J) give the codes of
+    plain CSC on sqrt(J) x (sum_j ||x - Dz/sqrt J||^2 = ||sqrt J x - D z||^2 + c)."""
+    grid, fs, K, J = (12, 12), (5, 5), 3, 3
+    d1 = rand_filters(K, 1, fs)
+    x = RNG.standard_normal((2, 1) + grid) * 3
+    dJ = np.repeat(d1, J, axis=1) / np.sqrt(J)
+    bJ = np.repeat(x, J, axis=1)
+    a = oracle.code(bJ, dJ, 0.5, 1.5, 25)
+    p = oracle.code(np.sqrt(J) * x, d1, 0.5, 1.5, 25)
+    np.testing.assert_allclose(a["z"], p["z"], atol=1e-11)
+    assert np.count_nonzero(p["z"]) > 0
+
+
+def test_tensor_3d_matches_dense():
+    grid, fs, K, J = (4, 4, 4), (2, 2, 2), 2, 2
+    d = rand_filters(K, J, fs)
+    b = RNG.standard_normal((1, J) + grid) * 2
+    Dm = dict_matrix(d, grid)
+    z_ref, th_ref, _ = dense_admm(b[0].reshape(-1), Dm, 0.3, 1.1, 6)
+    out = oracle.code(b, d, 0.3, 1.1, 6)
+    np.testing.assert_allclose(out["z"][0].reshape(-1), z_ref, atol=1e-12)
+
+
+# ------------------------------------------------------------- adaptive rho
+
+def test_adaptive_rho_replay_and_rule():
+    grid, fs, K = (16, 16), (5, 5), 4
+    d = rand_filters(K, 1, fs)
+    b = RNG.standard_normal((3, 1) + grid) * 4
+    out = oracle.code(b, d, 1.0, 10.0, 25, adaptive=True)
+    sched, res = out["rho"], out["resid"]
+    ratio = sched[1:] / sched[:-1]
+    assert set(np.unique(np.round(ratio, 12))) <= {0.5, 1.0, 2.0}
+    for i in range(25):
+        for n in range(3):
+            rp, rd = res[i, n]
+            want = 2.0 if rp > 10 * rd else (0.5 if rd > 10 * rp else 1.0)
+            assert ratio[i, n] == want
+    assert (ratio != 1.0).any()
+    rep = oracle.code(b, d, 1.0, 10.0, 25, rho_schedule=sched)
+    np.testing.assert_array_equal(rep["z"], out["z"])
+
+
+# -------------------------------------------------------- P10 / P11 learning
+
+def learning_dense(x, z, fs, mu):
+    """Primal ridge of eq:Learning_new by dense normal equations for one
+    channel: argmin_d 1/2 ||x - Z S^T d||^2 + sum_k mu_k ||d_k||^2.
+    x [N][*grid], z [N][K][*grid] -> d [K][*fs]."""
+    N, K = z.shape[:2]
+    grid = z.shape[2:]
+    M = int(np.prod(fs))
+    cols = []
+    for k in range(K):
+        for m in itertools.product(*[range(s) for s in fs]):
+            col = np.concatenate([np.roll(z[n, k], shift=m, axis=tuple(range(len(grid)))).reshape(-1)
+                                  for n in range(N)])
+            cols.append(col)
+    W = np.array(cols).T                                   # ND x KM
+    reg = np.repeat(2 * np.asarray(mu), M)
+    dvec = np.linalg.solve(W.T @ W + np.diag(reg), W.T @ x.reshape(-1))
+    return dvec.reshape((K,) + tuple(fs)), W
+
+
+def test_learning_dual_equals_primal_ridge():
+    N, K, grid, fs = 2, 2, (6, 6), (3, 3)
+    z = RNG.standard_normal((N, K) + grid) * (RNG.random((N, K) + grid) < 0.5)
+    b = RNG.standard_normal((N, 1) + grid)
+    mu = np.array([0.7, 1.9])
+    d_ref, W = learning_dense(b[:, 0], z, fs, mu)
+    d, mu_out, gamma = oracle.learn(b, z, fs, mu, None, inner_iters=1, cg_iters=300)
+    nrm = np.sqrt((d_ref.reshape(K, -1) ** 2).sum(1))
+    want = d_ref / np.maximum(1.0, nrm).reshape(K, 1, 1)
+    np.testing.assert_allclose(d[:, 0], want, atol=1e-12)
+    np.testing.assert_allclose(mu_out, mu * nrm, rtol=1e-12)
+    # gamma* = Z S^T d* - x
+    np.testing.assert_allclose(gamma[:, 0].reshape(-1), W @ d_ref.reshape(-1) - b[:, 0].reshape(-1),
+                               atol=1e-11)
+
+
+def test_learning_tensor_separates_over_channels():
+    N, K, J, grid, fs = 2, 2, 3, (6, 6), (3, 3)
+    z = RNG.standard_normal((N, K) + grid) * (RNG.random((N, K) + grid) < 0.5)
+    b = RNG.standard_normal((N, J) + grid)
+    mu = np.array([1.3, 0.8])
+    d, mu_out, _ = oracle.learn(b, z, fs, mu, None, inner_iters=1, cg_iters=300)
+    ref = np.stack([learning_dense(b[:, j], z, fs, mu)[0] for j in range(J)], axis=1)
+    nrm = np.sqrt((ref.reshape(K, -1) ** 2).sum(1))        # norm over channels and taps
+    np.testing.assert_allclose(d, ref / np.maximum(1.0, nrm).reshape(K, 1, 1, 1), atol=1e-12)
+    np.testing.assert_allclose(mu_out, mu * nrm, rtol=1e-12)
+
+
+def test_cg_fixed_count_matches_dense_steps():
+    """A few CG iterations agree with CG on the dense operator
+    I + sum_k W_k W_k^T / (2 mu_k)."""
+    N, K, grid, fs = 2, 2, (6, 6), (3, 3)
+    z = RNG.standard_normal((N, K) + grid) * (RNG.random((N, K) + grid) < 0.5)
+    b = RNG.standard_normal((N, 1) + grid)
+    mu = np.array([0.9, 1.1])
+    _, W = learning_dense(b[:, 0], z, fs, mu)
+    M = int(np.prod(fs))
+    A = np.eye(W.shape[0]) + (W / np.repeat(2 * mu, M)) @ W.T
+    x = np.zeros(W.shape[0])
+    rhs = -b[:, 0].reshape(-1)
+    r = rhs - A @ x
+    p = r.copy()
+    rr = r @ r
+    for _ in range(4):
+        ap = A @ p
+        al = rr / (p @ ap)
+        x += al * p
+        r -= al * ap
+        rn = r @ r
+        p = r + rn / rr * p
+        rr = rn
+    _, _, gamma = oracle.learn(b, z, fs, mu, None, inner_iters=1, cg_iters=4)
+    np.testing.assert_allclose(gamma[:, 0].reshape(-1), x, atol=1e-12)
+
+
+def test_mu_iteration_fixed_point_unit_norm():
+    """eq:mu_update: with the constraint active (codes small next to the
+    images, so the unregularised filters would be long) ||d_k|| -> 1 and mu is
+    a fixed point; with it inactive mu -> 0 and ||d_k|| < 1 (complementary
+    slackness)."""
+    N, K, grid, fs = 2, 3, (12, 12), (4, 4)
+    mask = RNG.random((N, K) + grid) < 0.3
+    z = RNG.standard_normal((N, K) + grid) * mask * 0.3
+    b = RNG.standard_normal((N, 1) + grid) * 3
+    d, mu, _ = oracle.learn(b, z, fs, np.ones(K), None, inner_iters=80, cg_iters=200)
+    nrm = np.sqrt((d.reshape(K, -1) ** 2).sum(1))
+    np.testing.assert_allclose(nrm, 1.0, atol=1e-6)
+    d2, mu2, _ = oracle.learn(b, z, fs, mu, None, inner_iters=1, cg_iters=200)
+    np.testing.assert_allclose(mu2, mu, rtol=1e-6)
+    # inactive: codes large, so the least-squares filters are short
+    d3, mu3, _ = oracle.learn(b, z * 100, fs, np.ones(K), None, inner_iters=80, cg_iters=200)
+    nrm3 = np.sqrt((d3.reshape(K, -1) ** 2).sum(1))
+    assert np.all(nrm3 < 1.0) and np.all(mu3 < 1e-3)
+
+
+def test_zero_filter_keeps_multiplier():
+    N, K, grid, fs = 2, 2, (8, 8), (3, 3)
+    z = RNG.standard_normal((N, K) + grid)
+    z[:, 1] = 0.0
+    b = RNG.standard_normal((N, 1) + grid)
+    d, mu, _ = oracle.learn(b, z, fs, np.array([1.0, 2.5]), None, inner_iters=3, cg_iters=20)
+    assert mu[1] == 2.5 and np.all(d[1] == 0) and np.all(np.isfinite(d))
+
+
+# ---------------------------------------------------------- P12 alternation
+
+def test_alternation_monotone_with_tight_inner_solves():
+    grid, fs, K = (16, 16), (5, 5), 4
+    b = RNG.standard_normal((2, 1) + grid) * 3
+    d0 = rand_filters(K, 1, fs)
+    d, z, th, mu, gamma = d0, None, None, np.ones(K), None
+    objs = []
+    for _ in range(4):
+        out = oracle.code(b, d, 0.5, 1.0, 1500, z0=z, theta0=th)
+        z, th = out["z"], out["theta"]
+        objs.append(oracle.objective(b, d, z, 0.5)[1])
+        d, mu, gamma = oracle.learn(b, z, fs, mu, gamma, inner_iters=60, cg_iters=150)
+        objs.append(oracle.objective(b, d, z, 0.5)[1])
+    assert all(o2 <= o1 * (1 + 1e-7) for o1, o2 in zip(objs, objs[1:])), objs
+    assert objs[-1] < objs[0]
+
+
+def test_learn_dictionary_runs_and_logs():
+    grid, fs, K = (12, 12), (3, 3), 3
+    b = RNG.standard_normal((2, 1) + grid) * 3
+    out = oracle.learn_dictionary(b, rand_filters(K, 1, fs), 0.5, 1.0, 5, 2, 3, 5)
+    assert len(out["objectives"]) == 4
+    assert np.all(np.sqrt((out["d"].reshape(K, -1) ** 2).sum(1)) <= 1 + 1e-12)
+
+
+# --------------------------------------------------------------- P14 gradient
+
+def _fd_margin_ok(b, d, beta, rho, T, margin):
+    """Every clip argument stays at least ``margin`` away from +-beta."""
+    N, J = b.shape[:2]
+    grid = b.shape[2:]
+    K = d.shape[0]
+    Dm = dict_matrix(d, grid)
+    A = Dm @ Dm.T + np.eye(Dm.shape[0]) / rho
+    for n in range(N):
+        x = b[n].reshape(-1)
+        z = np.zeros(Dm.shape[1])
+        th = np.zeros_like(z)
+        for _ in range(T):
+            lam = np.linalg.solve(A, Dm @ th + Dm @ z / rho - x / rho)
+            v = Dm.T @ lam
+            u = v - z / rho
+            if np.min(np.abs(np.abs(u) - beta)) < margin:
+                return False
+            th = np.clip(u, -beta, beta)
+            z = z + rho * (th - v)
+    return True
+
+
+def test_gradient_matches_finite_differences():
+    """Oracle reverse pass vs FP64 central differences on a small instance
+    (2 images 16x16, K = 3, 5x5 taps, 30 iterations)."""
+    rng = np.random.default_rng(7)
+    grid, fs, K, T, rho, beta = (10, 10), (3, 3), 3, 30, 10.0, 1.0
+    b = rng.standard_normal((2, 1) + grid) * 10
+    d = rand_filters(K, 1, fs, rng)
+    assert _fd_margin_ok(b, d, beta, rho, T, 1e-6)
+    L, gd, gb = oracle.code_loss_grad(b, d, beta, rho, T)
+    z = oracle.code(b, d, beta, rho, T)["z"]
+    assert abs(L - oracle.objective(b, d, z, beta)[1]) < 1e-10 * abs(L)
+    assert np.count_nonzero(z) > 0
+
+    def loss(dd, bb):
+        zz = oracle.code(b, dd, bb, rho, T)["z"]
+        return oracle.objective(b, dd, zz, bb)[1]
+
+    h = 1e-6
+    scale = max(np.abs(gd).max(), abs(gb))
+    picks = list(itertools.product(range(K), range(fs[0]), range(fs[1])))
+    for (k, m0, m1) in picks:
+        dp = d.copy(); dp[k, 0, m0, m1] += h
+        dm = d.copy(); dm[k, 0, m0, m1] -= h
+        fd = (loss(dp, beta) - loss(dm, beta)) / (2 * h)
+        assert abs(fd - gd[k, 0, m0, m1]) <= 1e-6 * scale, (k, m0, m1, fd, gd[k, 0, m0, m1])
+    fd_b = (loss(d, beta + h) - loss(d, beta - h)) / (2 * h)
+    assert abs(fd_b - gb) <= 1e-6 * scale
+
+
+def test_gradient_tensor_matches_finite_differences():
+    rng = np.random.default_rng(11)
+    grid, fs, K, J, T, rho, beta = (8, 8), (3, 3), 2, 2, 10, 3.0, 0.5
+    b = rng.standard_normal((1, J) + grid) * 4
+    d = rand_filters(K, J, fs, rng)
+    assert _fd_margin_ok(b, d, beta, rho, T, 1e-6)
+    L, gd, gb = oracle.code_loss_grad(b, d, beta, rho, T)
+
+    def loss(dd, bb):
+        zz = oracle.code(b, dd, bb, rho, T)["z"]
+        return oracle.objective(b, dd, zz, bb)[1]
+
+    h = 1e-6
+    scale = max(np.abs(gd).max(), abs(gb))
+    for idx in [(0, 0, 0, 0), (1, 1, 2, 1), (0, 1, 1, 2), (1, 0, 2, 2)]:
+        dp = d.copy(); dp[idx] += h
+        dm = d.copy(); dm[idx] -= h
+        fd = (loss(dp, beta) - loss(dm, beta)) / (2 * h)
+        assert abs(fd - gd[idx]) <= 1e-6 * scale
+    fd_b = (loss(d, beta + h) - loss(d, beta - h)) / (2 * h)
+    assert abs(fd_b - gb) <= 1e-6 * scale
