@@ -1,0 +1,175 @@
+/*
+ * dualcsc.h -- C ABI of the dual-domain convolutional sparse coding library
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * The library solves the two convex subproblems of convolutional sparse
+ * coding (CSC) in their dual form, as in Affara, Ghanem and Wonka, "Fast
+ * Convolutional Sparse Coding in the Dual Domain":
+ *
+ *   min_{d,z} 1/2 || x - sum_k d_k * z_k ||_2^2 + beta sum_k ||z_k||_1
+ *   s.t. ||d_k||_2 <= 1                                     (eq:CSC, Sec. 3.1)
+ *
+ * for N images x (each with J correlated channels, Sec. 3.3) sharing K
+ * filters d_k of fixed support M.  Convolutions are circular on a padded
+ * power-of-two grid and are diagonalised by the DFT (Sec. 3.2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every array argument is a DEVICE pointer to C-contiguous float32 unless
+ *    stated otherwise.  Shapes use the grid (H, W) or (T, H, W):
+ *        b     [N][J][grid]          images (zero-padded by the caller)
+ *        d     [K][J][fsupp]         filters; tap m sits at grid index m
+ *        z     [N][K][grid]          sparse codes
+ *        theta [N][K][grid]          ADMM split variable theta = D^T lambda
+ *  - The caller owns all memory.  The library never allocates or frees, and
+ *    never calls hipMalloc: scratch space is the caller's workspace `ws`
+ *    (device memory, 256-byte aligned, at least csc_workspace_bytes()).
+ *  - All work is enqueued on `stream` (a hipStream_t; NULL = default stream)
+ *    and is asynchronous: outputs are valid once the stream has synchronised.
+ *  - Host-side argument checks run before anything is enqueued, so an error
+ *    return leaves every output untouched.
+ *  - Calls on distinct workspaces are independent; two calls that share a
+ *    workspace must be ordered on one stream.
+ *  - Supported geometry: ndim 2 or 3; every grid side a power of two, H and W
+ *    in [8, 256], T in [2, 64]; 1 <= fsupp <= grid per axis; J in [1, 3];
+ *    K >= 1; N >= 1.
+ */
+#ifndef DUALCSC_H
+#define DUALCSC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CSC_ABI_VERSION 1
+
+/* Return codes. */
+#define CSC_OK 0
+#define CSC_EINVAL (-1)       /* bad shape or argument (see each entry point) */
+#define CSC_EWORKSPACE (-2)   /* workspace NULL, too small or not 256-B aligned */
+#define CSC_EUNSUPPORTED (-3) /* geometry outside the supported set */
+#define CSC_EHIP (-4)         /* a HIP runtime call failed */
+
+/* Workspace query operations. */
+#define CSC_OP_CODE 1
+#define CSC_OP_LEARN 2
+#define CSC_OP_OBJECTIVE 3
+
+/* Flags. */
+#define CSC_ADAPTIVE_RHO 0x1u /* csc_code: residual-balancing step size */
+#define CSC_Z_ZERO 0x2u       /* csc_code: start from z = 0 (z is output only) */
+#define CSC_THETA_ZERO 0x4u   /* csc_code: start from theta = 0 (theta output only) */
+#define CSC_GAMMA_ZERO 0x8u   /* csc_learn: start from gamma = 0 (gamma output only) */
+
+typedef struct csc_shape {
+  int32_t abi_version; /* must equal CSC_ABI_VERSION */
+  int32_t n;           /* images N */
+  int32_t j;           /* correlated channels J (1 = grayscale CSC) */
+  int32_t k;           /* filters K */
+  int32_t ndim;        /* 2: grid = (H, W); 3: grid = (T, H, W) */
+  int32_t grid[3];     /* padded FFT grid, first ndim entries used */
+  int32_t fsupp[3];    /* filter support, first ndim entries used */
+} csc_shape;
+
+/* Bytes of workspace needed by `op` (CSC_OP_*) for `shape` and `flags`;
+ * 0 if the shape is invalid. */
+size_t csc_workspace_bytes(const csc_shape* shape, int op, unsigned flags);
+
+/*
+ * Coding subproblem (eq:Inference) solved by ADMM on its dual
+ * (eq:Inference_Dual, eq:Inference_ADMM) with the updates of
+ * eq:Inference_solution, in the Fourier domain, for exactly `iters`
+ * iterations per image (images are independent, Sec. 3.1):
+ *
+ *   lambda <- (D D^T + I/rho)^-1 (D theta + D z/rho - x/rho)
+ *   theta  <- Pi_C(D^T lambda - z/rho),  C = { ||theta||_inf <= beta }
+ *   z      <- z + rho (theta - D^T lambda)
+ *
+ * For J > 1 (Sec. 3.3) the lambda system is block diagonal with one J x J
+ * Hermitian block per frequency and is solved exactly per frequency.
+ *
+ *   b      [N][J][grid]  images.
+ *   d      [K][J][fsupp] filters.
+ *   beta   sparsity weight (>= 0).
+ *   rho    [N] ADMM step per image (> 0); read at entry, and with
+ *          CSC_ADAPTIVE_RHO overwritten with the step for the next iteration
+ *          (residual balancing of Boyd et al. 2011 Sec. 3.4.1: double when
+ *          r_pri > 10 r_dual, halve when r_dual > 10 r_pri).
+ *   iters  number of ADMM iterations (>= 0).
+ *   z      [N][K][grid] in/out: warm start (ignored with CSC_Z_ZERO), result.
+ *   theta  [N][K][grid] in/out, or NULL (start from 0, not returned).  With
+ *          CSC_THETA_ZERO the input contents are ignored.
+ *   resid  NULL or [iters][N][3] float64: r_pri = ||theta' - D^T lambda'||,
+ *          r_dual = rho ||D (theta' - theta)||, and the rho used.
+ *   Errors: CSC_EINVAL for a bad shape, beta < 0, iters < 0, NULL b/d/rho/z;
+ *           CSC_EWORKSPACE; CSC_EHIP.
+ */
+int csc_code(const csc_shape* shape, const float* b, const float* d, float beta,
+             float* rho, int iters, unsigned flags, float* z, float* theta,
+             double* resid, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Learning subproblem (eq:Learning) in the dual: for fixed multipliers mu,
+ *   gamma = -(I + sum_k 1/(2 mu_k) Z_k S^T S Z_k^T)^-1 x      (eq:Learning_gamma)
+ * by `cg_iters` conjugate-gradient iterations warm-started from gamma, then
+ *   d_k = -1/(2 mu_k) S Z_k^T gamma                      (eq:Learning_Solution)
+ *   mu_k <- mu_k ||d_k||_2                                   (eq:mu_update)
+ * repeated `inner_iters` times; finally d_k <- d_k / max(1, ||d_k||).  The
+ * images are coupled through the shared filters; for J > 1 each channel has
+ * its own gamma_j with one shared operator, and mu_k and ||d_k|| span all
+ * channels (Sec. 3.3).  A filter whose norm is exactly 0 keeps its mu.
+ *
+ *   b      [N][J][grid] images.   z [N][K][grid] codes.
+ *   d      [K][J][fsupp] output filters.
+ *   mu     [K] in/out multipliers (> 0 on entry).
+ *   gamma  [N][J][grid] in/out dual variable (warm start unless
+ *          CSC_GAMMA_ZERO).
+ *   Errors: CSC_EINVAL for a bad shape, inner_iters < 1, cg_iters < 0, NULL
+ *           pointers; CSC_EWORKSPACE; CSC_EHIP.
+ */
+int csc_learn(const csc_shape* shape, const float* b, const float* z, float* d,
+              float* mu, float* gamma, int inner_iters, int cg_iters,
+              unsigned flags, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Objective of eq:CSC for given (d, z), summed over channels:
+ *   out[n] = 1/2 sum_j ||x_j^n - sum_k d_jk * z_k^n||^2 + beta ||z^n||_1,
+ *   out[N] = sum_n out[n]  (fixed summation order).
+ *   out: device float64 [N + 1].
+ *   Errors: CSC_EINVAL, CSC_EWORKSPACE, CSC_EHIP.
+ */
+int csc_objective(const csc_shape* shape, const float* b, const float* d,
+                  const float* z, float beta, double* out, void* ws,
+                  size_t ws_bytes, void* stream);
+
+/*
+ * Launch tracing (for benchmarks and profiling).  csc_trace_enable(1) clears
+ * the record and starts bracketing the launches of the traced kernel classes
+ * with HIP events on the stream they are launched on (at most 8192 records;
+ * later launches are not recorded); csc_trace_enable(0) stops recording.
+ * csc_trace_read waits for the recorded events and returns the summed
+ * duration in milliseconds and the number of records of class `cls`:
+ *   0 = coding map kernel (back-projection, inverse FFT, soft threshold,
+ *       forward FFT: one launch per ADMM iteration on single-tile grids),
+ *   1 = coding per-frequency kernels (spectral reduce and dual solve),
+ *   2 = learning operator, first half (pass A over the code spectra and the
+ *       filter-support projection; one record per operator application).
+ * Errors: CSC_EINVAL (bad class or NULL outputs), CSC_EHIP.
+ */
+int csc_trace_enable(int on);
+int csc_trace_read(int cls, double* total_ms, int* count);
+
+/* Static description of a return code. */
+const char* csc_strerror(int code);
+
+/* CSC_ABI_VERSION of the loaded library. */
+int csc_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DUALCSC_H */

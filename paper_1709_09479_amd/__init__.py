@@ -1,0 +1,278 @@
+"""Python binding of libdualcsc (dual-domain convolutional sparse coding on
+MI355X).  Argument marshalling only: every step runs in the HIP library;
+torch tensors provide device memory and the stream.
+
+    import paper_1709_09479_amd as dc
+    z, theta, resid = dc.code(b, d, beta=1.0, rho=10.0, iters=20)
+    d, mu, gamma = dc.learn(b, z, fsupp=(11, 11), mu=mu, gamma=gamma)
+    per_image, total = dc.objective(b, d, z, beta=1.0)
+
+Shapes follow the C header ``include/dualcsc.h``: images b [N][J][*grid],
+filters d [K][J][*fsupp], codes z [N][K][*grid], all float32 on the GPU.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+__all__ = [
+    "DualCSCError", "load", "lib_path", "Shape", "code", "learn", "objective",
+    "learn_dictionary", "workspace_bytes", "trace_enable", "trace_read", "ADAPTIVE_RHO", "Z_ZERO", "THETA_ZERO",
+    "GAMMA_ZERO",
+]
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_LIB_NAME = "libdualcsc.so"
+
+ABI_VERSION = 1
+OK, EINVAL, EWORKSPACE, EUNSUPPORTED, EHIP = 0, -1, -2, -3, -4
+OP_CODE, OP_LEARN, OP_OBJECTIVE = 1, 2, 3
+ADAPTIVE_RHO, Z_ZERO, THETA_ZERO, GAMMA_ZERO = 0x1, 0x2, 0x4, 0x8
+
+
+class DualCSCError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (code %d)" % (msg, code))
+        self.code = code
+
+
+class Shape(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_int32),
+        ("n", ctypes.c_int32),
+        ("j", ctypes.c_int32),
+        ("k", ctypes.c_int32),
+        ("ndim", ctypes.c_int32),
+        ("grid", ctypes.c_int32 * 3),
+        ("fsupp", ctypes.c_int32 * 3),
+    ]
+
+    @classmethod
+    def make(cls, n: int, j: int, k: int, grid: Sequence[int], fsupp: Sequence[int]) -> "Shape":
+        s = cls()
+        s.abi_version = ABI_VERSION
+        s.n, s.j, s.k = int(n), int(j), int(k)
+        s.ndim = len(grid)
+        for a in range(3):
+            s.grid[a] = int(grid[a]) if a < len(grid) else 0
+            s.fsupp[a] = int(fsupp[a]) if a < len(fsupp) else 0
+        return s
+
+
+_lib = None
+
+
+def lib_path() -> str:
+    return os.path.join(_PKG, _LIB_NAME)
+
+
+def load() -> ctypes.CDLL:
+    """Load the in-tree HIP library; raises if it is missing (there is no
+    fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = lib_path()
+    if not os.path.exists(path):
+        raise DualCSCError(EHIP, "libdualcsc.so not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    vp, i32, u32, f32, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint, ctypes.c_float, ctypes.c_size_t
+    sp = ctypes.POINTER(Shape)
+    lib.csc_abi_version.restype = i32
+    lib.csc_strerror.restype = ctypes.c_char_p
+    lib.csc_strerror.argtypes = [i32]
+    lib.csc_workspace_bytes.restype = sz
+    lib.csc_workspace_bytes.argtypes = [sp, i32, u32]
+    lib.csc_code.restype = i32
+    lib.csc_code.argtypes = [sp, vp, vp, f32, vp, i32, u32, vp, vp, vp, vp, sz, vp]
+    lib.csc_learn.restype = i32
+    lib.csc_learn.argtypes = [sp, vp, vp, vp, vp, vp, i32, i32, u32, vp, sz, vp]
+    lib.csc_objective.restype = i32
+    lib.csc_objective.argtypes = [sp, vp, vp, vp, f32, vp, vp, sz, vp]
+    lib.csc_trace_enable.restype = i32
+    lib.csc_trace_enable.argtypes = [i32]
+    lib.csc_trace_read.restype = i32
+    lib.csc_trace_read.argtypes = [i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
+    if lib.csc_abi_version() != ABI_VERSION:
+        raise DualCSCError(EINVAL, "ABI version mismatch")
+    _lib = lib
+    return lib
+
+
+def _check(rc: int) -> None:
+    if rc != OK:
+        msg = load().csc_strerror(rc).decode()
+        raise DualCSCError(rc, msg)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream() -> int:
+    return _torch().cuda.current_stream().cuda_stream
+
+
+_WS = {}
+
+
+def _workspace(shape: Shape, op: int, flags: int, device):
+    """Caller-side workspace (torch allocation), cached per device and size."""
+    torch = _torch()
+    nbytes = load().csc_workspace_bytes(ctypes.byref(shape), op, flags)
+    if nbytes == 0:
+        _check(EINVAL)
+    key = (str(device), op)
+    buf = _WS.get(key)
+    if buf is None or buf.numel() < nbytes:
+        buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        _WS[key] = buf
+    base = buf.data_ptr()
+    off = (-base) % 256
+    return base + off, nbytes
+
+
+def workspace_bytes(n, j, k, grid, fsupp, op=OP_CODE, flags=0) -> int:
+    s = Shape.make(n, j, k, grid, fsupp)
+    return int(load().csc_workspace_bytes(ctypes.byref(s), op, flags))
+
+
+def _need(t, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+        raise DualCSCError(EINVAL, "%s must be a contiguous float32 CUDA tensor" % name)
+
+
+def _shape_of(b, d) -> Shape:
+    nd = b.dim() - 2
+    return Shape.make(b.shape[0], b.shape[1], d.shape[0], tuple(b.shape[2:]), tuple(d.shape[2:2 + nd]))
+
+
+def code(b, d, beta: float, rho, iters: int, z=None, theta=None, adaptive: bool = False,
+         want_theta: bool = False, want_resid: bool = False):
+    """ADMM coding (eq:Inference_solution) for ``iters`` iterations.
+
+    b [N][J][*grid], d [K][J][*fsupp]; rho: float or [N] tensor (updated in
+    place when adaptive).  z / theta: warm starts (modified in place) or None
+    (start from zero).  Returns (z, theta or None, resid [iters][N][3] or None,
+    rho tensor)."""
+    torch = _torch()
+    lib = load()
+    _need(b, "b")
+    _need(d, "d")
+    shape = _shape_of(b, d)
+    N, K = b.shape[0], d.shape[0]
+    dev = b.device
+    flags = ADAPTIVE_RHO if adaptive else 0
+    if z is None:
+        z = torch.empty((N, K) + tuple(b.shape[2:]), dtype=torch.float32, device=dev)
+        flags |= Z_ZERO
+    _need(z, "z")
+    if theta is None and want_theta:
+        theta = torch.empty_like(z)
+        flags |= THETA_ZERO
+    if theta is not None:
+        _need(theta, "theta")
+    if isinstance(rho, torch.Tensor):
+        rho_t = rho
+    else:
+        rho_t = torch.full((N,), float(rho), dtype=torch.float32, device=dev)
+    _need(rho_t, "rho")
+    resid = torch.empty((iters, N, 3), dtype=torch.float64, device=dev) if (want_resid and iters > 0) else None
+    ws, nbytes = _workspace(shape, OP_CODE, flags, dev)
+    rc = lib.csc_code(ctypes.byref(shape), _ptr(b), _ptr(d), float(beta), _ptr(rho_t), int(iters), flags,
+                      _ptr(z), _ptr(theta), _ptr(resid), ws, nbytes, _stream())
+    _check(rc)
+    return z, theta, resid, rho_t
+
+
+def learn(b, z, fsupp: Sequence[int], mu=None, gamma=None, inner_iters: int = 10, cg_iters: int = 10):
+    """Dual dictionary learning (eq:Learning_gamma, eq:Learning_Solution,
+    eq:mu_update).  Returns (d [K][J][*fsupp], mu [K], gamma [N][J][*grid]);
+    mu and gamma are updated in place when given."""
+    torch = _torch()
+    lib = load()
+    _need(b, "b")
+    _need(z, "z")
+    N, J, K = b.shape[0], b.shape[1], z.shape[1]
+    dev = b.device
+    fsupp = tuple(int(s) for s in fsupp)
+    shape = Shape.make(N, J, K, tuple(b.shape[2:]), fsupp)
+    flags = 0
+    if mu is None:
+        mu = torch.ones(K, dtype=torch.float32, device=dev)
+    if gamma is None:
+        gamma = torch.empty_like(b)
+        flags |= GAMMA_ZERO
+    _need(mu, "mu")
+    _need(gamma, "gamma")
+    d = torch.empty((K, J) + fsupp, dtype=torch.float32, device=dev)
+    ws, nbytes = _workspace(shape, OP_LEARN, flags, dev)
+    rc = lib.csc_learn(ctypes.byref(shape), _ptr(b), _ptr(z), _ptr(d), _ptr(mu), _ptr(gamma), int(inner_iters),
+                       int(cg_iters), flags, ws, nbytes, _stream())
+    _check(rc)
+    return d, mu, gamma
+
+
+def objective(b, d, z, beta: float):
+    """eq:CSC objective: returns a float64 tensor [N + 1] (per image, total)."""
+    torch = _torch()
+    lib = load()
+    _need(b, "b")
+    _need(d, "d")
+    _need(z, "z")
+    shape = _shape_of(b, d)
+    out = torch.empty(b.shape[0] + 1, dtype=torch.float64, device=b.device)
+    ws, nbytes = _workspace(shape, OP_OBJECTIVE, 0, b.device)
+    rc = lib.csc_objective(ctypes.byref(shape), _ptr(b), _ptr(d), _ptr(z), float(beta), _ptr(out), ws, nbytes,
+                           _stream())
+    _check(rc)
+    return out
+
+
+TRACE_CODE_MAPS, TRACE_CODE_SPEC, TRACE_LEARN_OP = 0, 1, 2
+
+
+def trace_enable(on: bool = True) -> None:
+    """Start (clearing earlier records) or stop event tracing of launches."""
+    _check(load().csc_trace_enable(1 if on else 0))
+
+
+def trace_read(cls: int) -> Tuple[float, int]:
+    """(summed milliseconds, number of records) of a traced kernel class."""
+    ms = ctypes.c_double(0.0)
+    cnt = ctypes.c_int(0)
+    _check(load().csc_trace_read(int(cls), ctypes.byref(ms), ctypes.byref(cnt)))
+    return ms.value, cnt.value
+
+
+def learn_dictionary(b, d0, beta: float, rho, t_in: int, t_out: int, inner_iters: int = 10,
+                     cg_iters: int = 10, adaptive: bool = False, log_objective: bool = True):
+    """Alg. 1: alternate coding (warm-started z, theta) and learning
+    (warm-started gamma, carried mu) for ``t_out`` outer steps.  Returns a dict
+    with d, z, theta, mu, gamma, rho and the objective after each half step
+    (float64 device tensors, read back only at the end)."""
+    torch = _torch()
+    N, K = b.shape[0], d0.shape[0]
+    d = d0.clone()
+    fsupp = tuple(d0.shape[2:])
+    z = theta = gamma = None
+    mu = torch.ones(K, dtype=torch.float32, device=b.device)
+    rho_t = rho if isinstance(rho, torch.Tensor) else torch.full((N,), float(rho), dtype=torch.float32,
+                                                                 device=b.device)
+    objs = []
+    for _ in range(t_out):
+        z, theta, _, rho_t = code(b, d, beta, rho_t, t_in, z=z, theta=theta, adaptive=adaptive, want_theta=True)
+        if log_objective:
+            objs.append(objective(b, d, z, beta)[-1:].clone())
+        d, mu, gamma = learn(b, z, fsupp, mu, gamma, inner_iters, cg_iters)
+        if log_objective:
+            objs.append(objective(b, d, z, beta)[-1:].clone())
+    return {"d": d, "z": z, "theta": theta, "mu": mu, "gamma": gamma, "rho": rho_t,
+            "objectives": torch.cat(objs) if objs else None}

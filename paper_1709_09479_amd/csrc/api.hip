@@ -1,0 +1,197 @@
+// C ABI entry points: argument validation (before anything is enqueued),
+// planning, workspace sizing and dispatch to the coding / learning paths.
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace dcsc {
+
+int run_code(const Plan& pl, const float* b, const float* d, float beta, float* rho, int iters, unsigned flags,
+             float* z, float* theta, double* resid, void* ws, hipStream_t st);
+size_t run_code_ws(const Plan& pl);
+int run_objective(const Plan& pl, const float* b, const float* d, const float* z, float beta, double* out, void* ws,
+                  hipStream_t st);
+int run_learn(const Plan& pl, const float* b, const float* z, float* d, float* mu, float* gamma, int inner_iters,
+              int cg_iters, unsigned flags, void* ws, hipStream_t st);
+size_t run_learn_ws(const Plan& pl);
+
+static bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Resident workgroups per CU for a single-tile kernel of d complex elements
+// (LDS bound: one tile of 8 bytes per element plus row padding).
+static int tile_occupancy(int64_t d) {
+  if (d >= 16384) return 1;
+  if (d >= 8192) return 2;
+  if (d >= 4096) return 4;
+  return 8;
+}
+
+int make_plan(const csc_shape* s, Plan* pl) {
+  if (!s || s->abi_version != CSC_ABI_VERSION) return CSC_EINVAL;
+  if (s->n < 1 || s->k < 1 || s->j < 1 || s->j > 3) return CSC_EINVAL;
+  if (s->ndim != 2 && s->ndim != 3) return CSC_EINVAL;
+  Plan p;
+  p.n = s->n;
+  p.j = s->j;
+  p.k = s->k;
+  p.p = (s->k + 1) / 2;
+  p.nd = s->ndim;
+  const int off = 3 - s->ndim;
+  for (int a = 0; a < s->ndim; ++a) {
+    p.g[off + a] = s->grid[a];
+    p.fs[off + a] = s->fsupp[a];
+  }
+  for (int a = 0; a < 3; ++a) {
+    if (!pow2(p.g[a])) return CSC_EINVAL;
+    if (p.fs[a] < 1 || p.fs[a] > p.g[a]) return CSC_EINVAL;
+  }
+  if (p.g[1] < 8 || p.g[1] > 256 || p.g[2] < 8 || p.g[2] > 256) return CSC_EUNSUPPORTED;
+  if (s->ndim == 3 && (p.g[0] < 2 || p.g[0] > 64)) return CSC_EUNSUPPORTED;
+  p.dsz = int64_t(p.g[0]) * p.g[1] * p.g[2];
+  p.msz = int64_t(p.fs[0]) * p.fs[1] * p.fs[2];
+  p.lds = (p.g[0] == 1) && tile_supported(p.g[1], p.g[2]);
+  if (p.lds) {
+    const int64_t slots = 256LL * tile_occupancy(p.dsz);
+    int64_t ppg = (int64_t(p.n) * p.p + slots / 2) / slots;
+    if (ppg < 1) ppg = 1;
+    if (ppg > p.p) ppg = p.p;
+    p.ppg = (int)ppg;
+    p.ng = (p.p + p.ppg - 1) / p.ppg;
+  }
+  *pl = p;
+  return CSC_OK;
+}
+
+static int check_ws(void* ws, size_t have, size_t need) {
+  if (need == 0) return CSC_OK;
+  if (!ws || have < need || (reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return CSC_EWORKSPACE;
+  return CSC_OK;
+}
+
+// ------------------------------------------------------------- tracing
+
+namespace {
+constexpr int kTraceSlots = 8192;
+std::mutex g_trace_mu;
+bool g_trace_on = false;
+std::vector<hipEvent_t> g_ev_start, g_ev_stop;
+std::vector<int> g_ev_cls;
+int g_ev_used = 0;
+}  // namespace
+
+TraceScope::TraceScope(int cls, hipStream_t st) : cls_(cls), st_(st), slot_(-1) {
+  std::lock_guard<std::mutex> lk(g_trace_mu);
+  if (!g_trace_on || g_ev_used >= kTraceSlots) return;
+  slot_ = g_ev_used++;
+  g_ev_cls[slot_] = cls;
+  hipEventRecord(g_ev_start[slot_], st_);
+}
+
+TraceScope::~TraceScope() {
+  if (slot_ >= 0) hipEventRecord(g_ev_stop[slot_], st_);
+}
+
+}  // namespace dcsc
+
+using namespace dcsc;
+
+extern "C" {
+
+int csc_abi_version(void) { return CSC_ABI_VERSION; }
+
+int csc_trace_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_trace_mu);
+  if (on && g_ev_start.empty()) {
+    g_ev_start.resize(kTraceSlots);
+    g_ev_stop.resize(kTraceSlots);
+    g_ev_cls.resize(kTraceSlots);
+    for (int i = 0; i < kTraceSlots; ++i) {
+      if (hipEventCreate(&g_ev_start[i]) != hipSuccess || hipEventCreate(&g_ev_stop[i]) != hipSuccess) {
+        g_ev_start.clear();
+        g_ev_stop.clear();
+        return CSC_EHIP;
+      }
+    }
+  }
+  g_trace_on = on != 0;
+  if (on) g_ev_used = 0;
+  return CSC_OK;
+}
+
+int csc_trace_read(int cls, double* total_ms, int* count) {
+  if (!total_ms || !count || cls < 0 || cls >= kTraceClasses) return CSC_EINVAL;
+  std::lock_guard<std::mutex> lk(g_trace_mu);
+  double tot = 0.0;
+  int cnt = 0;
+  for (int i = 0; i < g_ev_used; ++i) {
+    if (g_ev_cls[i] != cls) continue;
+    if (hipEventSynchronize(g_ev_stop[i]) != hipSuccess) return CSC_EHIP;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, g_ev_start[i], g_ev_stop[i]) != hipSuccess) return CSC_EHIP;
+    tot += ms;
+    ++cnt;
+  }
+  *total_ms = tot;
+  *count = cnt;
+  return CSC_OK;
+}
+
+const char* csc_strerror(int code) {
+  switch (code) {
+    case CSC_OK: return "success";
+    case CSC_EINVAL: return "invalid argument or shape";
+    case CSC_EWORKSPACE: return "workspace missing, too small or not 256-byte aligned";
+    case CSC_EUNSUPPORTED: return "geometry not supported";
+    case CSC_EHIP: return "HIP runtime error";
+    default: return "unknown error";
+  }
+}
+
+size_t csc_workspace_bytes(const csc_shape* shape, int op, unsigned flags) {
+  (void)flags;
+  Plan pl;
+  if (make_plan(shape, &pl) != CSC_OK) return 0;
+  switch (op) {
+    case CSC_OP_CODE:
+    case CSC_OP_OBJECTIVE: return run_code_ws(pl);
+    case CSC_OP_LEARN: return run_learn_ws(pl);
+    default: return 0;
+  }
+}
+
+int csc_code(const csc_shape* shape, const float* b, const float* d, float beta, float* rho, int iters,
+             unsigned flags, float* z, float* theta, double* resid, void* ws, size_t ws_bytes, void* stream) {
+  Plan pl;
+  int rc = make_plan(shape, &pl);
+  if (rc != CSC_OK) return rc;
+  if (!b || !d || !rho || !z || iters < 0 || !(beta >= 0.0f)) return CSC_EINVAL;
+  if (flags & ~(CSC_ADAPTIVE_RHO | CSC_Z_ZERO | CSC_THETA_ZERO)) return CSC_EINVAL;
+  if ((rc = check_ws(ws, ws_bytes, run_code_ws(pl))) != CSC_OK) return rc;
+  return run_code(pl, b, d, beta, rho, iters, flags, z, theta, resid, ws, static_cast<hipStream_t>(stream));
+}
+
+int csc_learn(const csc_shape* shape, const float* b, const float* z, float* d, float* mu, float* gamma,
+              int inner_iters, int cg_iters, unsigned flags, void* ws, size_t ws_bytes, void* stream) {
+  Plan pl;
+  int rc = make_plan(shape, &pl);
+  if (rc != CSC_OK) return rc;
+  if (!b || !z || !d || !mu || !gamma || inner_iters < 1 || cg_iters < 0) return CSC_EINVAL;
+  if (flags & ~CSC_GAMMA_ZERO) return CSC_EINVAL;
+  if ((rc = check_ws(ws, ws_bytes, run_learn_ws(pl))) != CSC_OK) return rc;
+  return run_learn(pl, b, z, d, mu, gamma, inner_iters, cg_iters, flags, ws, static_cast<hipStream_t>(stream));
+}
+
+int csc_objective(const csc_shape* shape, const float* b, const float* d, const float* z, float beta, double* out,
+                  void* ws, size_t ws_bytes, void* stream) {
+  Plan pl;
+  int rc = make_plan(shape, &pl);
+  if (rc != CSC_OK) return rc;
+  if (!b || !d || !z || !out || !(beta >= 0.0f)) return CSC_EINVAL;
+  if ((rc = check_ws(ws, ws_bytes, run_code_ws(pl))) != CSC_OK) return rc;
+  return run_objective(pl, b, d, z, beta, out, ws, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,736 @@
+// Coding subproblem: ADMM on the dual of the lasso (eq:Inference_Dual,
+// eq:Inference_ADMM) with the updates of eq:Inference_solution, evaluated in
+// the Fourier domain (Sec. 3.2), plus the objective of eq:CSC.
+//
+// Restructuring used on the GPU (identical iterates in exact arithmetic):
+// theta is never stored.  From the z update, theta' = D^T lam' + (z' - z)/rho,
+// so DFT(D theta') = G lam' + (DFT(D z') - DFT(D z))/rho.  Per image the
+// library keeps yhat = DFT(D z) and Thhat = DFT(D theta) (J channels each),
+// and one iteration is
+//   lam'   = (G + I/rho)^-1 (Thhat + (yhat - xhat)/rho)          [k_solve]
+//   z'     = soft(z - rho D^T lam', rho beta)                     [k_fused]
+//   yhat'  = DFT(D z')                                            [k_fused + k_spec]
+//   Thhat' = G lam' + (yhat' - yhat)/rho                          [k_spec]
+// The soft threshold is the Moreau form of the theta/z pair of
+// eq:Inference_solution.  Only z streams through HBM each iteration.
+//
+// Filter pairs.  Filters (2p, 2p+1) travel together: with
+// E_jp(f) = conj(dhat_j,2p(f)) + i conj(dhat_j,2p+1(f)), which equals the
+// unnormalised inverse DFT of S^T d_2p + i S^T d_2p+1, one complex inverse FFT
+// of sum_j lamhat_j E_jp yields D^T lam for both maps (real and imaginary
+// part), and one complex forward FFT C of (z_2p + i z_2p+1) gives their
+// contribution to yhat as (Y(f) + conj(Y(-f)))/2 with Y = C conj(E).
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace dcsc {
+
+constexpr int kEW = 256;  // threads of the elementwise kernels
+
+__device__ __forceinline__ int64_t neg_index(int64_t f, int T, int H, int W) {
+  const int64_t hw = int64_t(H) * W;
+  const int t = (int)(f / hw), h = (int)((f / W) % H), w = (int)(f % W);
+  const int tn = t ? T - t : 0, hn = h ? H - h : 0, wn = w ? W - w : 0;
+  return (int64_t(tn) * H + hn) * W + wn;
+}
+
+// ------------------------------------------------------------------ set-up
+
+// Pair grids of the filters: E[j][p] = S^T d_{2p,j} + i S^T d_{2p+1,j}.
+__global__ void k_pack_filters(const float* __restrict__ d, float2* __restrict__ E, int K, int J, int P,
+                               int T, int H, int W, int ft, int fh, int fw) {
+  const int64_t D = int64_t(T) * H * W;
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (f >= D) return;
+  const int p = blockIdx.y, j = blockIdx.z;
+  const int t = (int)(f / (int64_t(H) * W)), h = (int)((f / W) % H), w = (int)(f % W);
+  float2 v = make_float2(0.f, 0.f);
+  if (t < ft && h < fh && w < fw) {
+    const int64_t m = (int64_t(t) * fh + h) * fw + w, msz = int64_t(ft) * fh * fw;
+    v.x = d[(int64_t(2 * p) * J + j) * msz + m];
+    if (2 * p + 1 < K) v.y = d[(int64_t(2 * p + 1) * J + j) * msz + m];
+  }
+  E[(int64_t(j) * P + p) * D + f] = v;
+}
+
+// Real planes -> complex planes with zero imaginary part.
+__global__ void k_real_to_complex(const float* __restrict__ src, float2* __restrict__ dst, int64_t count) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = make_float2(src[i], 0.f);
+}
+
+// Map pairs -> complex planes; l1 partial sums of |maps| per (image, block).
+__global__ void k_pack_maps(const float* __restrict__ z, float2* __restrict__ buf, double* __restrict__ l1,
+                            int K, int P, int64_t D) {
+  __shared__ double red[kEW / 64];
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int p = blockIdx.y, n = blockIdx.z;
+  double s = 0.0;
+  if (f < D) {
+    const float a = z[(int64_t(n) * K + 2 * p) * D + f];
+    const float b = (2 * p + 1 < K) ? z[(int64_t(n) * K + 2 * p + 1) * D + f] : 0.f;
+    buf[(int64_t(n) * P + p) * D + f] = make_float2(a, b);
+    s = (double)fabsf(a) + (double)fabsf(b);
+  }
+  const double t = block_sum(s, red);
+  if (l1 && threadIdx.x == 0) l1[(int64_t(n) * P + p) * gridDim.x + blockIdx.x] = t;
+}
+
+// G_f = sum_k dhat_.k(f) dhat_.k(f)^H, J x J per frequency (Sec. 3.2, 3.3),
+// from the pair spectra: dhat_j,2p(f) = (conj(E(f)) + E(-f))/2 and
+// dhat_j,2p+1(f) = i (conj(E(f)) - E(-f))/2.  Stored [D][J][J].
+template <int J>
+__global__ void k_gram(const float2* __restrict__ E, float2* __restrict__ G, int P, int T, int H, int W) {
+  const int64_t D = int64_t(T) * H * W;
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (f >= D) return;
+  const int64_t fn = neg_index(f, T, H, W);
+  double gr[J][J], gi[J][J];
+#pragma unroll
+  for (int a = 0; a < J; ++a)
+#pragma unroll
+    for (int c = 0; c < J; ++c) gr[a][c] = gi[a][c] = 0.0;
+  for (int p = 0; p < P; ++p) {
+    double ar[J], ai[J], br[J], bi[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const float2 e = E[(int64_t(j) * P + p) * D + f];
+      const float2 m = E[(int64_t(j) * P + p) * D + fn];
+      ar[j] = 0.5 * ((double)e.x + m.x);
+      ai[j] = 0.5 * (-(double)e.y + m.y);
+      // i (conj(e) - m) / 2 = i ((e.x - m.x) + i(-e.y - m.y)) / 2
+      br[j] = 0.5 * ((double)e.y + m.y);
+      bi[j] = 0.5 * ((double)e.x - m.x);
+    }
+#pragma unroll
+    for (int a = 0; a < J; ++a)
+#pragma unroll
+      for (int c = 0; c < J; ++c) {
+        // x conj(y) for x = a-row, y = c-row
+        gr[a][c] += ar[a] * ar[c] + ai[a] * ai[c] + br[a] * br[c] + bi[a] * bi[c];
+        gi[a][c] += ai[a] * ar[c] - ar[a] * ai[c] + bi[a] * br[c] - br[a] * bi[c];
+      }
+  }
+#pragma unroll
+  for (int a = 0; a < J; ++a)
+#pragma unroll
+    for (int c = 0; c < J; ++c) G[(f * J + a) * J + c] = make_float2((float)gr[a][c], (float)gi[a][c]);
+}
+
+__global__ void k_fill_f2(float2* __restrict__ dst, int64_t count) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = make_float2(0.f, 0.f);
+}
+__global__ void k_fill_f(float* __restrict__ dst, int64_t count, float v) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = v;
+}
+
+// dst[n][j](f) = (Y(f) + conj(Y(-f)))/2 with Y = sum_g part[n][g][j].
+template <int J>
+__global__ void k_sym_reduce(const float2* __restrict__ part, float2* __restrict__ dst, int ng, int T, int H,
+                             int W) {
+  const int64_t D = int64_t(T) * H * W;
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int n = blockIdx.y;
+  if (f >= D) return;
+  const int64_t fn = neg_index(f, T, H, W);
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    float2 y = make_float2(0.f, 0.f), ym = make_float2(0.f, 0.f);
+    for (int g = 0; g < ng; ++g) {
+      const float2* pp = part + ((int64_t(n) * ng + g) * J + j) * D;
+      y = cadd(y, pp[f]);
+      ym = cadd(ym, pp[fn]);
+    }
+    dst[(int64_t(n) * J + j) * D + f] = make_float2(0.5f * (y.x + ym.x), 0.5f * (y.y - ym.y));
+  }
+}
+
+// --------------------------------------------- per-frequency dual solve
+
+// lam = (G + I/rho)^-1 r for one frequency.  J = 1 is a division; J > 1 is a
+// Cholesky factorisation of the Hermitian positive-definite J x J block,
+// carried out in float64.
+template <int J>
+__device__ __forceinline__ void dual_solve(const float2* __restrict__ Gf, float inv_rho, const float2* r,
+                                           float2* lam) {
+  if constexpr (J == 1) {
+    const float den = Gf[0].x + inv_rho;
+    lam[0] = make_float2(r[0].x / den, r[0].y / den);
+  } else {
+    double Lr[J][J], Li[J][J];
+#pragma unroll
+    for (int a = 0; a < J; ++a)
+#pragma unroll
+      for (int c = 0; c < J; ++c) Lr[a][c] = Li[a][c] = 0.0;
+#pragma unroll
+    for (int c = 0; c < J; ++c) {
+      double s = (double)Gf[c * J + c].x + (double)inv_rho;
+#pragma unroll
+      for (int m = 0; m < c; ++m) s -= Lr[c][m] * Lr[c][m] + Li[c][m] * Li[c][m];
+      const double lcc = sqrt(s);
+      Lr[c][c] = lcc;
+#pragma unroll
+      for (int a = c + 1; a < J; ++a) {
+        // L[a][c] = (A[a][c] - sum_m L[a][m] conj(L[c][m])) / L[c][c]
+        double sr = Gf[a * J + c].x, si = Gf[a * J + c].y;
+#pragma unroll
+        for (int m = 0; m < c; ++m) {
+          sr -= Lr[a][m] * Lr[c][m] + Li[a][m] * Li[c][m];
+          si -= Li[a][m] * Lr[c][m] - Lr[a][m] * Li[c][m];
+        }
+        Lr[a][c] = sr / lcc;
+        Li[a][c] = si / lcc;
+      }
+    }
+    double yr[J], yi[J];
+#pragma unroll
+    for (int a = 0; a < J; ++a) {  // L y = r
+      double sr = r[a].x, si = r[a].y;
+#pragma unroll
+      for (int m = 0; m < a; ++m) {
+        sr -= Lr[a][m] * yr[m] - Li[a][m] * yi[m];
+        si -= Lr[a][m] * yi[m] + Li[a][m] * yr[m];
+      }
+      yr[a] = sr / Lr[a][a];
+      yi[a] = si / Lr[a][a];
+    }
+#pragma unroll
+    for (int a = J - 1; a >= 0; --a) {  // L^H x = y
+      double sr = yr[a], si = yi[a];
+#pragma unroll
+      for (int m = a + 1; m < J; ++m) {
+        // conj(L[m][a]) * x[m]
+        sr -= Lr[m][a] * yr[m] + Li[m][a] * yi[m];
+        si -= Lr[m][a] * yi[m] - Li[m][a] * yr[m];
+      }
+      yr[a] = sr / Lr[a][a];
+      yi[a] = si / Lr[a][a];
+    }
+#pragma unroll
+    for (int a = 0; a < J; ++a) lam[a] = make_float2((float)yr[a], (float)yi[a]);
+  }
+}
+
+template <int J>
+__global__ void k_solve(const float2* __restrict__ G, const float2* __restrict__ xh, const float2* __restrict__ yh,
+                        const float2* __restrict__ Th, const float* __restrict__ rho_cur, float2* __restrict__ lam,
+                        int64_t D) {
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int n = blockIdx.y;
+  if (f >= D) return;
+  const float inv_rho = 1.0f / rho_cur[n];
+  float2 r[J], l[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int64_t o = (int64_t(n) * J + j) * D + f;
+    const float2 y = yh[o], x = xh[o], th = Th[o];
+    r[j] = make_float2(th.x + (y.x - x.x) * inv_rho, th.y + (y.y - x.y) * inv_rho);
+  }
+  dual_solve<J>(G + f * J * J, inv_rho, r, l);
+#pragma unroll
+  for (int j = 0; j < J; ++j) lam[(int64_t(n) * J + j) * D + f] = l[j];
+}
+
+// After the forward pass of iteration i: yhat' = sym(sum_g part), Thhat' =
+// G lam + (yhat' - yhat)/rho_i, partial sums of |Thhat' - Thhat|^2 (the dual
+// residual by Parseval) and, when the step size is fixed, the next lam.
+template <int J>
+__global__ __launch_bounds__(kEW) void k_spec(const float2* __restrict__ part, const float2* __restrict__ G,
+                                              const float2* __restrict__ xh, float2* __restrict__ yh,
+                                              float2* __restrict__ Th, float2* __restrict__ lam,
+                                              const float* __restrict__ rho_cur, double* __restrict__ rdual,
+                                              int ng, int T, int H, int W, int solve_next) {
+  __shared__ double red[kEW / 64];
+  const int64_t D = int64_t(T) * H * W;
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int n = blockIdx.y;
+  double ds = 0.0;
+  if (f < D) {
+    const int64_t fn = neg_index(f, T, H, W);
+    const float rho = rho_cur[n], inv_rho = 1.0f / rho;
+    const float2* Gf = G + f * J * J;
+    float2 ynew[J], l[J], thn[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      float2 y = make_float2(0.f, 0.f), ym = make_float2(0.f, 0.f);
+      for (int g = 0; g < ng; ++g) {
+        const float2* pp = part + ((int64_t(n) * ng + g) * J + j) * D;
+        y = cadd(y, pp[f]);
+        ym = cadd(ym, pp[fn]);
+      }
+      ynew[j] = make_float2(0.5f * (y.x + ym.x), 0.5f * (y.y - ym.y));
+      l[j] = lam[(int64_t(n) * J + j) * D + f];
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      float2 gl = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int c = 0; c < J; ++c) gl = cadd(gl, cmul(Gf[j * J + c], l[c]));
+      const int64_t o = (int64_t(n) * J + j) * D + f;
+      const float2 yo = yh[o], tho = Th[o];
+      thn[j] = make_float2(gl.x + (ynew[j].x - yo.x) * inv_rho, gl.y + (ynew[j].y - yo.y) * inv_rho);
+      const double dx = (double)thn[j].x - tho.x, dy = (double)thn[j].y - tho.y;
+      ds += dx * dx + dy * dy;
+      yh[o] = ynew[j];
+      Th[o] = thn[j];
+    }
+    if (solve_next) {
+      float2 r[J];
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        const float2 x = xh[(int64_t(n) * J + j) * D + f];
+        r[j] = make_float2(thn[j].x + (ynew[j].x - x.x) * inv_rho, thn[j].y + (ynew[j].y - x.y) * inv_rho);
+      }
+      dual_solve<J>(Gf, inv_rho, r, l);
+#pragma unroll
+      for (int j = 0; j < J; ++j) lam[(int64_t(n) * J + j) * D + f] = l[j];
+    }
+  }
+  const double t = block_sum(ds, red);
+  if (threadIdx.x == 0) rdual[int64_t(n) * gridDim.x + blockIdx.x] = t;
+}
+
+// Residual norms per image (Boyd et al. 2011, Sec. 3.3) and the residual
+// balancing rule (Sec. 3.4.1): r_pri = ||z' - z|| / rho, r_dual = rho
+// sqrt(sum |dThhat|^2 / D).  Partial sums are added in a fixed order.
+__global__ void k_rho(const double* __restrict__ rpri, int npri, const double* __restrict__ rdual, int ndual,
+                      float* __restrict__ rho_cur, double* __restrict__ resid, int it, int N, int64_t D,
+                      int adaptive) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  double sp = 0.0, sd = 0.0;
+  for (int i = 0; i < npri; ++i) sp += rpri[int64_t(n) * npri + i];
+  for (int i = 0; i < ndual; ++i) sd += rdual[int64_t(n) * ndual + i];
+  const float rho = rho_cur[n];
+  const double r_pri = sqrt(sp) / (double)rho;
+  const double r_dual = (double)rho * sqrt(sd / (double)D);
+  if (resid) {
+    double* o = resid + (int64_t(it) * N + n) * 3;
+    o[0] = r_pri;
+    o[1] = r_dual;
+    o[2] = (double)rho;
+  }
+  if (adaptive) {
+    float nr = rho;
+    if (r_pri > 10.0 * r_dual) nr = rho * 2.0f;
+    else if (r_dual > 10.0 * r_pri) nr = rho * 0.5f;
+    rho_cur[n] = nr;
+  }
+}
+
+// ------------------------------------------------------- fused tile kernel
+
+constexpr int fused_threads(int d) { return d >= 16384 ? 1024 : d <= 1024 ? 64 : d / 16; }
+
+enum { kModeIter = 0, kModeForward = 1 };
+
+// One workgroup per (pair group g, image n).  kModeIter: for every pair p of
+// the group, back-project lam (V = sum_j lam_j E_jp), inverse FFT in LDS,
+// soft-threshold step on the two maps (z updated in place, optional theta),
+// forward FFT, and accumulate Y_j += C conj(E_jp).  kModeForward: only the
+// forward FFT and accumulation of the given maps (plus l1 sums).
+// part [N][ng][J][D]; rpart [N][ng] (sum (z'-z)^2, or sum |z| when forward).
+template <int H, int W, int J, int MODE>
+__global__ __launch_bounds__(fused_threads(H * W)) void k_fused(
+    const float2* __restrict__ E, const float2* __restrict__ lam, float* __restrict__ z,
+    float* __restrict__ theta, const float* __restrict__ rho_cur, float beta, float2* __restrict__ part,
+    double* __restrict__ rpart, int K, int P, int ppg, int ng) {
+  constexpr int D = H * W, NT = fused_threads(D), Q = D / NT, WP = W + 1;
+  constexpr bool kRegAcc = (J == 1);
+  __shared__ float2 tile[H * WP];
+  __shared__ float2 tw[256];
+  __shared__ double red[NT / 64];
+  const int g = blockIdx.x, n = blockIdx.y, tid = threadIdx.x;
+  load_twiddles(tw);
+  float2 acc[kRegAcc ? Q : 1];
+  if constexpr (kRegAcc) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) acc[q] = make_float2(0.f, 0.f);
+  }
+  double rsum = 0.0;
+  const float rho = (MODE == kModeIter) ? rho_cur[n] : 1.0f;
+  const float thr = rho * beta, inv_rho = 1.0f / rho, invD = 1.0f / (float)D;
+  const int p0 = g * ppg, p1 = min(P, p0 + ppg);
+  float2* mypart = part + (int64_t(n) * ng + g) * J * D;
+  for (int p = p0; p < p1; ++p) {
+    const int ka = 2 * p, kb = 2 * p + 1;
+    const bool hb = kb < K;
+    float* za = z + (int64_t(n) * K + ka) * D;
+    float* zb = z + (int64_t(n) * K + (hb ? kb : ka)) * D;
+    if constexpr (MODE == kModeIter) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int f = tid + q * NT;
+        float2 v = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+          v = cadd(v, cmul(lam[(int64_t(n) * J + j) * D + f], E[(int64_t(j) * P + p) * D + f]));
+        tile[(f / W) * WP + (f % W)] = v;
+      }
+      __syncthreads();
+      fft2d_tile<H, W, WP, NT, 1>(tile, tw);
+      float* tha = theta ? theta + (int64_t(n) * K + ka) * D : nullptr;
+      float* thb = theta ? theta + (int64_t(n) * K + (hb ? kb : ka)) * D : nullptr;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int f = tid + q * NT;
+        const int a = (f / W) * WP + (f % W);
+        const float2 c = tile[a];
+        const float va = c.x * invD, vb = c.y * invD;
+        const float a0 = za[f], b0 = hb ? zb[f] : 0.f;
+        const float a1 = soft_thresh(fmaf(-rho, va, a0), thr);
+        const float b1 = hb ? soft_thresh(fmaf(-rho, vb, b0), thr) : 0.f;
+        const double da = (double)a1 - a0, db = (double)b1 - b0;
+        rsum += da * da + db * db;
+        za[f] = a1;
+        if (hb) zb[f] = b1;
+        if (tha) {
+          tha[f] = va + (a1 - a0) * inv_rho;
+          if (hb) thb[f] = vb + (b1 - b0) * inv_rho;
+        }
+        tile[a] = make_float2(a1, b1);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int f = tid + q * NT;
+        const float a0 = za[f], b0 = hb ? zb[f] : 0.f;
+        rsum += (double)fabsf(a0) + (double)fabsf(b0);
+        tile[(f / W) * WP + (f % W)] = make_float2(a0, b0);
+      }
+    }
+    __syncthreads();
+    fft2d_tile<H, W, WP, NT, -1>(tile, tw);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int f = tid + q * NT;
+      const float2 c = tile[(f / W) * WP + (f % W)];
+      if constexpr (kRegAcc) {
+        acc[q] = cadd(acc[q], cmulc(c, E[int64_t(p) * D + f]));
+      } else {
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+          const float2 y = cmulc(c, E[(int64_t(j) * P + p) * D + f]);
+          float2* dst = mypart + int64_t(j) * D + f;
+          *dst = (p == p0) ? y : cadd(*dst, y);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if constexpr (kRegAcc) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) mypart[tid + q * NT] = acc[q];
+  } else if (p0 >= p1) {
+    for (int q = 0; q < Q; ++q)
+      for (int j = 0; j < J; ++j) mypart[int64_t(j) * D + tid + q * NT] = make_float2(0.f, 0.f);
+  }
+  const double tot = block_sum(rsum, red);
+  if (tid == 0) rpart[int64_t(n) * ng + g] = tot;
+}
+
+// ------------------------------------------------ global path (large grids)
+
+// buf[n][p](f) = sum_j lam_j(f) E_jp(f)
+template <int J>
+__global__ void k_make_v(const float2* __restrict__ E, const float2* __restrict__ lam, float2* __restrict__ buf,
+                         int P, int64_t D) {
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int p = blockIdx.y, n = blockIdx.z;
+  if (f >= D) return;
+  float2 v = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int j = 0; j < J; ++j) v = cadd(v, cmul(lam[(int64_t(n) * J + j) * D + f], E[(int64_t(j) * P + p) * D + f]));
+  buf[(int64_t(n) * P + p) * D + f] = v;
+}
+
+// Soft-threshold step on buf (holding D * (D^T lam) for the pair); writes the
+// new pair back into buf for the forward FFT.  rpart [N][P * gridDim.x].
+__global__ __launch_bounds__(kEW) void k_spatial(float2* __restrict__ buf, float* __restrict__ z,
+                                                 float* __restrict__ theta, const float* __restrict__ rho_cur,
+                                                 float beta, double* __restrict__ rpart, int K, int P, int64_t D) {
+  __shared__ double red[kEW / 64];
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int p = blockIdx.y, n = blockIdx.z;
+  const float rho = rho_cur[n], thr = rho * beta, inv_rho = 1.0f / rho, invD = 1.0f / (float)D;
+  double s = 0.0;
+  if (f < D) {
+    const int ka = 2 * p, kb = 2 * p + 1;
+    const bool hb = kb < K;
+    float2* bp = buf + (int64_t(n) * P + p) * D + f;
+    const float2 c = *bp;
+    const float va = c.x * invD, vb = c.y * invD;
+    float* za = z + (int64_t(n) * K + ka) * D + f;
+    float* zb = z + (int64_t(n) * K + (hb ? kb : ka)) * D + f;
+    const float a0 = *za, b0 = hb ? *zb : 0.f;
+    const float a1 = soft_thresh(fmaf(-rho, va, a0), thr);
+    const float b1 = hb ? soft_thresh(fmaf(-rho, vb, b0), thr) : 0.f;
+    const double da = (double)a1 - a0, db = (double)b1 - b0;
+    s = da * da + db * db;
+    *za = a1;
+    if (hb) *zb = b1;
+    if (theta) {
+      theta[(int64_t(n) * K + ka) * D + f] = va + (a1 - a0) * inv_rho;
+      if (hb) theta[(int64_t(n) * K + kb) * D + f] = vb + (b1 - b0) * inv_rho;
+    }
+    *bp = make_float2(a1, b1);
+  }
+  const double t = block_sum(s, red);
+  if (threadIdx.x == 0) rpart[(int64_t(n) * P + p) * gridDim.x + blockIdx.x] = t;
+}
+
+// part[n][0][j](f) = sum_p buf[n][p](f) conj(E_jp(f))
+template <int J>
+__global__ void k_accum(const float2* __restrict__ buf, const float2* __restrict__ E, float2* __restrict__ part,
+                        int P, int64_t D) {
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int n = blockIdx.y;
+  if (f >= D) return;
+  float2 y[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) y[j] = make_float2(0.f, 0.f);
+  for (int p = 0; p < P; ++p) {
+    const float2 c = buf[(int64_t(n) * P + p) * D + f];
+#pragma unroll
+    for (int j = 0; j < J; ++j) y[j] = cadd(y[j], cmulc(c, E[(int64_t(j) * P + p) * D + f]));
+  }
+#pragma unroll
+  for (int j = 0; j < J; ++j) part[(int64_t(n) * J + j) * D + f] = y[j];
+}
+
+// ---------------------------------------------------------------- objective
+
+// opart[n][blk] = sum_f sum_j |xhat_j - yhat_j|^2 (yhat = sym(sum_g part)).
+template <int J>
+__global__ __launch_bounds__(kEW) void k_obj_spec(const float2* __restrict__ part, const float2* __restrict__ xh,
+                                                  double* __restrict__ opart, int ng, int T, int H, int W) {
+  __shared__ double red[kEW / 64];
+  const int64_t D = int64_t(T) * H * W;
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int n = blockIdx.y;
+  double s = 0.0;
+  if (f < D) {
+    const int64_t fn = neg_index(f, T, H, W);
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      float2 y = make_float2(0.f, 0.f), ym = make_float2(0.f, 0.f);
+      for (int g = 0; g < ng; ++g) {
+        const float2* pp = part + ((int64_t(n) * ng + g) * J + j) * D;
+        y = cadd(y, pp[f]);
+        ym = cadd(ym, pp[fn]);
+      }
+      const float2 x = xh[(int64_t(n) * J + j) * D + f];
+      const double rx = (double)x.x - 0.5 * ((double)y.x + ym.x);
+      const double ry = (double)x.y - 0.5 * ((double)y.y - ym.y);
+      s += rx * rx + ry * ry;
+    }
+  }
+  const double t = block_sum(s, red);
+  if (threadIdx.x == 0) opart[int64_t(n) * gridDim.x + blockIdx.x] = t;
+}
+
+__global__ void k_obj_final(const double* __restrict__ opart, int nopart, const double* __restrict__ l1,
+                            int nl1, double* __restrict__ out, int N, int64_t D, float beta) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double tot = 0.0;
+  for (int n = 0; n < N; ++n) {
+    double r = 0.0, a = 0.0;
+    for (int i = 0; i < nopart; ++i) r += opart[int64_t(n) * nopart + i];
+    for (int i = 0; i < nl1; ++i) a += l1[int64_t(n) * nl1 + i];
+    const double v = 0.5 * r / (double)D + (double)beta * a;
+    out[n] = v;
+    tot += v;
+  }
+  out[N] = tot;
+}
+
+// ================================================================== host side
+
+static unsigned nblk(int64_t n, int b = kEW) { return (unsigned)((n + b - 1) / b); }
+
+#define LAUNCH_J(KERNEL, J, grid, block, st, ...)                                          \
+  do {                                                                                     \
+    if ((J) == 1) hipLaunchKernelGGL(KERNEL<1>, grid, block, 0, st, __VA_ARGS__);          \
+    else if ((J) == 2) hipLaunchKernelGGL(KERNEL<2>, grid, block, 0, st, __VA_ARGS__);     \
+    else hipLaunchKernelGGL(KERNEL<3>, grid, block, 0, st, __VA_ARGS__);                   \
+  } while (0)
+
+template <int J, int MODE>
+static bool fused_launch(const Plan& pl, const float2* E, const float2* lam, float* z, float* theta,
+                         const float* rho, float beta, float2* part, double* rpart, hipStream_t st) {
+  const dim3 grid(pl.ng, pl.n);
+  const int h = pl.g[1], w = pl.g[2];
+#define FL(HH, WW)                                                                                         \
+  if (h == HH && w == WW) {                                                                                \
+    hipLaunchKernelGGL((k_fused<HH, WW, J, MODE>), grid, dim3(fused_threads(HH * WW)), 0, st, E, lam, z, \
+                       theta, rho, beta, part, rpart, pl.k, pl.p, pl.ppg, pl.ng);                        \
+    return true;                                                                                           \
+  }
+  FL(16, 16) FL(16, 32) FL(16, 64) FL(16, 128) FL(16, 256)
+  FL(32, 16) FL(32, 32) FL(32, 64) FL(32, 128) FL(32, 256)
+  FL(64, 16) FL(64, 32) FL(64, 64) FL(64, 128) FL(64, 256)
+  FL(128, 16) FL(128, 32) FL(128, 64) FL(128, 128)
+  FL(256, 16) FL(256, 32) FL(256, 64)
+#undef FL
+  return false;
+}
+
+template <int MODE>
+static bool fused_dispatch(const Plan& pl, const float2* E, const float2* lam, float* z, float* theta,
+                           const float* rho, float beta, float2* part, double* rpart, hipStream_t st) {
+  if (pl.j == 1) return fused_launch<1, MODE>(pl, E, lam, z, theta, rho, beta, part, rpart, st);
+  if (pl.j == 2) return fused_launch<2, MODE>(pl, E, lam, z, theta, rho, beta, part, rpart, st);
+  return fused_launch<3, MODE>(pl, E, lam, z, theta, rho, beta, part, rpart, st);
+}
+
+// Workspace for the coding / objective paths.
+struct CodeWs {
+  float2 *E, *G, *xh, *yh, *Th, *lam, *part, *buf;
+  double *rpri, *rdual, *opart;
+  float* rho;
+  int npri, ndual, ngp;  // partial counts per image; pair groups written to part
+};
+
+static size_t carve_code(const Plan& pl, void* base, CodeWs* w) {
+  Carver c(base);
+  const int64_t D = pl.dsz, N = pl.n, J = pl.j, P = pl.p;
+  w->ngp = pl.lds ? pl.ng : 1;
+  w->npri = pl.lds ? pl.ng : int(P * nblk(D));
+  w->ndual = (int)nblk(D);
+  w->E = c.take<float2>(J * P * D);
+  w->G = c.take<float2>(D * J * J);
+  w->xh = c.take<float2>(N * J * D);
+  w->yh = c.take<float2>(N * J * D);
+  w->Th = c.take<float2>(N * J * D);
+  w->lam = c.take<float2>(N * J * D);
+  w->part = c.take<float2>(N * w->ngp * J * D);
+  w->buf = pl.lds ? nullptr : c.take<float2>(N * P * D);
+  w->rpri = c.take<double>(N * w->npri);
+  w->rdual = c.take<double>(N * w->ndual);
+  w->opart = c.take<double>(N * w->ndual);
+  w->rho = c.take<float>(N);
+  return c.off;
+}
+
+static size_t code_ws_bytes(const Plan& pl) {
+  CodeWs w;
+  return carve_code(pl, nullptr, &w);
+}
+
+// Filter pair spectra E and the Gram blocks G; image spectra xhat.
+static hipError_t setup_spectra(const Plan& pl, const float* b, const float* d, CodeWs& w, hipStream_t st) {
+  const int64_t D = pl.dsz;
+  const int T = pl.g[0], H = pl.g[1], W = pl.g[2];
+  hipLaunchKernelGGL(k_pack_filters, dim3(nblk(D), pl.p, pl.j), dim3(kEW), 0, st, d, w.E, pl.k, pl.j, pl.p, T, H,
+                     W, pl.fs[0], pl.fs[1], pl.fs[2]);
+  hipError_t e = fft_grids(w.E, int64_t(pl.j) * pl.p, pl.g, +1, st);
+  if (e != hipSuccess) return e;
+  LAUNCH_J(k_gram, pl.j, dim3(nblk(D)), dim3(kEW), st, w.E, w.G, pl.p, T, H, W);
+  const int64_t nx = int64_t(pl.n) * pl.j * D;
+  hipLaunchKernelGGL(k_real_to_complex, dim3(nblk(nx)), dim3(kEW), 0, st, b, w.xh, nx);
+  e = fft_grids(w.xh, int64_t(pl.n) * pl.j, pl.g, -1, st);
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+// part <- contributions of the given maps (forward FFT, times conj(E)); the
+// per-image l1 norms go to `l1` ([N][npri]).
+static hipError_t forward_maps(const Plan& pl, const float* maps, CodeWs& w, double* l1, hipStream_t st) {
+  const int64_t D = pl.dsz;
+  if (pl.lds) {
+    if (!fused_dispatch<kModeForward>(pl, w.E, w.lam, const_cast<float*>(maps), nullptr, w.rho, 0.f, w.part, l1,
+                                      st))
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_pack_maps, dim3(nblk(D), pl.p, pl.n), dim3(kEW), 0, st, maps, w.buf, l1, pl.k, pl.p, D);
+  hipError_t e = fft_grids(w.buf, int64_t(pl.n) * pl.p, pl.g, -1, st);
+  if (e != hipSuccess) return e;
+  LAUNCH_J(k_accum, pl.j, dim3(nblk(D), pl.n), dim3(kEW), st, w.buf, w.E, w.part, pl.p, D);
+  return hipGetLastError();
+}
+
+// One ADMM iteration's map work: back-projection, soft threshold, forward.
+static hipError_t iterate_maps(const Plan& pl, CodeWs& w, float* z, float* theta, float beta, hipStream_t st) {
+  const int64_t D = pl.dsz;
+  TraceScope trace(kTraceCodeMaps, st);
+  if (pl.lds) {
+    if (!fused_dispatch<kModeIter>(pl, w.E, w.lam, z, theta, w.rho, beta, w.part, w.rpri, st))
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
+  LAUNCH_J(k_make_v, pl.j, dim3(nblk(D), pl.p, pl.n), dim3(kEW), st, w.E, w.lam, w.buf, pl.p, D);
+  hipError_t e = fft_grids(w.buf, int64_t(pl.n) * pl.p, pl.g, +1, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_spatial, dim3(nblk(D), pl.p, pl.n), dim3(kEW), 0, st, w.buf, z, theta, w.rho, beta, w.rpri,
+                     pl.k, pl.p, D);
+  e = fft_grids(w.buf, int64_t(pl.n) * pl.p, pl.g, -1, st);
+  if (e != hipSuccess) return e;
+  LAUNCH_J(k_accum, pl.j, dim3(nblk(D), pl.n), dim3(kEW), st, w.buf, w.E, w.part, pl.p, D);
+  return hipGetLastError();
+}
+
+int run_code(const Plan& pl, const float* b, const float* d, float beta, float* rho, int iters, unsigned flags,
+             float* z, float* theta, double* resid, void* ws, hipStream_t st) {
+  CodeWs w;
+  carve_code(pl, ws, &w);
+  const int64_t D = pl.dsz, N = pl.n, J = pl.j;
+  const int T = pl.g[0], H = pl.g[1], W = pl.g[2];
+  const bool adaptive = (flags & CSC_ADAPTIVE_RHO) != 0;
+  const bool z_zero = (flags & CSC_Z_ZERO) != 0;
+  const bool th_zero = theta == nullptr || (flags & CSC_THETA_ZERO) != 0;
+  const int64_t nz = N * pl.k * D, ns = N * J * D;
+  hipError_t e;
+  if ((e = setup_spectra(pl, b, d, w, st)) != hipSuccess) return CSC_EHIP;
+  hipMemcpyAsync(w.rho, rho, sizeof(float) * N, hipMemcpyDeviceToDevice, st);
+  if (z_zero) {
+    hipLaunchKernelGGL(k_fill_f, dim3(nblk(nz)), dim3(kEW), 0, st, z, nz, 0.f);
+    hipLaunchKernelGGL(k_fill_f2, dim3(nblk(ns)), dim3(kEW), 0, st, w.yh, ns);
+  } else {
+    if ((e = forward_maps(pl, z, w, w.rpri, st)) != hipSuccess) return CSC_EHIP;
+    LAUNCH_J(k_sym_reduce, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.part, w.yh, w.ngp, T, H, W);
+  }
+  if (th_zero) {
+    hipLaunchKernelGGL(k_fill_f2, dim3(nblk(ns)), dim3(kEW), 0, st, w.Th, ns);
+    if (theta && iters == 0) hipLaunchKernelGGL(k_fill_f, dim3(nblk(nz)), dim3(kEW), 0, st, theta, nz, 0.f);
+  } else {
+    if ((e = forward_maps(pl, theta, w, w.rpri, st)) != hipSuccess) return CSC_EHIP;
+    LAUNCH_J(k_sym_reduce, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.part, w.Th, w.ngp, T, H, W);
+  }
+  if (iters > 0) LAUNCH_J(k_solve, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.G, w.xh, w.yh, w.Th, w.rho, w.lam, D);
+  const bool need_rho = adaptive || resid != nullptr;
+  for (int it = 0; it < iters; ++it) {
+    const bool last = it == iters - 1;
+    if ((e = iterate_maps(pl, w, z, last ? theta : nullptr, beta, st)) != hipSuccess) return CSC_EHIP;
+    const int solve_next = (!last && !adaptive) ? 1 : 0;
+    TraceScope trace(kTraceCodeSpec, st);
+    LAUNCH_J(k_spec, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.part, w.G, w.xh, w.yh, w.Th, w.lam, w.rho, w.rdual,
+             w.ngp, T, H, W, solve_next);
+    if (need_rho)
+      hipLaunchKernelGGL(k_rho, dim3(nblk(N, 64)), dim3(64), 0, st, w.rpri, w.npri, w.rdual, w.ndual, w.rho, resid,
+                         it, (int)N, D, adaptive ? 1 : 0);
+    if (adaptive && !last)
+      LAUNCH_J(k_solve, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.G, w.xh, w.yh, w.Th, w.rho, w.lam, D);
+  }
+  if (adaptive) hipMemcpyAsync(rho, w.rho, sizeof(float) * N, hipMemcpyDeviceToDevice, st);
+  return hipGetLastError() == hipSuccess ? CSC_OK : CSC_EHIP;
+}
+
+size_t run_code_ws(const Plan& pl) { return code_ws_bytes(pl); }
+
+int run_objective(const Plan& pl, const float* b, const float* d, const float* z, float beta, double* out, void* ws,
+                  hipStream_t st) {
+  CodeWs w;
+  carve_code(pl, ws, &w);
+  const int64_t D = pl.dsz, N = pl.n;
+  const int T = pl.g[0], H = pl.g[1], W = pl.g[2];
+  if (setup_spectra(pl, b, d, w, st) != hipSuccess) return CSC_EHIP;
+  if (forward_maps(pl, z, w, w.rpri, st) != hipSuccess) return CSC_EHIP;
+  LAUNCH_J(k_obj_spec, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.part, w.xh, w.opart, w.ngp, T, H, W);
+  hipLaunchKernelGGL(k_obj_final, dim3(1), dim3(64), 0, st, w.opart, w.ndual, w.rpri, w.npri, out, (int)N, D, beta);
+  return hipGetLastError() == hipSuccess ? CSC_OK : CSC_EHIP;
+}
+
+}  // namespace dcsc

@@ -1,0 +1,64 @@
+// Host-side plan and launch helpers shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/dualcsc.h"
+
+namespace dcsc {
+
+// Geometry of one call.  Grids are stored as (T, H, W) with T = 1 for 2-D.
+// Filters are handled in pairs p = (2p, 2p+1): two real maps travel as the
+// real and imaginary parts of one complex grid.
+struct Plan {
+  int n = 0, j = 0, k = 0, p = 0;  // images, channels, filters, filter pairs
+  int nd = 2;
+  int g[3] = {1, 1, 1};            // T, H, W
+  int fs[3] = {1, 1, 1};           // filter support, same axis order
+  int64_t dsz = 0;                 // pixels per grid
+  int64_t msz = 0;                 // taps per filter channel
+  bool lds = false;                // whole grid fits one LDS tile (fused path)
+  int ng = 1;                      // pair groups per image in the fused kernel
+  int ppg = 1;                     // pairs per group
+};
+
+// Largest grid (complex elements) that one LDS tile holds.
+constexpr int kTileMax = 16384;
+
+int make_plan(const csc_shape* s, Plan* pl);
+
+// Workspace carving: aligned sub-buffers of one caller-provided block.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+// In-place unnormalised DFT (dir = -1 forward, +1 inverse) of `count`
+// complex grids of shape g (T, H, W), contiguous one after the other.
+hipError_t fft_grids(float2* data, int64_t count, const int g[3], int dir, hipStream_t st);
+
+// Whether the fused single-tile kernels exist for this (H, W).
+bool tile_supported(int h, int w);
+
+// Launch tracing.  While enabled (csc_trace_enable), a TraceScope brackets
+// the launches made in its lifetime with a pair of HIP events recorded on
+// the launching stream; csc_trace_read sums the elapsed times per class.
+enum TraceClass { kTraceCodeMaps = 0, kTraceCodeSpec = 1, kTraceLearnOp = 2, kTraceClasses = 4 };
+struct TraceScope {
+  TraceScope(int cls, hipStream_t st);
+  ~TraceScope();
+  int cls_;
+  hipStream_t st_;
+  int slot_;
+};
+
+}  // namespace dcsc
