@@ -64,7 +64,9 @@ _lib = None
 
 
 def lib_path() -> str:
-    return os.path.join(_PKG, _LIB_NAME)
+    """The in-tree library, or the file named by DUALCSC_LIB (another build of
+    the same sources, e.g. for A/B timing)."""
+    return os.environ.get("DUALCSC_LIB") or os.path.join(_PKG, _LIB_NAME)
 
 
 def load() -> ctypes.CDLL:

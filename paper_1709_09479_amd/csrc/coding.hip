@@ -27,11 +27,37 @@ namespace dcsc {
 
 constexpr int kEW = 256;  // threads of the elementwise kernels
 
-__device__ __forceinline__ int64_t neg_index(int64_t f, int T, int H, int W) {
-  const int64_t hw = int64_t(H) * W;
-  const int t = (int)(f / hw), h = (int)((f / W) % H), w = (int)(f % W);
-  const int tn = t ? T - t : 0, hn = h ? H - h : 0, wn = w ? W - w : 0;
-  return (int64_t(tn) * H + hn) * W + wn;
+// Index of -f on the grid (T, H, W all powers of two).
+__device__ __forceinline__ int64_t neg_index(int64_t fl, int T, int H, int W) {
+  const int f = (int)fl;
+  const int lw = __builtin_ctz(W), lh = __builtin_ctz(H);
+  const int w = f & (W - 1), h = (f >> lw) & (H - 1), t = f >> (lw + lh);
+  return (((((T - t) & (T - 1)) << lh) | ((H - h) & (H - 1))) << lw) | ((W - w) & (W - 1));
+}
+
+// Y(f) and Y(-f) for Y = sum_g part[n][g][j] (groups added in a fixed order
+// by four interleaved accumulators, so that the loads overlap).
+__device__ __forceinline__ void group_sums(const float2* __restrict__ part, int64_t stride_g, int ng, int64_t f,
+                                           int64_t fn, float2& y, float2& ym) {
+  float2 a[4], m[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) a[u] = m[u] = make_float2(0.f, 0.f);
+  int g = 0;
+  for (; g + 4 <= ng; g += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const float2* pp = part + (g + u) * stride_g;
+      a[u] = cadd(a[u], pp[f]);
+      m[u] = cadd(m[u], pp[fn]);
+    }
+  }
+  for (int u = 0; g < ng; ++g, ++u) {
+    const float2* pp = part + g * stride_g;
+    a[u] = cadd(a[u], pp[f]);
+    m[u] = cadd(m[u], pp[fn]);
+  }
+  y = cadd(cadd(a[0], a[1]), cadd(a[2], a[3]));
+  ym = cadd(cadd(m[0], m[1]), cadd(m[2], m[3]));
 }
 
 // ------------------------------------------------------------------ set-up
@@ -137,12 +163,8 @@ __global__ void k_sym_reduce(const float2* __restrict__ part, float2* __restrict
   const int64_t fn = neg_index(f, T, H, W);
 #pragma unroll
   for (int j = 0; j < J; ++j) {
-    float2 y = make_float2(0.f, 0.f), ym = make_float2(0.f, 0.f);
-    for (int g = 0; g < ng; ++g) {
-      const float2* pp = part + ((int64_t(n) * ng + g) * J + j) * D;
-      y = cadd(y, pp[f]);
-      ym = cadd(ym, pp[fn]);
-    }
+    float2 y, ym;
+    group_sums(part + (int64_t(n) * ng * J + j) * D, int64_t(J) * D, ng, f, fn, y, ym);
     dst[(int64_t(n) * J + j) * D + f] = make_float2(0.5f * (y.x + ym.x), 0.5f * (y.y - ym.y));
   }
 }
@@ -254,12 +276,8 @@ __global__ __launch_bounds__(kEW) void k_spec(const float2* __restrict__ part, c
     float2 ynew[J], l[J], thn[J];
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-      float2 y = make_float2(0.f, 0.f), ym = make_float2(0.f, 0.f);
-      for (int g = 0; g < ng; ++g) {
-        const float2* pp = part + ((int64_t(n) * ng + g) * J + j) * D;
-        y = cadd(y, pp[f]);
-        ym = cadd(ym, pp[fn]);
-      }
+      float2 y, ym;
+      group_sums(part + (int64_t(n) * ng * J + j) * D, int64_t(J) * D, ng, f, fn, y, ym);
       ynew[j] = make_float2(0.5f * (y.x + ym.x), 0.5f * (y.y - ym.y));
       l[j] = lam[(int64_t(n) * J + j) * D + f];
     }
@@ -295,14 +313,19 @@ __global__ __launch_bounds__(kEW) void k_spec(const float2* __restrict__ part, c
 // Residual norms per image (Boyd et al. 2011, Sec. 3.3) and the residual
 // balancing rule (Sec. 3.4.1): r_pri = ||z' - z|| / rho, r_dual = rho
 // sqrt(sum |dThhat|^2 / D).  Partial sums are added in a fixed order.
-__global__ void k_rho(const double* __restrict__ rpri, int npri, const double* __restrict__ rdual, int ndual,
-                      float* __restrict__ rho_cur, double* __restrict__ resid, int it, int N, int64_t D,
-                      int adaptive) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
+__global__ __launch_bounds__(64) void k_rho(const double* __restrict__ rpri, int npri,
+                                            const double* __restrict__ rdual, int ndual, float* __restrict__ rho_cur,
+                                            double* __restrict__ resid, int it, int N, int64_t D, int adaptive) {
+  const int n = blockIdx.x, lane = threadIdx.x;
   double sp = 0.0, sd = 0.0;
-  for (int i = 0; i < npri; ++i) sp += rpri[int64_t(n) * npri + i];
-  for (int i = 0; i < ndual; ++i) sd += rdual[int64_t(n) * ndual + i];
+  for (int i = lane; i < npri; i += 64) sp += rpri[int64_t(n) * npri + i];
+  for (int i = lane; i < ndual; i += 64) sd += rdual[int64_t(n) * ndual + i];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    sp += __shfl_down(sp, off, 64);
+    sd += __shfl_down(sd, off, 64);
+  }
+  if (lane != 0) return;
   const float rho = rho_cur[n];
   const double r_pri = sqrt(sp) / (double)rho;
   const double r_dual = (double)rho * sqrt(sd / (double)D);
@@ -322,113 +345,190 @@ __global__ void k_rho(const double* __restrict__ rpri, int npri, const double* _
 
 // ------------------------------------------------------- fused tile kernel
 
-constexpr int fused_threads(int d) { return d >= 16384 ? 1024 : d <= 1024 ? 64 : d / 16; }
+// Threads per workgroup of the fused kernel: 32 elements per thread (512
+// threads for the largest tiles).  J = 1 keeps its accumulator in
+// registers; J > 1 accumulates into its partial slice in global memory.
+#ifndef FUSED_GACC
+#define FUSED_GACC 0
+#endif
+#ifndef FUSED_NT16K
+#define FUSED_NT16K 1024
+#endif
+constexpr int fused_threads(int t, int j) {
+  return j == 1 ? (t >= 16384 ? FUSED_NT16K : (t / 32 < 64 ? 64 : t / 32))
+                : (t >= 16384 ? 1024 : (t / 16 < 64 ? 64 : t / 16));
+}
 
 enum { kModeIter = 0, kModeForward = 1 };
 
 // One workgroup per (pair group g, image n).  kModeIter: for every pair p of
-// the group, back-project lam (V = sum_j lam_j E_jp), inverse FFT in LDS,
-// soft-threshold step on the two maps (z updated in place, optional theta),
-// forward FFT, and accumulate Y_j += C conj(E_jp).  kModeForward: only the
-// forward FFT and accumulation of the given maps (plus l1 sums).
+// the group, back-project lam (V = sum_j lam_j E_jp), inverse 2-D FFT, soft
+// threshold step on the two maps (z updated in place, optional theta),
+// forward 2-D FFT, and accumulate Y_j += C conj(E_jp).  kModeForward: only
+// the forward FFT and accumulation of the given maps (plus l1 sums).
+// The first pass of the inverse transform takes V straight from global
+// memory, its last pass leaves D^T lam in registers for the soft threshold,
+// whose result feeds the first forward pass from registers; the last forward
+// pass leaves the spectrum in registers for the accumulation.
 // part [N][ng][J][D]; rpart [N][ng] (sum (z'-z)^2, or sum |z| when forward).
 template <int H, int W, int J, int MODE>
-__global__ __launch_bounds__(fused_threads(H * W)) void k_fused(
+__global__ __launch_bounds__(fused_threads(H * W, J)) void k_fused(
     const float2* __restrict__ E, const float2* __restrict__ lam, float* __restrict__ z,
     float* __restrict__ theta, const float* __restrict__ rho_cur, float beta, float2* __restrict__ part,
     double* __restrict__ rpart, int K, int P, int ppg, int ng) {
-  constexpr int D = H * W, NT = fused_threads(D), Q = D / NT, WP = W + 1;
-  constexpr bool kRegAcc = (J == 1);
+  constexpr int D = H * W, NT = fused_threads(D, J), WP = tile_stride(W);
+  using PL = TilePlan<H, W, NT, WP>;
+  using P1 = typename PL::InvRow0;
+  using P4 = typename PL::InvColL;
+  using P6 = typename PL::FwdCol0;
+  using P8 = typename PL::FwdRowL;
+  static_assert(P4::JPT == P6::JPT && P4::R == P6::R, "register hand-off mismatch");
+  static_assert(P1::JPT == P8::JPT && P1::R == P8::R, "register hand-off mismatch");
+  constexpr bool kRegAcc = (J == 1) && !FUSED_GACC;
   __shared__ float2 tile[H * WP];
   __shared__ float2 tw[256];
   __shared__ double red[NT / 64];
-  const int g = blockIdx.x, n = blockIdx.y, tid = threadIdx.x;
+  const int g = blockIdx.x, n = blockIdx.y;
   load_twiddles(tw);
-  float2 acc[kRegAcc ? Q : 1];
+  float2 acc[kRegAcc ? P8::JPT : 1][kRegAcc ? P8::R : 1];
   if constexpr (kRegAcc) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) acc[q] = make_float2(0.f, 0.f);
+    for (int q = 0; q < P8::JPT; ++q)
+#pragma unroll
+      for (int r = 0; r < P8::R; ++r) acc[q][r] = make_float2(0.f, 0.f);
   }
   double rsum = 0.0;
   const float rho = (MODE == kModeIter) ? rho_cur[n] : 1.0f;
   const float thr = rho * beta, inv_rho = 1.0f / rho, invD = 1.0f / (float)D;
   const int p0 = g * ppg, p1 = min(P, p0 + ppg);
   float2* mypart = part + (int64_t(n) * ng + g) * J * D;
+  const float2* lamn = lam + int64_t(n) * J * D;
   for (int p = p0; p < p1; ++p) {
+    const int tid = opaque_tid();
     const int ka = 2 * p, kb = 2 * p + 1;
     const bool hb = kb < K;
     float* za = z + (int64_t(n) * K + ka) * D;
     float* zb = z + (int64_t(n) * K + (hb ? kb : ka)) * D;
+    const float2* Ep[J];
+#pragma unroll
+    for (int c = 0; c < J; ++c) Ep[c] = E + (int64_t(c) * P + p) * D;
+    float2 v4[P4::JPT][P4::R];
     if constexpr (MODE == kModeIter) {
+      // first inverse row pass straight from global memory, one job at a time
+      __syncthreads();
 #pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        const int f = tid + q * NT;
-        float2 v = make_float2(0.f, 0.f);
+      for (int q = 0; q < P1::JPT; ++q) {
+        int b, j;
+        if (!P1::job(tid, q, b, j)) continue;
+        __builtin_amdgcn_sched_barrier(0);
+        float2 v1[1][P1::R];
 #pragma unroll
-        for (int j = 0; j < J; ++j)
-          v = cadd(v, cmul(lam[(int64_t(n) * J + j) * D + f], E[(int64_t(j) * P + p) * D + f]));
-        tile[(f / W) * WP + (f % W)] = v;
+        for (int r = 0; r < P1::R; ++r) {
+          const int f = b * W + P1::in_pos(j, r);
+          float2 v = make_float2(0.f, 0.f);
+#pragma unroll
+          for (int c = 0; c < J; ++c) v = cadd(v, cmul(lamn[c * D + f], Ep[c][f]));
+          v1[0][r] = v;
+        }
+        dft<P1::R, 1>(v1[0]);
+#pragma unroll
+        for (int r = 0; r < P1::R; ++r) tile[P1::addr(b, P1::out_pos(j, r))] = v1[0][r];
       }
       __syncthreads();
-      fft2d_tile<H, W, WP, NT, 1>(tile, tw);
+      if constexpr (PL::NA == 2) pass_lds<typename PL::InvRow1>(tile, tw);
+      if constexpr (PL::NB == 2) pass_lds<typename PL::InvCol0>(tile, tw);
+      pass_to_regs<P4>(tid, tile, tw, v4);
       float* tha = theta ? theta + (int64_t(n) * K + ka) * D : nullptr;
       float* thb = theta ? theta + (int64_t(n) * K + (hb ? kb : ka)) * D : nullptr;
 #pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        const int f = tid + q * NT;
-        const int a = (f / W) * WP + (f % W);
-        const float2 c = tile[a];
-        const float va = c.x * invD, vb = c.y * invD;
-        const float a0 = za[f], b0 = hb ? zb[f] : 0.f;
-        const float a1 = soft_thresh(fmaf(-rho, va, a0), thr);
-        const float b1 = hb ? soft_thresh(fmaf(-rho, vb, b0), thr) : 0.f;
-        const double da = (double)a1 - a0, db = (double)b1 - b0;
-        rsum += da * da + db * db;
-        za[f] = a1;
-        if (hb) zb[f] = b1;
-        if (tha) {
-          tha[f] = va + (a1 - a0) * inv_rho;
-          if (hb) thb[f] = vb + (b1 - b0) * inv_rho;
+      for (int q = 0; q < P4::JPT; ++q) {
+        int b, j;
+        if (!P4::job(tid, q, b, j)) continue;
+        __builtin_amdgcn_sched_barrier(0);
+        float rs = 0.f;
+#pragma unroll
+        for (int r = 0; r < P4::R; ++r) {
+          const int f = P4::out_pos(j, r) * W + b;
+          const float va = v4[q][r].x * invD, vb = v4[q][r].y * invD;
+          const float a0 = za[f], b0 = hb ? zb[f] : 0.f;
+          const float a1 = soft_thresh(fmaf(-rho, va, a0), thr);
+          const float b1 = hb ? soft_thresh(fmaf(-rho, vb, b0), thr) : 0.f;
+          const float da = a1 - a0, db = b1 - b0;
+          rs = fmaf(da, da, fmaf(db, db, rs));
+          za[f] = a1;
+          if (hb) zb[f] = b1;
+          if (tha) {
+            tha[f] = va + da * inv_rho;
+            if (hb) thb[f] = vb + db * inv_rho;
+          }
+          v4[q][r] = make_float2(a1, b1);
         }
-        tile[a] = make_float2(a1, b1);
+        rsum += (double)rs;
       }
     } else {
 #pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        const int f = tid + q * NT;
-        const float a0 = za[f], b0 = hb ? zb[f] : 0.f;
-        rsum += (double)fabsf(a0) + (double)fabsf(b0);
-        tile[(f / W) * WP + (f % W)] = make_float2(a0, b0);
-      }
-    }
-    __syncthreads();
-    fft2d_tile<H, W, WP, NT, -1>(tile, tw);
+      for (int q = 0; q < P6::JPT; ++q) {
+        int b, j;
+        if (!P6::job(tid, q, b, j)) continue;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int f = tid + q * NT;
-      const float2 c = tile[(f / W) * WP + (f % W)];
-      if constexpr (kRegAcc) {
-        acc[q] = cadd(acc[q], cmulc(c, E[int64_t(p) * D + f]));
-      } else {
-#pragma unroll
-        for (int j = 0; j < J; ++j) {
-          const float2 y = cmulc(c, E[(int64_t(j) * P + p) * D + f]);
-          float2* dst = mypart + int64_t(j) * D + f;
-          *dst = (p == p0) ? y : cadd(*dst, y);
+        for (int r = 0; r < P6::R; ++r) {
+          const int f = P6::in_pos(j, r) * W + b;
+          const float a0 = za[f], b0 = hb ? zb[f] : 0.f;
+          rsum += (double)fabsf(a0) + (double)fabsf(b0);
+          v4[q][r] = make_float2(a0, b0);
         }
       }
     }
-    __syncthreads();
+    pass_from_regs<P6>(tid, tile, v4);
+    if constexpr (PL::NB == 2) pass_lds<typename PL::FwdCol1>(tile, tw);
+    if constexpr (PL::NA == 2) pass_lds<typename PL::FwdRow0>(tile, tw);
+    float2 v8[P8::JPT][P8::R];
+    if constexpr (kRegAcc) {
+      pass_to_regs<P8>(tid, tile, tw, v8);
+#pragma unroll
+      for (int q = 0; q < P8::JPT; ++q) {
+        int b, j;
+        if (!P8::job(tid, q, b, j)) continue;
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int r = 0; r < P8::R; ++r)
+          acc[q][r] = cadd(acc[q][r], cmulc(v8[q][r], Ep[0][b * W + P8::out_pos(j, r)]));
+      }
+    } else {
+      pass_to_regs<P8>(tid, tile, tw, v8);
+#pragma unroll
+      for (int q = 0; q < P8::JPT; ++q) {
+        int b, j;
+        if (!P8::job(tid, q, b, j)) continue;
+#pragma unroll
+        for (int r = 0; r < P8::R; ++r) {
+          __builtin_amdgcn_sched_barrier(0);
+          const int f = b * W + P8::out_pos(j, r);
+#pragma unroll
+          for (int c = 0; c < J; ++c) {
+            const float2 y = cmulc(v8[q][r], Ep[c][f]);
+            float2* dst = mypart + c * D + f;
+            *dst = (p == p0) ? y : cadd(*dst, y);
+          }
+        }
+      }
+    }
   }
   if constexpr (kRegAcc) {
+    const int tid = opaque_tid();
 #pragma unroll
-    for (int q = 0; q < Q; ++q) mypart[tid + q * NT] = acc[q];
+    for (int q = 0; q < P8::JPT; ++q) {
+      int b, j;
+      if (!P8::job(tid, q, b, j)) continue;
+#pragma unroll
+      for (int r = 0; r < P8::R; ++r) mypart[b * W + P8::out_pos(j, r)] = acc[q][r];
+    }
   } else if (p0 >= p1) {
-    for (int q = 0; q < Q; ++q)
-      for (int j = 0; j < J; ++j) mypart[int64_t(j) * D + tid + q * NT] = make_float2(0.f, 0.f);
+    for (int f = threadIdx.x; f < D; f += NT)
+      for (int c = 0; c < J; ++c) mypart[int64_t(c) * D + f] = make_float2(0.f, 0.f);
   }
   const double tot = block_sum(rsum, red);
-  if (tid == 0) rpart[int64_t(n) * ng + g] = tot;
+  if (threadIdx.x == 0) rpart[int64_t(n) * ng + g] = tot;
 }
 
 // ------------------------------------------------ global path (large grids)
@@ -515,12 +615,8 @@ __global__ __launch_bounds__(kEW) void k_obj_spec(const float2* __restrict__ par
     const int64_t fn = neg_index(f, T, H, W);
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-      float2 y = make_float2(0.f, 0.f), ym = make_float2(0.f, 0.f);
-      for (int g = 0; g < ng; ++g) {
-        const float2* pp = part + ((int64_t(n) * ng + g) * J + j) * D;
-        y = cadd(y, pp[f]);
-        ym = cadd(ym, pp[fn]);
-      }
+      float2 y, ym;
+      group_sums(part + (int64_t(n) * ng * J + j) * D, int64_t(J) * D, ng, f, fn, y, ym);
       const float2 x = xh[(int64_t(n) * J + j) * D + f];
       const double rx = (double)x.x - 0.5 * ((double)y.x + ym.x);
       const double ry = (double)x.y - 0.5 * ((double)y.y - ym.y);
@@ -564,7 +660,7 @@ static bool fused_launch(const Plan& pl, const float2* E, const float2* lam, flo
   const int h = pl.g[1], w = pl.g[2];
 #define FL(HH, WW)                                                                                         \
   if (h == HH && w == WW) {                                                                                \
-    hipLaunchKernelGGL((k_fused<HH, WW, J, MODE>), grid, dim3(fused_threads(HH * WW)), 0, st, E, lam, z, \
+    hipLaunchKernelGGL((k_fused<HH, WW, J, MODE>), grid, dim3(fused_threads(HH * WW, J)), 0, st, E, lam, z, \
                        theta, rho, beta, part, rpart, pl.k, pl.p, pl.ppg, pl.ng);                        \
     return true;                                                                                           \
   }
@@ -709,7 +805,7 @@ int run_code(const Plan& pl, const float* b, const float* d, float beta, float* 
     LAUNCH_J(k_spec, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.part, w.G, w.xh, w.yh, w.Th, w.lam, w.rho, w.rdual,
              w.ngp, T, H, W, solve_next);
     if (need_rho)
-      hipLaunchKernelGGL(k_rho, dim3(nblk(N, 64)), dim3(64), 0, st, w.rpri, w.npri, w.rdual, w.ndual, w.rho, resid,
+      hipLaunchKernelGGL(k_rho, dim3((unsigned)N), dim3(64), 0, st, w.rpri, w.npri, w.rdual, w.ndual, w.rho, resid,
                          it, (int)N, D, adaptive ? 1 : 0);
     if (adaptive && !last)
       LAUNCH_J(k_solve, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.G, w.xh, w.yh, w.Th, w.rho, w.lam, D);

@@ -188,6 +188,149 @@ __device__ __forceinline__ void fft2d_tile(float2* tile, const float2* tw) {
   fft_lines<H, H * W, NT, DIR, WP, 1>(tile, tw);
 }
 
+// ---------------------------------------------------------------------------
+// Tile passes with explicit register hand-off.
+//
+// A 2-D tile of H x W complex values lives in LDS row-major with row stride
+// WP.  Each axis of length L is transformed by plan_n(L) Stockham passes with
+// radices plan_r(L, 0..) ("inverse order"); a forward transform uses the same
+// radices in reverse order.  With that pairing the first pass of one
+// transform reads exactly the register layout the last pass of the other
+// leaves behind, so element-wise work between two transforms (and the global
+// loads/stores feeding them) happens in registers without an LDS round trip.
+constexpr int plan_n(int L) { return L <= 16 ? 1 : 2; }
+constexpr int plan_r(int L, int i) {
+  return L <= 16 ? L : L == 32 ? (i == 0 ? 8 : 4) : L == 64 ? 8 : L == 128 ? (i == 0 ? 8 : 16) : 16;
+}
+
+// One pass of radix R over the lines of a tile.  ROWS: lines are rows
+// (address b * WP + pos); otherwise columns (address pos * WP + b).  JFAST:
+// consecutive threads take consecutive positions j of one line; otherwise
+// consecutive lines b.  NS: product of the radices already applied.
+template <int L, int T, int NT, int DIR, int R_, int NS, bool JFAST, bool ROWS, int WP>
+struct TilePass {
+  static constexpr int R = R_;
+  static constexpr int B = T / L, LR = L / R, JOBS = T / R;
+  static constexpr int JPT = (JOBS + NT - 1) / NT;
+  static constexpr bool FULL = (JOBS % NT) == 0;
+  static constexpr int TWSTEP = 256 / (NS * R);
+  __device__ static __forceinline__ bool job(int tid, int q, int& b, int& j) {
+    const int jb = tid + q * NT;
+    if (JFAST) {
+      j = jb % LR;
+      b = jb / LR;
+    } else {
+      b = jb % B;
+      j = jb / B;
+    }
+    return FULL || jb < JOBS;
+  }
+  // one pad element after every 8 along a row; WP is the (odd) padded row
+  // stride, so both lane-per-row and strided in-row accesses spread over banks
+  __device__ static __forceinline__ int addr(int b, int pos) {
+    return ROWS ? b * WP + pos + (pos >> 3) : pos * WP + b + (b >> 3);
+  }
+  __device__ static __forceinline__ int in_pos(int j, int r) { return j + r * LR; }
+  __device__ static __forceinline__ int out_pos(int j, int r) { return (j / NS) * NS * R + (j % NS) + r * NS; }
+  // read inputs from the tile, apply twiddles
+  __device__ static __forceinline__ void load(int tid, const float2* tile, const float2* tw, float2 (&v)[JPT][R]) {
+#pragma unroll
+    for (int q = 0; q < JPT; ++q) {
+      int b, j;
+      if (!job(tid, q, b, j)) continue;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = tile[addr(b, in_pos(j, r))];
+      if constexpr (NS > 1) {
+        const int k = j % NS;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          float2 w = tw[r * k * TWSTEP];
+          if (DIR > 0) w.y = -w.y;
+          v[q][r] = cmul(v[q][r], w);
+        }
+      }
+    }
+  }
+  __device__ static __forceinline__ void compute(int tid, float2 (&v)[JPT][R]) {
+#pragma unroll
+    for (int q = 0; q < JPT; ++q) {
+      int b, j;
+      if (job(tid, q, b, j)) dft<R, DIR>(v[q]);
+    }
+  }
+  __device__ static __forceinline__ void store(int tid, float2* tile, const float2 (&v)[JPT][R]) {
+#pragma unroll
+    for (int q = 0; q < JPT; ++q) {
+      int b, j;
+      if (!job(tid, q, b, j)) continue;
+#pragma unroll
+      for (int r = 0; r < R; ++r) tile[addr(b, out_pos(j, r))] = v[q][r];
+    }
+  }
+};
+
+// The thread index as a value the compiler cannot treat as loop invariant:
+// address arithmetic is then redone inside loops instead of being hoisted
+// and held in registers across them.
+__device__ __forceinline__ int opaque_tid() {
+  int t = (int)threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
+// LDS -> LDS pass (in place; ends synchronised).
+template <class P>
+__device__ __forceinline__ void pass_lds(float2* tile, const float2* tw) {
+  const int tid = opaque_tid();
+  float2 v[P::JPT][P::R];
+  P::load(tid, tile, tw, v);
+  P::compute(tid, v);
+  __syncthreads();
+  P::store(tid, tile, v);
+  __syncthreads();
+}
+
+// Register -> LDS pass (first pass of a transform, NS = 1).  Synchronises
+// before writing (earlier readers of the tile) and after.
+template <class P>
+__device__ __forceinline__ void pass_from_regs(int tid, float2* tile, float2 (&v)[P::JPT][P::R]) {
+  P::compute(tid, v);
+  __syncthreads();
+  P::store(tid, tile, v);
+  __syncthreads();
+}
+
+// LDS -> register pass (last pass of a transform): outputs stay in v.
+template <class P>
+__device__ __forceinline__ void pass_to_regs(int tid, const float2* tile, const float2* tw, float2 (&v)[P::JPT][P::R]) {
+  P::load(tid, tile, tw, v);
+  P::compute(tid, v);
+}
+
+#ifndef TILE_ROW_JFAST
+#define TILE_ROW_JFAST false
+#endif
+// Row stride of a padded W-wide tile (odd).
+constexpr int tile_stride(int W) { return W + W / 8 + 1; }
+// Pass types of the fused H x W tile transforms.
+template <int H, int W, int NT, int WP>
+struct TilePlan {
+  static constexpr int T = H * W;
+  static constexpr int NA = plan_n(W), NB = plan_n(H);
+  static constexpr int A0 = plan_r(W, 0), AL = plan_r(W, NA - 1);
+  static constexpr int B0 = plan_r(H, 0), BL = plan_r(H, NB - 1);
+  // inverse: rows (A0 from registers [, AL]), then columns ([B0,] BL to registers)
+  using InvRow0 = TilePass<W, T, NT, 1, A0, 1, true, true, WP>;
+  using InvRow1 = TilePass<W, T, NT, 1, AL, A0, TILE_ROW_JFAST, true, WP>;
+  using InvCol0 = TilePass<H, T, NT, 1, B0, 1, false, false, WP>;
+  using InvColL = TilePass<H, T, NT, 1, BL, H / BL, false, false, WP>;
+  // forward: columns (BL from registers [, B0]), then rows ([AL,] A0 to registers)
+  using FwdCol0 = TilePass<H, T, NT, -1, BL, 1, false, false, WP>;
+  using FwdCol1 = TilePass<H, T, NT, -1, B0, BL, false, false, WP>;
+  using FwdRow0 = TilePass<W, T, NT, -1, AL, 1, TILE_ROW_JFAST, true, WP>;
+  using FwdRowL = TilePass<W, T, NT, -1, A0, W / A0, true, true, WP>;
+};
+
 // Copy the twiddle table into LDS (caller synchronises before use).
 __device__ __forceinline__ void load_twiddles(float2* tw_lds) {
   for (int i = threadIdx.x; i < 256; i += blockDim.x) tw_lds[i] = c_tw256[i];

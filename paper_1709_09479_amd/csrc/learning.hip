@@ -23,10 +23,11 @@ constexpr int kLW = 256;
 
 static unsigned lblk(int64_t n, int b = kLW) { return (unsigned)((n + b - 1) / b); }
 
-__device__ __forceinline__ int64_t lneg(int64_t f, int T, int H, int W) {
-  const int64_t hw = int64_t(H) * W;
-  const int t = (int)(f / hw), h = (int)((f / W) % H), w = (int)(f % W);
-  return (int64_t(t ? T - t : 0) * H + (h ? H - h : 0)) * W + (w ? W - w : 0);
+__device__ __forceinline__ int64_t lneg(int64_t fl, int T, int H, int W) {
+  const int f = (int)fl;
+  const int lw = __builtin_ctz(W), lh = __builtin_ctz(H);
+  const int w = f & (W - 1), h = (f >> lw) & (H - 1), t = f >> (lw + lh);
+  return (((((T - t) & (T - 1)) << lh) | ((H - h) & (H - 1))) << lw) | ((W - w) & (W - 1));
 }
 
 __device__ __forceinline__ void unpack_pair(float2 c, float2 cm, float2& a, float2& b) {
