@@ -63,6 +63,7 @@ extern "C" {
 #define CSC_Z_ZERO 0x2u       /* csc_code: start from z = 0 (z is output only) */
 #define CSC_THETA_ZERO 0x4u   /* csc_code: start from theta = 0 (theta output only) */
 #define CSC_GAMMA_ZERO 0x8u   /* csc_learn: start from gamma = 0 (gamma output only) */
+#define CSC_USE_GRAPH 0x10u   /* csc_code_batched: capture once into a hipGraph, then replay */
 
 typedef struct csc_shape {
   int32_t abi_version; /* must equal CSC_ABI_VERSION */
@@ -144,6 +145,61 @@ int csc_learn(const csc_shape* shape, const float* b, const float* z, float* d,
 int csc_objective(const csc_shape* shape, const float* b, const float* d,
                   const float* z, float beta, double* out, void* ws,
                   size_t ws_bytes, void* stream);
+
+/*
+ * Batched coding: many grayscale images of uneven sizes share K filters
+ * (the coding problem separates over images, Sec. 3.1, so each image is
+ * coded exactly as by csc_code with J = 1 and a fixed rho).
+ *
+ *   batch->grid   host [n][2] padded grid (H, W) of each image (powers of two,
+ *                 as for csc_code); images are grouped by grid internally.
+ *   batch->b_off  host [n] element offset of image i's H x W block in `b`.
+ *   batch->z_off  host [n] element offset of image i's K x H x W codes in `z`.
+ *   batch->ppg    NULL, or host [classes] filter pairs per workgroup for each
+ *                 grid class (classes in increasing (H, W) order, see
+ *                 csc_batch_classes); 0 entries keep the built-in choice.
+ *   b, d, z       device buffers; d [K][1][fsupp]; z in/out (warm start
+ *                 unless CSC_Z_ZERO).
+ *   flags         CSC_Z_ZERO, CSC_USE_GRAPH.  With CSC_USE_GRAPH (and a
+ *                 non-NULL stream) the first call for a given set of
+ *                 arguments captures the whole call into a hipGraph; later
+ *                 calls with identical arguments (pointers, sizes, beta, rho,
+ *                 iters) replay it.  Buffer contents may change between
+ *                 replays; pointers may not.
+ *   Errors: CSC_EINVAL (bad table, grid, K, beta < 0, rho <= 0, iters < 0,
+ *           flags), CSC_EUNSUPPORTED, CSC_EWORKSPACE, CSC_EHIP.
+ */
+typedef struct csc_batch {
+  int32_t abi_version; /* CSC_ABI_VERSION */
+  int32_t n;           /* images */
+  int32_t k;           /* filters */
+  int32_t fsupp[2];    /* filter support (2-D) */
+  const int32_t* grid;
+  const int64_t* b_off;
+  const int64_t* z_off;
+  const int32_t* ppg;
+} csc_batch;
+
+size_t csc_batch_workspace_bytes(const csc_batch* batch);
+
+/* Grid classes of a batch in processing order: grids [classes][2] and image
+ * counts [classes] (either may be NULL; at most max_classes written).
+ * Returns the number of classes, or a negative error code. */
+int csc_batch_classes(const csc_batch* batch, int32_t* grids, int32_t* counts,
+                      int max_classes);
+
+int csc_code_batched(const csc_batch* batch, const float* b, const float* d,
+                     float beta, float rho, int iters, unsigned flags, float* z,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/* Measured choice of filter pairs per workgroup for each single-tile grid
+ * class: runs `iters` coding iterations of each class per candidate (z is
+ * overwritten) and writes the fastest into ppg_out [classes] (host).
+ * Synchronises the stream.  Errors as csc_code_batched. */
+int csc_batch_autotune(const csc_batch* batch, const float* b, const float* d,
+                       float beta, float rho, int iters, float* z, void* ws,
+                       size_t ws_bytes, void* stream, int32_t* ppg_out,
+                       int max_classes);
 
 /*
  * Launch tracing (for benchmarks and profiling).  csc_trace_enable(1) clears

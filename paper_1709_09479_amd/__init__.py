@@ -19,7 +19,7 @@ from typing import Optional, Sequence, Tuple
 __all__ = [
     "DualCSCError", "load", "lib_path", "Shape", "code", "learn", "objective",
     "learn_dictionary", "workspace_bytes", "trace_enable", "trace_read", "ADAPTIVE_RHO", "Z_ZERO", "THETA_ZERO",
-    "GAMMA_ZERO",
+    "GAMMA_ZERO", "USE_GRAPH", "PackedBatch", "code_batched", "autotune_batched",
 ]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -28,7 +28,7 @@ _LIB_NAME = "libdualcsc.so"
 ABI_VERSION = 1
 OK, EINVAL, EWORKSPACE, EUNSUPPORTED, EHIP = 0, -1, -2, -3, -4
 OP_CODE, OP_LEARN, OP_OBJECTIVE = 1, 2, 3
-ADAPTIVE_RHO, Z_ZERO, THETA_ZERO, GAMMA_ZERO = 0x1, 0x2, 0x4, 0x8
+ADAPTIVE_RHO, Z_ZERO, THETA_ZERO, GAMMA_ZERO, USE_GRAPH = 0x1, 0x2, 0x4, 0x8, 0x10
 
 
 class DualCSCError(RuntimeError):
@@ -58,6 +58,19 @@ class Shape(ctypes.Structure):
             s.grid[a] = int(grid[a]) if a < len(grid) else 0
             s.fsupp[a] = int(fsupp[a]) if a < len(fsupp) else 0
         return s
+
+
+class Batch(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_int32),
+        ("n", ctypes.c_int32),
+        ("k", ctypes.c_int32),
+        ("fsupp", ctypes.c_int32 * 2),
+        ("grid", ctypes.POINTER(ctypes.c_int32)),
+        ("b_off", ctypes.POINTER(ctypes.c_int64)),
+        ("z_off", ctypes.POINTER(ctypes.c_int64)),
+        ("ppg", ctypes.POINTER(ctypes.c_int32)),
+    ]
 
 
 _lib = None
@@ -96,6 +109,15 @@ def load() -> ctypes.CDLL:
     lib.csc_trace_enable.argtypes = [i32]
     lib.csc_trace_read.restype = i32
     lib.csc_trace_read.argtypes = [i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
+    bp = ctypes.POINTER(Batch)
+    lib.csc_batch_workspace_bytes.restype = sz
+    lib.csc_batch_workspace_bytes.argtypes = [bp]
+    lib.csc_batch_classes.restype = i32
+    lib.csc_batch_classes.argtypes = [bp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), i32]
+    lib.csc_code_batched.restype = i32
+    lib.csc_code_batched.argtypes = [bp, vp, vp, f32, f32, i32, u32, vp, vp, sz, vp]
+    lib.csc_batch_autotune.restype = i32
+    lib.csc_batch_autotune.argtypes = [bp, vp, vp, f32, f32, i32, vp, vp, sz, vp, ctypes.POINTER(ctypes.c_int32), i32]
     if lib.csc_abi_version() != ABI_VERSION:
         raise DualCSCError(EINVAL, "ABI version mismatch")
     _lib = lib
@@ -278,3 +300,172 @@ def learn_dictionary(b, d0, beta: float, rho, t_in: int, t_out: int, inner_iters
             objs.append(objective(b, d, z, beta)[-1:].clone())
     return {"d": d, "z": z, "theta": theta, "mu": mu, "gamma": gamma, "rho": rho_t,
             "objectives": torch.cat(objs) if objs else None}
+
+
+# ------------------------------------------------------------------ batched
+
+class PackedBatch:
+    """Images of uneven padded grids packed into one device buffer.
+
+    ``b`` holds image i's H_i x W_i block at ``b_off[i]``; the codes of image
+    i (K x H_i x W_i) live at ``z_off[i]`` of a buffer of ``z_numel``."""
+
+    def __init__(self, images, k: int):
+        torch = _torch()
+        self.k = int(k)
+        self.grids = [tuple(int(s) for s in im.shape[-2:]) for im in images]
+        sizes = [h * w for h, w in self.grids]
+        self.b_off, self.z_off = [], []
+        ob = oz = 0
+        for sz_ in sizes:
+            self.b_off.append(ob)
+            self.z_off.append(oz)
+            ob += sz_
+            oz += self.k * sz_
+        self.z_numel = oz
+        dev = images[0].device
+        self.b = torch.cat([im.reshape(-1) for im in images]).to(dev).contiguous()
+        n = len(images)
+        self._grid = (ctypes.c_int32 * (2 * n))(*[v for g in self.grids for v in g])
+        self._boff = (ctypes.c_int64 * n)(*self.b_off)
+        self._zoff = (ctypes.c_int64 * n)(*self.z_off)
+        self._ppg = None
+
+    def struct(self, fsupp, ppg=None) -> Batch:
+        bt = Batch()
+        bt.abi_version = ABI_VERSION
+        bt.n = len(self.grids)
+        bt.k = self.k
+        bt.fsupp[0], bt.fsupp[1] = int(fsupp[0]), int(fsupp[1])
+        bt.grid = self._grid
+        bt.b_off = self._boff
+        bt.z_off = self._zoff
+        if ppg is not None:
+            self._ppg = (ctypes.c_int32 * len(ppg))(*[int(v) for v in ppg])
+            bt.ppg = self._ppg
+        return bt
+
+    def classes(self, fsupp):
+        bt = self.struct(fsupp)
+        lib = load()
+        nc = lib.csc_batch_classes(ctypes.byref(bt), None, None, 0)
+        _check(0 if nc >= 0 else nc)
+        g = (ctypes.c_int32 * (2 * nc))()
+        c = (ctypes.c_int32 * nc)()
+        lib.csc_batch_classes(ctypes.byref(bt), g, c, nc)
+        return [((g[2 * i], g[2 * i + 1]), c[i]) for i in range(nc)]
+
+    def z_views(self, z):
+        """Per-image [K][H][W] views of a packed code buffer."""
+        return [z[o:o + self.k * h * w].view(self.k, h, w) for o, (h, w) in zip(self.z_off, self.grids)]
+
+
+def _tune_file():
+    return os.environ.get("DUALCSC_TUNE_FILE") or os.path.join(
+        os.path.expanduser("~"), ".cache", "dualcsc", "autotune.json")
+
+
+def _tune_key(grid, count, k, fsupp):
+    return "gfx950|%dx%d|n%d|k%d|f%dx%d" % (grid[0], grid[1], count, k, fsupp[0], fsupp[1])
+
+
+def load_tuning(pb: PackedBatch, fsupp):
+    """ppg table for the batch's classes from the persisted autotune file
+    (None entries -> 0 = built-in choice)."""
+    import json
+    path = _tune_file()
+    try:
+        with open(path) as fh:
+            table = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    vals = [int(table.get(_tune_key(g, c, pb.k, fsupp), 0)) for g, c in pb.classes(fsupp)]
+    return vals if any(vals) else None
+
+
+def autotune_batched(pb: PackedBatch, d, beta: float, rho: float, iters: int = 3, persist: bool = True):
+    """Measure the best filter pairs per workgroup for every single-tile grid
+    class of the batch and (optionally) store them in the autotune file."""
+    import json
+    torch = _torch()
+    lib = load()
+    fsupp = tuple(d.shape[2:4])
+    bt = pb.struct(fsupp)
+    need = lib.csc_batch_workspace_bytes(ctypes.byref(bt))
+    ws, nbytes = _workspace_raw(need, "batch", pb.b.device)
+    z = torch.empty(pb.z_numel, dtype=torch.float32, device=pb.b.device)
+    cls = pb.classes(fsupp)
+    out = (ctypes.c_int32 * len(cls))()
+    rc = lib.csc_batch_autotune(ctypes.byref(bt), _ptr(pb.b), _ptr(d), float(beta), float(rho), int(iters),
+                                _ptr(z), ws, nbytes, _stream(), out, len(cls))
+    _check(rc)
+    ppg = [int(v) for v in out]
+    if persist:
+        path = _tune_file()
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        try:
+            with open(path) as fh:
+                table = json.load(fh)
+        except (OSError, ValueError):
+            table = {}
+        for (g, c), v in zip(cls, ppg):
+            table[_tune_key(g, c, pb.k, fsupp)] = v
+        with open(path, "w") as fh:
+            json.dump(table, fh, indent=1, sort_keys=True)
+    return ppg
+
+
+def _workspace_raw(nbytes, tag, device):
+    torch = _torch()
+    if nbytes == 0:
+        _check(EINVAL)
+    key = (str(device), tag)
+    buf = _WS.get(key)
+    if buf is None or buf.numel() < nbytes + 256:
+        buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        _WS[key] = buf
+    base = buf.data_ptr()
+    return base + (-base) % 256, nbytes
+
+
+def code_batched(pb: PackedBatch, d, beta: float, rho: float, iters: int, z=None, warm: bool = False,
+                 graph: bool = True, ppg=None, stream=None):
+    """Code every image of a PackedBatch (csc_code_batched).  Returns the
+    packed codes (see PackedBatch.z_views); ``z`` is the output buffer, read
+    as a warm start only when ``warm``.  ``ppg``: per-class pairs per
+    workgroup (default: the persisted autotune table, else built-in).
+    With ``graph`` the call is captured once and replayed on later calls with
+    the same buffers; it runs on ``stream`` (a torch.cuda.Stream, default: a
+    stream owned by this module) ordered after the current stream."""
+    torch = _torch()
+    lib = load()
+    _need(d, "d")
+    fsupp = tuple(d.shape[2:4])
+    if ppg is None:
+        ppg = load_tuning(pb, fsupp)
+    bt = pb.struct(fsupp, ppg)
+    need = lib.csc_batch_workspace_bytes(ctypes.byref(bt))
+    ws, nbytes = _workspace_raw(need, "batch", pb.b.device)
+    flags = 0 if warm else Z_ZERO
+    if z is None:
+        z = torch.empty(pb.z_numel, dtype=torch.float32, device=pb.b.device)
+        flags = Z_ZERO
+    _need(z, "z")
+    cur = torch.cuda.current_stream()
+    if graph:
+        global _BATCH_STREAM
+        s = stream or _BATCH_STREAM
+        if s is None:
+            s = _BATCH_STREAM = torch.cuda.Stream()
+        s.wait_stream(cur)
+        rc = lib.csc_code_batched(ctypes.byref(bt), _ptr(pb.b), _ptr(d), float(beta), float(rho), int(iters),
+                                  flags | USE_GRAPH, _ptr(z), ws, nbytes, s.cuda_stream)
+        cur.wait_stream(s)
+    else:
+        rc = lib.csc_code_batched(ctypes.byref(bt), _ptr(pb.b), _ptr(d), float(beta), float(rho), int(iters),
+                                  flags, _ptr(z), ws, nbytes, cur.cuda_stream)
+    _check(rc)
+    return z
+
+
+_BATCH_STREAM = None

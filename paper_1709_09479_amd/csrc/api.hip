@@ -29,6 +29,23 @@ static int tile_occupancy(int64_t d) {
   return 8;
 }
 
+void set_grouping(Plan* p, int ppg_override) {
+  if (!p->lds) {
+    p->ppg = 1;
+    p->ng = 1;
+    return;
+  }
+  int64_t ppg = ppg_override;
+  if (ppg <= 0) {
+    const int64_t slots = 256LL * tile_occupancy(p->dsz);
+    ppg = (int64_t(p->n) * p->p + slots / 2) / slots;
+  }
+  if (ppg < 1) ppg = 1;
+  if (ppg > p->p) ppg = p->p;
+  p->ppg = (int)ppg;
+  p->ng = (p->p + p->ppg - 1) / p->ppg;
+}
+
 int make_plan(const csc_shape* s, Plan* pl) {
   if (!s || s->abi_version != CSC_ABI_VERSION) return CSC_EINVAL;
   if (s->n < 1 || s->k < 1 || s->j < 1 || s->j > 3) return CSC_EINVAL;
@@ -53,14 +70,7 @@ int make_plan(const csc_shape* s, Plan* pl) {
   p.dsz = int64_t(p.g[0]) * p.g[1] * p.g[2];
   p.msz = int64_t(p.fs[0]) * p.fs[1] * p.fs[2];
   p.lds = (p.g[0] == 1) && tile_supported(p.g[1], p.g[2]);
-  if (p.lds) {
-    const int64_t slots = 256LL * tile_occupancy(p.dsz);
-    int64_t ppg = (int64_t(p.n) * p.p + slots / 2) / slots;
-    if (ppg < 1) ppg = 1;
-    if (ppg > p.p) ppg = p.p;
-    p.ppg = (int)ppg;
-    p.ng = (p.p + p.ppg - 1) / p.ppg;
-  }
+  set_grouping(&p, 0);
   *pl = p;
   return CSC_OK;
 }
@@ -85,6 +95,8 @@ int g_ev_used = 0;
 TraceScope::TraceScope(int cls, hipStream_t st) : cls_(cls), st_(st), slot_(-1) {
   std::lock_guard<std::mutex> lk(g_trace_mu);
   if (!g_trace_on || g_ev_used >= kTraceSlots) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st_, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
   slot_ = g_ev_used++;
   g_ev_cls[slot_] = cls;
   hipEventRecord(g_ev_start[slot_], st_);

@@ -60,6 +60,11 @@ __device__ __forceinline__ void group_sums(const float2* __restrict__ part, int6
   ym = cadd(cadd(m[0], m[1]), cadd(m[2], m[3]));
 }
 
+// Start of image n's code maps ([K][grid]) and of its image ([J][grid]).
+__device__ __forceinline__ int64_t map_base(const int64_t* __restrict__ zoff, int n, int K, int64_t D) {
+  return zoff ? zoff[n] : int64_t(n) * K * D;
+}
+
 // ------------------------------------------------------------------ set-up
 
 // Pair grids of the filters: E[j][p] = S^T d_{2p,j} + i S^T d_{2p+1,j}.
@@ -79,22 +84,35 @@ __global__ void k_pack_filters(const float* __restrict__ d, float2* __restrict__
   E[(int64_t(j) * P + p) * D + f] = v;
 }
 
-// Real planes -> complex planes with zero imaginary part.
-__global__ void k_real_to_complex(const float* __restrict__ src, float2* __restrict__ dst, int64_t count) {
+// Images -> complex planes with zero imaginary part: dst[n][j] = b of image n
+// (dense [N][J][grid], or at boff[n] when a table is given).
+__global__ void k_pack_images(const float* __restrict__ b, const int64_t* __restrict__ boff,
+                              float2* __restrict__ dst, int J, int64_t D) {
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int j = blockIdx.y, n = blockIdx.z;
+  if (f >= D) return;
+  const int64_t base = boff ? boff[n] : int64_t(n) * J * D;
+  dst[(int64_t(n) * J + j) * D + f] = make_float2(b[base + int64_t(j) * D + f], 0.f);
+}
+
+// Zero the code maps of every image (dense or through the offset table).
+__global__ void k_zero_maps(float* __restrict__ z, const int64_t* __restrict__ zoff, int K, int64_t D) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < count) dst[i] = make_float2(src[i], 0.f);
+  const int n = blockIdx.y;
+  if (i < int64_t(K) * D) z[map_base(zoff, n, K, D) + i] = 0.f;
 }
 
 // Map pairs -> complex planes; l1 partial sums of |maps| per (image, block).
-__global__ void k_pack_maps(const float* __restrict__ z, float2* __restrict__ buf, double* __restrict__ l1,
-                            int K, int P, int64_t D) {
+__global__ void k_pack_maps(const float* __restrict__ z, const int64_t* __restrict__ zoff, float2* __restrict__ buf,
+                            double* __restrict__ l1, int K, int P, int64_t D) {
   __shared__ double red[kEW / 64];
   const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int p = blockIdx.y, n = blockIdx.z;
   double s = 0.0;
   if (f < D) {
-    const float a = z[(int64_t(n) * K + 2 * p) * D + f];
-    const float b = (2 * p + 1 < K) ? z[(int64_t(n) * K + 2 * p + 1) * D + f] : 0.f;
+    const float* zn = z + map_base(zoff, n, K, D);
+    const float a = zn[int64_t(2 * p) * D + f];
+    const float b = (2 * p + 1 < K) ? zn[int64_t(2 * p + 1) * D + f] : 0.f;
     buf[(int64_t(n) * P + p) * D + f] = make_float2(a, b);
     s = (double)fabsf(a) + (double)fabsf(b);
   }
@@ -146,6 +164,10 @@ __global__ void k_gram(const float2* __restrict__ E, float2* __restrict__ G, int
 __global__ void k_fill_f2(float2* __restrict__ dst, int64_t count) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < count) dst[i] = make_float2(0.f, 0.f);
+}
+__global__ void k_copy_f(float* __restrict__ dst, const float* __restrict__ src, int64_t count) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = src[i];
 }
 __global__ void k_fill_f(float* __restrict__ dst, int64_t count, float v) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -374,8 +396,8 @@ enum { kModeIter = 0, kModeForward = 1 };
 template <int H, int W, int J, int MODE>
 __global__ __launch_bounds__(fused_threads(H * W, J)) void k_fused(
     const float2* __restrict__ E, const float2* __restrict__ lam, float* __restrict__ z,
-    float* __restrict__ theta, const float* __restrict__ rho_cur, float beta, float2* __restrict__ part,
-    double* __restrict__ rpart, int K, int P, int ppg, int ng) {
+    float* __restrict__ theta, const int64_t* __restrict__ zoff, const float* __restrict__ rho_cur, float beta,
+    float2* __restrict__ part, double* __restrict__ rpart, int K, int P, int ppg, int ng) {
   constexpr int D = H * W, NT = fused_threads(D, J), WP = tile_stride(W);
   using PL = TilePlan<H, W, NT, WP>;
   using P1 = typename PL::InvRow0;
@@ -407,8 +429,9 @@ __global__ __launch_bounds__(fused_threads(H * W, J)) void k_fused(
     const int tid = opaque_tid();
     const int ka = 2 * p, kb = 2 * p + 1;
     const bool hb = kb < K;
-    float* za = z + (int64_t(n) * K + ka) * D;
-    float* zb = z + (int64_t(n) * K + (hb ? kb : ka)) * D;
+    const int64_t zbase = map_base(zoff, n, K, D);
+    float* za = z + zbase + int64_t(ka) * D;
+    float* zb = z + zbase + int64_t(hb ? kb : ka) * D;
     const float2* Ep[J];
 #pragma unroll
     for (int c = 0; c < J; ++c) Ep[c] = E + (int64_t(c) * P + p) * D;
@@ -438,8 +461,8 @@ __global__ __launch_bounds__(fused_threads(H * W, J)) void k_fused(
       if constexpr (PL::NA == 2) pass_lds<typename PL::InvRow1>(tile, tw);
       if constexpr (PL::NB == 2) pass_lds<typename PL::InvCol0>(tile, tw);
       pass_to_regs<P4>(tid, tile, tw, v4);
-      float* tha = theta ? theta + (int64_t(n) * K + ka) * D : nullptr;
-      float* thb = theta ? theta + (int64_t(n) * K + (hb ? kb : ka)) * D : nullptr;
+      float* tha = theta ? theta + zbase + int64_t(ka) * D : nullptr;
+      float* thb = theta ? theta + zbase + int64_t(hb ? kb : ka) * D : nullptr;
 #pragma unroll
       for (int q = 0; q < P4::JPT; ++q) {
         int b, j;
@@ -549,7 +572,8 @@ __global__ void k_make_v(const float2* __restrict__ E, const float2* __restrict_
 // Soft-threshold step on buf (holding D * (D^T lam) for the pair); writes the
 // new pair back into buf for the forward FFT.  rpart [N][P * gridDim.x].
 __global__ __launch_bounds__(kEW) void k_spatial(float2* __restrict__ buf, float* __restrict__ z,
-                                                 float* __restrict__ theta, const float* __restrict__ rho_cur,
+                                                 float* __restrict__ theta, const int64_t* __restrict__ zoff,
+                                                 const float* __restrict__ rho_cur,
                                                  float beta, double* __restrict__ rpart, int K, int P, int64_t D) {
   __shared__ double red[kEW / 64];
   const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -562,8 +586,9 @@ __global__ __launch_bounds__(kEW) void k_spatial(float2* __restrict__ buf, float
     float2* bp = buf + (int64_t(n) * P + p) * D + f;
     const float2 c = *bp;
     const float va = c.x * invD, vb = c.y * invD;
-    float* za = z + (int64_t(n) * K + ka) * D + f;
-    float* zb = z + (int64_t(n) * K + (hb ? kb : ka)) * D + f;
+    const int64_t zbase = map_base(zoff, n, K, D);
+    float* za = z + zbase + int64_t(ka) * D + f;
+    float* zb = z + zbase + int64_t(hb ? kb : ka) * D + f;
     const float a0 = *za, b0 = hb ? *zb : 0.f;
     const float a1 = soft_thresh(fmaf(-rho, va, a0), thr);
     const float b1 = hb ? soft_thresh(fmaf(-rho, vb, b0), thr) : 0.f;
@@ -572,8 +597,8 @@ __global__ __launch_bounds__(kEW) void k_spatial(float2* __restrict__ buf, float
     *za = a1;
     if (hb) *zb = b1;
     if (theta) {
-      theta[(int64_t(n) * K + ka) * D + f] = va + (a1 - a0) * inv_rho;
-      if (hb) theta[(int64_t(n) * K + kb) * D + f] = vb + (b1 - b0) * inv_rho;
+      theta[zbase + int64_t(ka) * D + f] = va + (a1 - a0) * inv_rho;
+      if (hb) theta[zbase + int64_t(kb) * D + f] = vb + (b1 - b0) * inv_rho;
     }
     *bp = make_float2(a1, b1);
   }
@@ -661,7 +686,7 @@ static bool fused_launch(const Plan& pl, const float2* E, const float2* lam, flo
 #define FL(HH, WW)                                                                                         \
   if (h == HH && w == WW) {                                                                                \
     hipLaunchKernelGGL((k_fused<HH, WW, J, MODE>), grid, dim3(fused_threads(HH * WW, J)), 0, st, E, lam, z, \
-                       theta, rho, beta, part, rpart, pl.k, pl.p, pl.ppg, pl.ng);                        \
+                       theta, pl.zoff, rho, beta, part, rpart, pl.k, pl.p, pl.ppg, pl.ng);               \
     return true;                                                                                           \
   }
   FL(16, 16) FL(16, 32) FL(16, 64) FL(16, 128) FL(16, 256)
@@ -724,8 +749,7 @@ static hipError_t setup_spectra(const Plan& pl, const float* b, const float* d, 
   hipError_t e = fft_grids(w.E, int64_t(pl.j) * pl.p, pl.g, +1, st);
   if (e != hipSuccess) return e;
   LAUNCH_J(k_gram, pl.j, dim3(nblk(D)), dim3(kEW), st, w.E, w.G, pl.p, T, H, W);
-  const int64_t nx = int64_t(pl.n) * pl.j * D;
-  hipLaunchKernelGGL(k_real_to_complex, dim3(nblk(nx)), dim3(kEW), 0, st, b, w.xh, nx);
+  hipLaunchKernelGGL(k_pack_images, dim3(nblk(D), pl.j, pl.n), dim3(kEW), 0, st, b, pl.boff, w.xh, pl.j, D);
   e = fft_grids(w.xh, int64_t(pl.n) * pl.j, pl.g, -1, st);
   if (e != hipSuccess) return e;
   return hipGetLastError();
@@ -741,7 +765,8 @@ static hipError_t forward_maps(const Plan& pl, const float* maps, CodeWs& w, dou
       return hipErrorInvalidValue;
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_pack_maps, dim3(nblk(D), pl.p, pl.n), dim3(kEW), 0, st, maps, w.buf, l1, pl.k, pl.p, D);
+  hipLaunchKernelGGL(k_pack_maps, dim3(nblk(D), pl.p, pl.n), dim3(kEW), 0, st, maps, pl.zoff, w.buf, l1, pl.k,
+                     pl.p, D);
   hipError_t e = fft_grids(w.buf, int64_t(pl.n) * pl.p, pl.g, -1, st);
   if (e != hipSuccess) return e;
   LAUNCH_J(k_accum, pl.j, dim3(nblk(D), pl.n), dim3(kEW), st, w.buf, w.E, w.part, pl.p, D);
@@ -760,8 +785,8 @@ static hipError_t iterate_maps(const Plan& pl, CodeWs& w, float* z, float* theta
   LAUNCH_J(k_make_v, pl.j, dim3(nblk(D), pl.p, pl.n), dim3(kEW), st, w.E, w.lam, w.buf, pl.p, D);
   hipError_t e = fft_grids(w.buf, int64_t(pl.n) * pl.p, pl.g, +1, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_spatial, dim3(nblk(D), pl.p, pl.n), dim3(kEW), 0, st, w.buf, z, theta, w.rho, beta, w.rpri,
-                     pl.k, pl.p, D);
+  hipLaunchKernelGGL(k_spatial, dim3(nblk(D), pl.p, pl.n), dim3(kEW), 0, st, w.buf, z, theta, pl.zoff, w.rho, beta,
+                     w.rpri, pl.k, pl.p, D);
   e = fft_grids(w.buf, int64_t(pl.n) * pl.p, pl.g, -1, st);
   if (e != hipSuccess) return e;
   LAUNCH_J(k_accum, pl.j, dim3(nblk(D), pl.n), dim3(kEW), st, w.buf, w.E, w.part, pl.p, D);
@@ -777,12 +802,12 @@ int run_code(const Plan& pl, const float* b, const float* d, float beta, float* 
   const bool adaptive = (flags & CSC_ADAPTIVE_RHO) != 0;
   const bool z_zero = (flags & CSC_Z_ZERO) != 0;
   const bool th_zero = theta == nullptr || (flags & CSC_THETA_ZERO) != 0;
-  const int64_t nz = N * pl.k * D, ns = N * J * D;
+  const int64_t ns = N * J * D;
   hipError_t e;
   if ((e = setup_spectra(pl, b, d, w, st)) != hipSuccess) return CSC_EHIP;
-  hipMemcpyAsync(w.rho, rho, sizeof(float) * N, hipMemcpyDeviceToDevice, st);
+  hipLaunchKernelGGL(k_copy_f, dim3(nblk(N)), dim3(kEW), 0, st, w.rho, rho, N);
   if (z_zero) {
-    hipLaunchKernelGGL(k_fill_f, dim3(nblk(nz)), dim3(kEW), 0, st, z, nz, 0.f);
+    hipLaunchKernelGGL(k_zero_maps, dim3(nblk(int64_t(pl.k) * D), N), dim3(kEW), 0, st, z, pl.zoff, pl.k, D);
     hipLaunchKernelGGL(k_fill_f2, dim3(nblk(ns)), dim3(kEW), 0, st, w.yh, ns);
   } else {
     if ((e = forward_maps(pl, z, w, w.rpri, st)) != hipSuccess) return CSC_EHIP;
@@ -790,7 +815,8 @@ int run_code(const Plan& pl, const float* b, const float* d, float beta, float* 
   }
   if (th_zero) {
     hipLaunchKernelGGL(k_fill_f2, dim3(nblk(ns)), dim3(kEW), 0, st, w.Th, ns);
-    if (theta && iters == 0) hipLaunchKernelGGL(k_fill_f, dim3(nblk(nz)), dim3(kEW), 0, st, theta, nz, 0.f);
+    if (theta && iters == 0)
+      hipLaunchKernelGGL(k_zero_maps, dim3(nblk(int64_t(pl.k) * D), N), dim3(kEW), 0, st, theta, pl.zoff, pl.k, D);
   } else {
     if ((e = forward_maps(pl, theta, w, w.rpri, st)) != hipSuccess) return CSC_EHIP;
     LAUNCH_J(k_sym_reduce, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.part, w.Th, w.ngp, T, H, W);
@@ -810,7 +836,7 @@ int run_code(const Plan& pl, const float* b, const float* d, float beta, float* 
     if (adaptive && !last)
       LAUNCH_J(k_solve, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.G, w.xh, w.yh, w.Th, w.rho, w.lam, D);
   }
-  if (adaptive) hipMemcpyAsync(rho, w.rho, sizeof(float) * N, hipMemcpyDeviceToDevice, st);
+  if (adaptive) hipLaunchKernelGGL(k_copy_f, dim3(nblk(N)), dim3(kEW), 0, st, rho, w.rho, N);
   return hipGetLastError() == hipSuccess ? CSC_OK : CSC_EHIP;
 }
 

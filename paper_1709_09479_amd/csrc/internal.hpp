@@ -21,7 +21,15 @@ struct Plan {
   bool lds = false;                // whole grid fits one LDS tile (fused path)
   int ng = 1;                      // pair groups per image in the fused kernel
   int ppg = 1;                     // pairs per group
+  // Optional device tables (batched form): element offset of image n's
+  // block in b ([J][grid]) and in z / theta ([K][grid]).  NULL = dense.
+  const int64_t* boff = nullptr;
+  const int64_t* zoff = nullptr;
 };
+
+// Pairs per group for a tile-path plan (fills the chip with one or a few
+// workgroups per CU); ppg_override > 0 replaces the heuristic.
+void set_grouping(Plan* pl, int ppg_override);
 
 // Largest grid (complex elements) that one LDS tile holds.
 constexpr int kTileMax = 16384;
