@@ -33,6 +33,61 @@ def alg_bytes_per_iter(n, j, k, d):
     return 8 * n * k * d + 4 * j * k * d + 12 * n * j * d
 
 
+def bench_batched(dc, synth, np, torch, n_images):
+    """Ragged batch: 256 images with sides drawn from 48..256 (padded to the
+    next power of two), K = 64 shared 11x11 filters, beta = 1, rho = 10,
+    30 ADMM iterations; one csc_code_batched call replayed from its hipGraph,
+    against the plain solver called once per image."""
+    cfg = synth.CONFIGS["batched"]
+    imgs, grids, d0 = synth.ragged_inputs(cfg, n=n_images)
+    dev = torch.device("cuda:0")
+    padded = []
+    for im, g in zip(imgs, grids):
+        t = torch.zeros((1,) + g, dtype=torch.float32)
+        t[:, :im.shape[1], :im.shape[2]] = torch.from_numpy(im)
+        padded.append(t.to(dev))
+    dt = torch.from_numpy(d0).to(dev)
+    pb = dc.PackedBatch(padded, cfg.k)
+    classes = pb.classes(cfg.fsupp)
+    z = torch.empty(pb.z_numel, dtype=torch.float32, device=dev)
+    it = cfg.t_in
+    dc.code_batched(pb, dt, cfg.beta, cfg.rho, it, z=z, graph=True)   # capture + first replay
+    torch.cuda.synchronize()
+    reps = 3
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dc.code_batched(pb, dt, cfg.beta, cfg.rho, it, z=z, graph=True)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    # plain solver, one call per image
+    stack = [p[None] for p in padded]
+    dc.code(stack[0], dt, cfg.beta, cfg.rho, it)
+    torch.cuda.synchronize()
+    p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    p0.record()
+    for x in stack:
+        dc.code(x, dt, cfg.beta, cfg.rho, it)
+    p1.record()
+    torch.cuda.synchronize()
+    ms_plain = p0.elapsed_time(p1)
+    pix_pad = sum(g[0] * g[1] for g in grids)
+    pix_raw = sum(im.shape[1] * im.shape[2] for im in imgs)
+    bytes_iter = sum(alg_bytes_per_iter(c, 1, cfg.k, g[0] * g[1]) for g, c in classes)
+    return {
+        "workload": "%d ragged images (sides 48..256, padded to powers of two), K=%d 11x11, beta=1, rho=10, "
+                    "%d iterations, hipGraph replay" % (len(imgs), cfg.k, it),
+        "grid_classes": [[g[0], g[1], c] for g, c in classes],
+        "ms_per_call": ms,
+        "cp_it_per_s_padded": cfg.k * pix_pad * it / (ms / 1e3),
+        "cp_it_per_s_unpadded": cfg.k * pix_raw * it / (ms / 1e3),
+        "alg_gbps": bytes_iter * it / (ms / 1e3) / 1e9,
+        "plain_per_image_ms": ms_plain,
+        "speedup_vs_plain": ms_plain / ms,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -40,6 +95,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-images", type=int, default=2)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-images", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on one GPU only (the build targets a single MI355X); "
@@ -161,6 +218,9 @@ def main():
         },
         "objective_last": float(state["obj"][-1].item()),
     }
+
+    if not args.no_batched:
+        out["batched"] = bench_batched(dc, synth, np, torch, args.batched_images)
 
     if not args.no_cpu_baseline:
         import oracle

@@ -147,6 +147,49 @@ int csc_objective(const csc_shape* shape, const float* b, const float* d,
                   size_t ws_bytes, void* stream);
 
 /*
+ * Differentiable coding (grayscale, J = 1; J > 1 gives CSC_EUNSUPPORTED).
+ *
+ * csc_code_unrolled runs `iters` literal iterations of eq:Inference_solution
+ * from z = theta = 0 at the fixed per-image steps rho [N] (device) and
+ * writes z^T.  If `ckpt` is non-NULL it receives the state (z, theta) at
+ * iterations 0, every, 2 every, ... : ceil(iters / every) records of
+ * [2][N][K][grid] floats (device, caller-owned).
+ *
+ * csc_code_backward is the reverse pass of that solve: given the same
+ * inputs, the checkpoints and zbar = dL/dz^T [N][K][grid], it writes
+ * dd = dL/dd [K][1][fsupp] and *dbeta = dL/dbeta (device float64) through
+ * every iteration (the filters enter each iteration through D and
+ * (D D^T + I/rho)^-1).  It replays `every` iterations at a time from their
+ * checkpoint.  Kinks: the clip passes gradient iff |u| < beta strictly and
+ * contributes sign(u) to dL/dbeta iff |u| > beta.
+ *
+ * csc_loss_grad evaluates the objective of eq:CSC, loss [N + 1] (as
+ * csc_objective), and its gradients: zbar = D^T (D z - x) + beta sign(z)
+ * (sign(0) = 0) [N][K][grid], dd [K][1][fsupp] and *dbeta = ||z||_1.
+ *
+ * All three share one workspace size, csc_unrolled_workspace_bytes(shape,
+ * every) (use every = 1 for csc_loss_grad).
+ * Errors: CSC_EINVAL (NULL pointers, iters < 0, every < 1, beta < 0),
+ *         CSC_EUNSUPPORTED, CSC_EWORKSPACE, CSC_EHIP.
+ */
+size_t csc_unrolled_workspace_bytes(const csc_shape* shape, int every);
+
+int csc_code_unrolled(const csc_shape* shape, const float* b, const float* d,
+                      float beta, const float* rho, int iters, int every,
+                      float* z, float* ckpt, void* ws, size_t ws_bytes,
+                      void* stream);
+
+int csc_code_backward(const csc_shape* shape, const float* b, const float* d,
+                      float beta, const float* rho, int iters, int every,
+                      const float* ckpt, const float* zbar, float* dd,
+                      double* dbeta, void* ws, size_t ws_bytes, void* stream);
+
+int csc_loss_grad(const csc_shape* shape, const float* b, const float* d,
+                  const float* z, float beta, double* loss, float* zbar,
+                  float* dd, double* dbeta, void* ws, size_t ws_bytes,
+                  void* stream);
+
+/*
  * Batched coding: many grayscale images of uneven sizes share K filters
  * (the coding problem separates over images, Sec. 3.1, so each image is
  * coded exactly as by csc_code with J = 1 and a fixed rho).

@@ -14,6 +14,7 @@ from .csc import (  # noqa: F401
     filter_spectra,
     reconstruct,
     objective,
+    objective_grad,
     soft,
     code,
     code_implicit,

@@ -332,6 +332,27 @@ def learn_dictionary(b, d0, beta, rho, t_in, t_out, inner_iters=10, cg_iters=10,
             "objectives": objs}
 
 
+def objective_grad(b, d, z, beta):
+    """Gradients of the objective of eq:CSC, f = sum_n 1/2 ||D z - x||^2 +
+    beta ||z||_1: dz = D^T (D z - x) + beta sign(z) (sign(0) = 0),
+    dd_jk[m] = sum_n sum_p (D z - x)_j[p] z_k[p - m], dbeta = ||z||_1.
+    Returns (f, dz, dd, dbeta)."""
+    b = np.asarray(b, _f64)
+    z = np.asarray(z, _f64)
+    d = np.asarray(d, _f64)
+    nd = d.ndim - 2
+    fsupp = d.shape[2:]
+    grid = b.shape[2:]
+    dh = filter_spectra(d, grid)
+    res = reconstruct(d, z) - b
+    f = 0.5 * (res ** 2).sum() + beta * np.abs(z).sum()
+    dz = _ifft_real(np.einsum("jk...,nj...->nk...", np.conj(dh), _fft(res, nd)), nd) + beta * np.sign(z)
+    dd = np.zeros(d.shape)
+    for n in range(b.shape[0]):
+        dd += _corr_crop(res[n], z[n], fsupp, nd)
+    return float(f), dz, dd, float(np.abs(z).sum())
+
+
 def _corr_crop(a, bsig, fsupp, nd):
     """c_jk[m] = sum_p a_j[p] b_k[p - m] for m in the support: the gradient of
     <a, d * b> with respect to the taps of d.  a [J][*grid], b [K][*grid] ->

@@ -19,7 +19,7 @@ from typing import Optional, Sequence, Tuple
 __all__ = [
     "DualCSCError", "load", "lib_path", "Shape", "code", "learn", "objective",
     "learn_dictionary", "workspace_bytes", "trace_enable", "trace_read", "ADAPTIVE_RHO", "Z_ZERO", "THETA_ZERO",
-    "GAMMA_ZERO", "USE_GRAPH", "PackedBatch", "code_batched", "autotune_batched",
+    "GAMMA_ZERO", "USE_GRAPH", "PackedBatch", "code_batched", "autotune_batched", "unrolled_code", "csc_loss",
 ]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -118,6 +118,14 @@ def load() -> ctypes.CDLL:
     lib.csc_code_batched.argtypes = [bp, vp, vp, f32, f32, i32, u32, vp, vp, sz, vp]
     lib.csc_batch_autotune.restype = i32
     lib.csc_batch_autotune.argtypes = [bp, vp, vp, f32, f32, i32, vp, vp, sz, vp, ctypes.POINTER(ctypes.c_int32), i32]
+    lib.csc_unrolled_workspace_bytes.restype = sz
+    lib.csc_unrolled_workspace_bytes.argtypes = [sp, i32]
+    lib.csc_code_unrolled.restype = i32
+    lib.csc_code_unrolled.argtypes = [sp, vp, vp, f32, vp, i32, i32, vp, vp, vp, sz, vp]
+    lib.csc_code_backward.restype = i32
+    lib.csc_code_backward.argtypes = [sp, vp, vp, f32, vp, i32, i32, vp, vp, vp, vp, vp, sz, vp]
+    lib.csc_loss_grad.restype = i32
+    lib.csc_loss_grad.argtypes = [sp, vp, vp, vp, f32, vp, vp, vp, vp, vp, sz, vp]
     if lib.csc_abi_version() != ABI_VERSION:
         raise DualCSCError(EINVAL, "ABI version mismatch")
     _lib = lib
@@ -469,3 +477,115 @@ def code_batched(pb: PackedBatch, d, beta: float, rho: float, iters: int, z=None
 
 
 _BATCH_STREAM = None
+
+
+# ----------------------------------------------------------- differentiable
+
+def _diff_ws(shape, every, device):
+    need = load().csc_unrolled_workspace_bytes(ctypes.byref(shape), int(every))
+    return _workspace_raw(need, "diff", device)
+
+
+def _rho_tensor(rho, n, device):
+    torch = _torch()
+    if isinstance(rho, torch.Tensor):
+        return rho.to(device=device, dtype=torch.float32).contiguous()
+    return torch.full((n,), float(rho), dtype=torch.float32, device=device)
+
+
+def _make_unrolled():
+    torch = _torch()
+
+    class CSCUnrolled(torch.autograd.Function):
+        """z^T = unrolled coding solve (csc_code_unrolled); the backward pass
+        is the library's adjoint (csc_code_backward) with respect to the
+        filters d and the sparsity weight beta (a tensor)."""
+
+        @staticmethod
+        def forward(ctx, b, d, beta, rho, iters, every):
+            lib = load()
+            _need(b, "b")
+            d = d.detach().contiguous()
+            _need(d, "d")
+            shape = _shape_of(b, d)
+            N, K = b.shape[0], d.shape[0]
+            rho_t = _rho_tensor(rho, N, b.device)
+            nck = (int(iters) + int(every) - 1) // int(every)
+            z = torch.empty((N, K) + tuple(b.shape[2:]), dtype=torch.float32, device=b.device)
+            ckpt = torch.empty(max(1, nck) * 2 * z.numel(), dtype=torch.float32, device=b.device)
+            ws, nbytes = _diff_ws(shape, every, b.device)
+            _check(lib.csc_code_unrolled(ctypes.byref(shape), _ptr(b), _ptr(d), float(beta), _ptr(rho_t),
+                                         int(iters), int(every), _ptr(z), _ptr(ckpt), ws, nbytes, _stream()))
+            ctx.save_for_backward(b, d, rho_t, ckpt)
+            ctx.cfg = (float(beta), int(iters), int(every))
+            ctx.beta_is_tensor = isinstance(beta, torch.Tensor)
+            return z
+
+        @staticmethod
+        def backward(ctx, zbar):
+            lib = load()
+            b, d, rho_t, ckpt = ctx.saved_tensors
+            beta, iters, every = ctx.cfg
+            shape = _shape_of(b, d)
+            zbar = zbar.contiguous().to(torch.float32)
+            dd = torch.empty_like(d)
+            dbeta = torch.empty(1, dtype=torch.float64, device=b.device)
+            ws, nbytes = _diff_ws(shape, every, b.device)
+            _check(lib.csc_code_backward(ctypes.byref(shape), _ptr(b), _ptr(d), beta, _ptr(rho_t), iters, every,
+                                         _ptr(ckpt), _ptr(zbar), _ptr(dd), _ptr(dbeta), ws, nbytes, _stream()))
+            gb = dbeta.reshape(()) if ctx.beta_is_tensor else None
+            return None, dd, gb, None, None, None
+
+    class CSCLoss(torch.autograd.Function):
+        """Objective of eq:CSC summed over images (float64 scalar), with
+        gradients with respect to d, z and beta (csc_loss_grad)."""
+
+        @staticmethod
+        def forward(ctx, b, d, z, beta):
+            lib = load()
+            d = d.detach().contiguous()
+            z = z.detach().contiguous()
+            _need(b, "b")
+            _need(d, "d")
+            _need(z, "z")
+            shape = _shape_of(b, d)
+            loss = torch.empty(b.shape[0] + 1, dtype=torch.float64, device=b.device)
+            zbar = torch.empty_like(z)
+            dd = torch.empty_like(d)
+            dbeta = torch.empty(1, dtype=torch.float64, device=b.device)
+            ws, nbytes = _diff_ws(shape, 1, b.device)
+            _check(lib.csc_loss_grad(ctypes.byref(shape), _ptr(b), _ptr(d), _ptr(z), float(beta), _ptr(loss),
+                                     _ptr(zbar), _ptr(dd), _ptr(dbeta), ws, nbytes, _stream()))
+            ctx.save_for_backward(zbar, dd, dbeta)
+            ctx.beta_is_tensor = isinstance(beta, torch.Tensor)
+            return loss[-1]
+
+        @staticmethod
+        def backward(ctx, g):
+            zbar, dd, dbeta = ctx.saved_tensors
+            gf = g.to(torch.float32)
+            gb = (g * dbeta.reshape(())) if ctx.beta_is_tensor else None
+            return None, dd * gf, zbar * gf, gb
+
+    return CSCUnrolled, CSCLoss
+
+
+_AUTOGRAD = None
+
+
+def _autograd():
+    global _AUTOGRAD
+    if _AUTOGRAD is None:
+        _AUTOGRAD = _make_unrolled()
+    return _AUTOGRAD
+
+
+def unrolled_code(b, d, beta, rho, iters: int, every: int = 5):
+    """Codes after ``iters`` unrolled ADMM iterations from zero, differentiable
+    in d and (when a tensor) beta; checkpoints every ``every`` iterations."""
+    return _autograd()[0].apply(b, d, beta, rho, int(iters), int(every))
+
+
+def csc_loss(b, d, z, beta):
+    """Objective of eq:CSC (sum over images), differentiable in d, z, beta."""
+    return _autograd()[1].apply(b, d, z, beta)

@@ -17,6 +17,13 @@ int run_objective(const Plan& pl, const float* b, const float* d, const float* z
 int run_learn(const Plan& pl, const float* b, const float* z, float* d, float* mu, float* gamma, int inner_iters,
               int cg_iters, unsigned flags, void* ws, hipStream_t st);
 size_t run_learn_ws(const Plan& pl);
+size_t run_diff_ws(const Plan& pl, int every);
+int run_unrolled(const Plan& pl, const float* b, const float* d, float beta, const float* rho, int iters, int every,
+                 float* z, float* ckpt, void* ws, hipStream_t st);
+int run_backward(const Plan& pl, const float* b, const float* d, float beta, const float* rho, int iters, int every,
+                 const float* ckpt, const float* zbar_in, float* dd, double* dbeta, void* ws, hipStream_t st);
+int run_loss_grad(const Plan& pl, const float* b, const float* d, const float* z, float beta, double* loss,
+                  float* zbar, float* dd, double* dbeta, void* ws, hipStream_t st);
 
 static bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
@@ -194,6 +201,50 @@ int csc_learn(const csc_shape* shape, const float* b, const float* z, float* d, 
   if (flags & ~CSC_GAMMA_ZERO) return CSC_EINVAL;
   if ((rc = check_ws(ws, ws_bytes, run_learn_ws(pl))) != CSC_OK) return rc;
   return run_learn(pl, b, z, d, mu, gamma, inner_iters, cg_iters, flags, ws, static_cast<hipStream_t>(stream));
+}
+
+size_t csc_unrolled_workspace_bytes(const csc_shape* shape, int every) {
+  Plan pl;
+  if (make_plan(shape, &pl) != CSC_OK || pl.j != 1 || every < 1) return 0;
+  return run_diff_ws(pl, every);
+}
+
+static int diff_plan(const csc_shape* shape, Plan* pl) {
+  int rc = make_plan(shape, pl);
+  if (rc != CSC_OK) return rc;
+  return pl->j == 1 ? CSC_OK : CSC_EUNSUPPORTED;
+}
+
+int csc_code_unrolled(const csc_shape* shape, const float* b, const float* d, float beta, const float* rho,
+                      int iters, int every, float* z, float* ckpt, void* ws, size_t ws_bytes, void* stream) {
+  Plan pl;
+  int rc = diff_plan(shape, &pl);
+  if (rc != CSC_OK) return rc;
+  if (!b || !d || !rho || !z || iters < 0 || every < 1 || !(beta >= 0.0f)) return CSC_EINVAL;
+  if ((rc = check_ws(ws, ws_bytes, run_diff_ws(pl, every))) != CSC_OK) return rc;
+  return run_unrolled(pl, b, d, beta, rho, iters, every, z, ckpt, ws, static_cast<hipStream_t>(stream));
+}
+
+int csc_code_backward(const csc_shape* shape, const float* b, const float* d, float beta, const float* rho,
+                      int iters, int every, const float* ckpt, const float* zbar, float* dd, double* dbeta, void* ws,
+                      size_t ws_bytes, void* stream) {
+  Plan pl;
+  int rc = diff_plan(shape, &pl);
+  if (rc != CSC_OK) return rc;
+  if (!b || !d || !rho || !zbar || !dd || !dbeta || iters < 0 || every < 1 || !(beta >= 0.0f)) return CSC_EINVAL;
+  if (iters > 0 && !ckpt) return CSC_EINVAL;
+  if ((rc = check_ws(ws, ws_bytes, run_diff_ws(pl, every))) != CSC_OK) return rc;
+  return run_backward(pl, b, d, beta, rho, iters, every, ckpt, zbar, dd, dbeta, ws, static_cast<hipStream_t>(stream));
+}
+
+int csc_loss_grad(const csc_shape* shape, const float* b, const float* d, const float* z, float beta, double* loss,
+                  float* zbar, float* dd, double* dbeta, void* ws, size_t ws_bytes, void* stream) {
+  Plan pl;
+  int rc = diff_plan(shape, &pl);
+  if (rc != CSC_OK) return rc;
+  if (!b || !d || !z || !loss || !zbar || !dd || !dbeta || !(beta >= 0.0f)) return CSC_EINVAL;
+  if ((rc = check_ws(ws, ws_bytes, run_diff_ws(pl, 1))) != CSC_OK) return rc;
+  return run_loss_grad(pl, b, d, z, beta, loss, zbar, dd, dbeta, ws, static_cast<hipStream_t>(stream));
 }
 
 int csc_objective(const csc_shape* shape, const float* b, const float* d, const float* z, float beta, double* out,

@@ -706,15 +706,7 @@ static bool fused_dispatch(const Plan& pl, const float2* E, const float2* lam, f
   return fused_launch<3, MODE>(pl, E, lam, z, theta, rho, beta, part, rpart, st);
 }
 
-// Workspace for the coding / objective paths.
-struct CodeWs {
-  float2 *E, *G, *xh, *yh, *Th, *lam, *part, *buf;
-  double *rpri, *rdual, *opart;
-  float* rho;
-  int npri, ndual, ngp;  // partial counts per image; pair groups written to part
-};
-
-static size_t carve_code(const Plan& pl, void* base, CodeWs* w) {
+size_t carve_code(const Plan& pl, void* base, CodeWs* w) {
   Carver c(base);
   const int64_t D = pl.dsz, N = pl.n, J = pl.j, P = pl.p;
   w->ngp = pl.lds ? pl.ng : 1;
@@ -741,7 +733,7 @@ static size_t code_ws_bytes(const Plan& pl) {
 }
 
 // Filter pair spectra E and the Gram blocks G; image spectra xhat.
-static hipError_t setup_spectra(const Plan& pl, const float* b, const float* d, CodeWs& w, hipStream_t st) {
+hipError_t setup_spectra(const Plan& pl, const float* b, const float* d, CodeWs& w, hipStream_t st) {
   const int64_t D = pl.dsz;
   const int T = pl.g[0], H = pl.g[1], W = pl.g[2];
   hipLaunchKernelGGL(k_pack_filters, dim3(nblk(D), pl.p, pl.j), dim3(kEW), 0, st, d, w.E, pl.k, pl.j, pl.p, T, H,
@@ -757,7 +749,7 @@ static hipError_t setup_spectra(const Plan& pl, const float* b, const float* d, 
 
 // part <- contributions of the given maps (forward FFT, times conj(E)); the
 // per-image l1 norms go to `l1` ([N][npri]).
-static hipError_t forward_maps(const Plan& pl, const float* maps, CodeWs& w, double* l1, hipStream_t st) {
+hipError_t forward_maps(const Plan& pl, const float* maps, CodeWs& w, double* l1, hipStream_t st) {
   const int64_t D = pl.dsz;
   if (pl.lds) {
     if (!fused_dispatch<kModeForward>(pl, w.E, w.lam, const_cast<float*>(maps), nullptr, w.rho, 0.f, w.part, l1,
@@ -841,6 +833,21 @@ int run_code(const Plan& pl, const float* b, const float* d, float beta, float* 
 }
 
 size_t run_code_ws(const Plan& pl) { return code_ws_bytes(pl); }
+
+void launch_make_v(const Plan& pl, const float2* E, const float2* lam, float2* buf, hipStream_t st) {
+  LAUNCH_J(k_make_v, pl.j, dim3(nblk(pl.dsz), pl.p, pl.n), dim3(kEW), st, E, lam, buf, pl.p, pl.dsz);
+}
+
+void launch_sym_reduce(const Plan& pl, const float2* part, int ng, float2* dst, hipStream_t st) {
+  LAUNCH_J(k_sym_reduce, pl.j, dim3(nblk(pl.dsz), pl.n), dim3(kEW), st, part, dst, ng, pl.g[0], pl.g[1], pl.g[2]);
+}
+
+void launch_objective_tail(const Plan& pl, CodeWs& w, float beta, double* out, hipStream_t st) {
+  LAUNCH_J(k_obj_spec, pl.j, dim3(nblk(pl.dsz), pl.n), dim3(kEW), st, w.part, w.xh, w.opart, w.ngp, pl.g[0], pl.g[1],
+           pl.g[2]);
+  hipLaunchKernelGGL(k_obj_final, dim3(1), dim3(64), 0, st, w.opart, w.ndual, w.rpri, w.npri, out, pl.n, pl.dsz,
+                     beta);
+}
 
 int run_objective(const Plan& pl, const float* b, const float* d, const float* z, float beta, double* out, void* ws,
                   hipStream_t st) {

@@ -1,0 +1,420 @@
+// Differentiable coding: the coding ADMM unrolled for a fixed number of
+// iterations, its reverse (adjoint) pass with respect to the filters and the
+// sparsity weight, and the gradient of the objective of eq:CSC.  Grayscale
+// (J = 1).
+//
+// The unrolled solve runs the literal updates of eq:Inference_solution with
+// theta kept (w = theta + z/rho, s = D w - x/rho, lam = P s with
+// P = (D D^T + I/rho)^-1, v = D^T lam, u = v - z/rho, theta' = clip(u, +-beta),
+// z' = z + rho (theta' - v)) and stores (z, theta) every `every` iterations.
+// The backward pass replays each segment from its checkpoint and walks its
+// iterations in reverse:
+//   t = thbar' + rho zbar';  ubar = t [|u| < beta];  betabar += t sign(u) [|u| > beta]
+//   vbar = ubar - rho zbar';  zbar = zbar' - ubar/rho
+//   sbar = P D vbar;  wbar = D^T sbar;  thetabar = wbar;  zbar += wbar/rho
+//   dbar_k += corr(lam, vbar_k - wbar_k) + corr(sbar, w_k - v_k)
+// where corr(a, b)[m] = sum_p a[p] b[p - m] over the filter support.  In the
+// Fourier domain the filter term per frequency is
+//   lam conj(vbarhat_k) + sbar conj(what_k) - 2 dhat_k Re(lam conj(sbar)),
+// summed over images (fixed order) and iterations, and mapped back to taps
+// by one inverse FFT and the support crop at the end.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace dcsc {
+
+constexpr int kDW = 256;
+
+static unsigned dblk(int64_t n) { return (unsigned)((n + kDW - 1) / kDW); }
+
+__device__ __forceinline__ int64_t dneg(int64_t fl, int T, int H, int W) {
+  const int f = (int)fl;
+  const int lw = __builtin_ctz(W), lh = __builtin_ctz(H);
+  const int w = f & (W - 1), h = (f >> lw) & (H - 1), t = f >> (lw + lh);
+  return (((((T - t) & (T - 1)) << lh) | ((H - h) & (H - 1))) << lw) | ((W - w) & (W - 1));
+}
+
+// a = (c + conj(cm))/2, b = -i (c - conj(cm))/2
+__device__ __forceinline__ void dunpack(float2 c, float2 cm, float2& a, float2& b) {
+  a = make_float2(0.5f * (c.x + cm.x), 0.5f * (c.y - cm.y));
+  b = make_float2(0.5f * (c.y + cm.y), -0.5f * (c.x - cm.x));
+}
+
+// Wbuf[n][p] = (theta + z/rho) for maps 2p, 2p+1
+__global__ void d_pack_w(const float* __restrict__ z, const float* __restrict__ th, float2* __restrict__ Wb,
+                         const float* __restrict__ rho, int K, int P, int64_t D) {
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int p = blockIdx.y, n = blockIdx.z;
+  if (f >= D) return;
+  const float ir = 1.0f / rho[n];
+  const int64_t a = (int64_t(n) * K + 2 * p) * D + f;
+  float2 v = make_float2(th[a] + z[a] * ir, 0.f);
+  if (2 * p + 1 < K) v.y = th[a + D] + z[a + D] * ir;
+  Wb[(int64_t(n) * P + p) * D + f] = v;
+}
+
+// Wbuf[n][p] = (z_2p, z_2p+1)
+__global__ void d_pack_z(const float* __restrict__ z, float2* __restrict__ Wb, int K, int P, int64_t D) {
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int p = blockIdx.y, n = blockIdx.z;
+  if (f >= D) return;
+  const int64_t a = (int64_t(n) * K + 2 * p) * D + f;
+  Wb[(int64_t(n) * P + p) * D + f] = make_float2(z[a], (2 * p + 1 < K) ? z[a + D] : 0.f);
+}
+
+// out[n](f) = Y / (S + 1/rho), Y = sym(sum_p buf conj(E)) (- xhat/rho when xh)
+__global__ void d_reduce_solve(const float2* __restrict__ buf, const float2* __restrict__ E,
+                               const float2* __restrict__ G, const float2* __restrict__ xh,
+                               const float* __restrict__ rho, float2* __restrict__ out, int P, int T, int H,
+                               int W) {
+  const int64_t D = int64_t(T) * H * W;
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int n = blockIdx.y;
+  if (f >= D) return;
+  const int64_t fn = dneg(f, T, H, W);
+  float2 y = make_float2(0.f, 0.f), ym = make_float2(0.f, 0.f);
+  for (int p = 0; p < P; ++p) {
+    const float2* bp = buf + (int64_t(n) * P + p) * D;
+    const float2* ep = E + int64_t(p) * D;
+    y = cadd(y, cmulc(bp[f], ep[f]));
+    ym = cadd(ym, cmulc(bp[fn], ep[fn]));
+  }
+  const float ir = 1.0f / rho[n];
+  float2 s = make_float2(0.5f * (y.x + ym.x), 0.5f * (y.y - ym.y));
+  if (xh) {
+    const float2 x = xh[int64_t(n) * D + f];
+    s = make_float2(s.x - x.x * ir, s.y - x.y * ir);
+  }
+  const float den = G[f].x + ir;
+  out[int64_t(n) * D + f] = make_float2(s.x / den, s.y / den);
+}
+
+// Forward update from V = D * (v_2p + i v_2p+1): theta' = clip(v - z/rho), z' = z + rho (theta' - v).
+__global__ void d_update(const float2* __restrict__ Vb, const float* __restrict__ z, const float* __restrict__ th,
+                         float* __restrict__ zo, float* __restrict__ tho, const float* __restrict__ rho, float beta,
+                         int K, int P, int64_t D) {
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int p = blockIdx.y, n = blockIdx.z;
+  if (f >= D) return;
+  const float r = rho[n], ir = 1.0f / r, invD = 1.0f / (float)D;
+  const float2 c = Vb[(int64_t(n) * P + p) * D + f];
+  const int64_t a = (int64_t(n) * K + 2 * p) * D + f;
+  for (int s = 0; s < 2 && 2 * p + s < K; ++s) {
+    const float v = (s ? c.y : c.x) * invD;
+    const float zz = z[a + s * D];
+    const float t1 = fminf(fmaxf(v - zz * ir, -beta), beta);
+    tho[a + s * D] = t1;
+    zo[a + s * D] = zz + r * (t1 - v);
+  }
+  (void)th;
+}
+
+// Adjoint of the clip and z updates.  In: V (forward D^T lam, unscaled),
+// z_i, zbar', thbar'.  Out: V <- vbar pair (spatial), zbar <- zbar' - ubar/rho,
+// bpart[(n P + p) nblk + blk] += sum t sign(u) [|u| > beta].
+__global__ __launch_bounds__(kDW) void d_adj_clip(float2* __restrict__ Vb, const float* __restrict__ z,
+                                                  float* __restrict__ zbar, const float* __restrict__ thbar,
+                                                  const float* __restrict__ rho, float beta,
+                                                  double* __restrict__ bpart, int K, int P, int64_t D) {
+  __shared__ double red[kDW / 64];
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int p = blockIdx.y, n = blockIdx.z;
+  double bs = 0.0;
+  if (f < D) {
+    const float r = rho[n], ir = 1.0f / r, invD = 1.0f / (float)D;
+    float2* vp = Vb + (int64_t(n) * P + p) * D + f;
+    const float2 c = *vp;
+    const int64_t a = (int64_t(n) * K + 2 * p) * D + f;
+    float vbar[2] = {0.f, 0.f};
+    for (int s = 0; s < 2 && 2 * p + s < K; ++s) {
+      const float v = (s ? c.y : c.x) * invD;
+      const float u = v - z[a + s * D] * ir;
+      const float zb = zbar[a + s * D];
+      const float t = thbar[a + s * D] + r * zb;
+      const float au = fabsf(u);
+      const float ub = au < beta ? t : 0.f;
+      if (au > beta) bs += (double)(u > 0.f ? t : -t);
+      vbar[s] = ub - r * zb;
+      zbar[a + s * D] = zb - ub * ir;
+    }
+    *vp = make_float2(vbar[0], vbar[1]);
+  }
+  const double tot = block_sum(bs, red);
+  if (threadIdx.x == 0) bpart[(int64_t(n) * P + p) * gridDim.x + blockIdx.x] += tot;
+}
+
+// Dbar[p](f) += sum_n [A_2p + i A_2p+1],
+// A_k = lam conj(vbarhat_k) + sbar conj(what_k) - 2 dhat_k Re(lam conj(sbar))
+// (vbarhat from Vb, what from Wb, both pair spectra).  With Wb == nullptr the
+// term is res conj(zhat_k) (lam = res, Vb = code pair spectra): the filter
+// gradient of the data term of eq:CSC.
+__global__ void d_dbar(const float2* __restrict__ Vb, const float2* __restrict__ Wb, const float2* __restrict__ E,
+                       const float2* __restrict__ lam, const float2* __restrict__ sbar, float2* __restrict__ Dbar,
+                       int N, int P, int T, int H, int W) {
+  const int64_t D = int64_t(T) * H * W;
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (f >= D) return;
+  const int64_t fn = dneg(f, T, H, W);
+  float2 da = make_float2(0.f, 0.f), db = make_float2(0.f, 0.f);
+  if (Wb) {
+    const float2 ef = E[int64_t(p) * D + f], em = E[int64_t(p) * D + fn];
+    // dhat_2p = (conj(E(f)) + E(-f))/2, dhat_2p+1 = i (conj(E(f)) - E(-f))/2
+    da = make_float2(0.5f * (ef.x + em.x), 0.5f * (-ef.y + em.y));
+    db = make_float2(0.5f * (ef.y + em.y), 0.5f * (ef.x - em.x));
+  }
+  float2 acc_a = make_float2(0.f, 0.f), acc_b = make_float2(0.f, 0.f);
+  for (int n = 0; n < N; ++n) {
+    const float2* vp = Vb + (int64_t(n) * P + p) * D;
+    float2 va, vb;
+    dunpack(vp[f], vp[fn], va, vb);
+    const float2 l = lam[int64_t(n) * D + f];
+    acc_a = cadd(acc_a, cmulc(l, va));
+    acc_b = cadd(acc_b, cmulc(l, vb));
+    if (Wb) {
+      const float2* wp = Wb + (int64_t(n) * P + p) * D;
+      float2 wa, wb;
+      dunpack(wp[f], wp[fn], wa, wb);
+      const float2 s = sbar[int64_t(n) * D + f];
+      const float re2 = 2.0f * (l.x * s.x + l.y * s.y);
+      acc_a = cadd(acc_a, csub(cmulc(s, wa), cscale(da, re2)));
+      acc_b = cadd(acc_b, csub(cmulc(s, wb), cscale(db, re2)));
+    }
+  }
+  float2* o = Dbar + int64_t(p) * D + f;
+  const float2 cur = *o;
+  *o = make_float2(cur.x + acc_a.x - acc_b.y, cur.y + acc_a.y + acc_b.x);
+}
+
+// thetabar = wbar, zbar += wbar / rho, from W = D * (wbar_2p + i wbar_2p+1).
+__global__ void d_adj_finish(const float2* __restrict__ Wb, float* __restrict__ zbar, float* __restrict__ thbar,
+                             const float* __restrict__ rho, int K, int P, int64_t D) {
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int p = blockIdx.y, n = blockIdx.z;
+  if (f >= D) return;
+  const float ir = 1.0f / rho[n], invD = 1.0f / (float)D;
+  const float2 c = Wb[(int64_t(n) * P + p) * D + f];
+  const int64_t a = (int64_t(n) * K + 2 * p) * D + f;
+  for (int s = 0; s < 2 && 2 * p + s < K; ++s) {
+    const float wb = (s ? c.y : c.x) * invD;
+    thbar[a + s * D] = wb;
+    zbar[a + s * D] += wb * ir;
+  }
+}
+
+// zbar = D^T (D z - x) + beta sign(z) from V = D * D^T(res) pairs.
+__global__ void d_zbar_loss(const float2* __restrict__ Vb, const float* __restrict__ z, float* __restrict__ zbar,
+                            float beta, int K, int P, int64_t D) {
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int p = blockIdx.y, n = blockIdx.z;
+  if (f >= D) return;
+  const float invD = 1.0f / (float)D;
+  const float2 c = Vb[(int64_t(n) * P + p) * D + f];
+  const int64_t a = (int64_t(n) * K + 2 * p) * D + f;
+  for (int s = 0; s < 2 && 2 * p + s < K; ++s) {
+    const float zz = z[a + s * D];
+    const float sg = zz > 0.f ? 1.f : (zz < 0.f ? -1.f : 0.f);
+    zbar[a + s * D] = (s ? c.y : c.x) * invD + beta * sg;
+  }
+}
+
+__global__ void d_sub(const float2* __restrict__ a, const float2* __restrict__ b, float2* __restrict__ o, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) o[i] = csub(a[i], b[i]);
+}
+
+__global__ void d_zero(float* __restrict__ p, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.f;
+}
+__global__ void d_zero_d(double* __restrict__ p, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+__global__ void d_copy(float* __restrict__ dst, const float* __restrict__ src, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+// dd[k][0][m] (+)= (1/D) Re/Im of the inverse FFT of Dbar pair k/2 at tap m.
+__global__ void d_crop_taps(const float2* __restrict__ Dsp, float* __restrict__ dd, int K, int T, int H, int W,
+                            int ft, int fh, int fw, int accumulate) {
+  const int64_t msz = int64_t(ft) * fh * fw;
+  const int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (m >= msz) return;
+  const int t = (int)(m / (int64_t(fh) * fw)), h = (int)((m / fw) % fh), w = (int)(m % fw);
+  const int64_t D = int64_t(T) * H * W;
+  const float2 c = Dsp[int64_t(k / 2) * D + (int64_t(t) * H + h) * W + w];
+  const float v = ((k & 1) ? c.y : c.x) / (float)D;
+  dd[int64_t(k) * msz + m] = accumulate ? dd[int64_t(k) * msz + m] + v : v;
+}
+
+// out[0] = sum of n partials (fixed order), single thread.
+__global__ void d_sum(const double* __restrict__ part, int64_t n, double* __restrict__ out) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int64_t i = 0; i < n; ++i) s += part[i];
+  out[0] = s;
+}
+
+// ----------------------------------------------------------------- host
+
+struct DiffWs {
+  CodeWs cw;
+  float2 *Wb, *Vb, *lam, *sbar, *Dbar;
+  float *zs, *ths, *zbar, *thbar, *seg;
+  double* bpart;
+  int64_t nbpart;
+};
+
+static size_t carve_diff(const Plan& pl, int every, void* base, DiffWs* w) {
+  Carver c(base);
+  const int64_t D = pl.dsz, N = pl.n, P = pl.p, K = pl.k;
+  const size_t cbytes = carve_code(pl, base, &w->cw);
+  c.off = cbytes;
+  w->Wb = c.take<float2>(N * P * D);
+  w->Vb = c.take<float2>(N * P * D);
+  w->lam = c.take<float2>(N * D);
+  w->sbar = c.take<float2>(N * D);
+  w->Dbar = c.take<float2>(P * D);
+  w->zs = c.take<float>(N * K * D);
+  w->ths = c.take<float>(N * K * D);
+  w->zbar = c.take<float>(N * K * D);
+  w->thbar = c.take<float>(N * K * D);
+  w->seg = c.take<float>(int64_t(every > 0 ? every : 1) * 2 * N * K * D);
+  w->nbpart = N * P * int64_t(dblk(D));
+  w->bpart = c.take<double>(w->nbpart + 1);
+  return c.off;
+}
+
+size_t run_diff_ws(const Plan& pl, int every) {
+  DiffWs w;
+  return carve_diff(pl, every, nullptr, &w);
+}
+
+// One literal forward iteration: (z, th) -> (zo, tho); leaves what in Wb,
+// lam, and D * (D^T lam) pairs in Vb.
+static hipError_t lit_forward(const Plan& pl, DiffWs& w, const float* z, const float* th, float* zo, float* tho,
+                              const float* rho, float beta, hipStream_t st, bool update) {
+  const int64_t D = pl.dsz;
+  const dim3 g3(dblk(D), pl.p, pl.n);
+  hipLaunchKernelGGL(d_pack_w, g3, dim3(kDW), 0, st, z, th, w.Wb, rho, pl.k, pl.p, D);
+  hipError_t e = fft_grids(w.Wb, int64_t(pl.n) * pl.p, pl.g, -1, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(d_reduce_solve, dim3(dblk(D), pl.n), dim3(kDW), 0, st, w.Wb, w.cw.E, w.cw.G, w.cw.xh, rho,
+                     w.lam, pl.p, pl.g[0], pl.g[1], pl.g[2]);
+  launch_make_v(pl, w.cw.E, w.lam, w.Vb, st);
+  e = fft_grids(w.Vb, int64_t(pl.n) * pl.p, pl.g, +1, st);
+  if (e != hipSuccess) return e;
+  if (update) hipLaunchKernelGGL(d_update, g3, dim3(kDW), 0, st, w.Vb, z, th, zo, tho, rho, beta, pl.k, pl.p, D);
+  return hipGetLastError();
+}
+
+// Adjoint of one iteration whose input state is (z, th); (zbar, thbar) hold
+// the adjoint of its output and are replaced by the adjoint of its input.
+static hipError_t adjoint_iter(const Plan& pl, DiffWs& w, const float* z, const float* th, const float* rho,
+                               float beta, hipStream_t st) {
+  const int64_t D = pl.dsz;
+  const dim3 g3(dblk(D), pl.p, pl.n);
+  hipError_t e = lit_forward(pl, w, z, th, nullptr, nullptr, rho, beta, st, false);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(d_adj_clip, g3, dim3(kDW), 0, st, w.Vb, z, w.zbar, w.thbar, rho, beta, w.bpart, pl.k, pl.p, D);
+  if ((e = fft_grids(w.Vb, int64_t(pl.n) * pl.p, pl.g, -1, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(d_reduce_solve, dim3(dblk(D), pl.n), dim3(kDW), 0, st, w.Vb, w.cw.E, w.cw.G,
+                     (const float2*)nullptr, rho, w.sbar, pl.p, pl.g[0], pl.g[1], pl.g[2]);
+  hipLaunchKernelGGL(d_dbar, dim3(dblk(D), pl.p), dim3(kDW), 0, st, w.Vb, w.Wb, w.cw.E, w.lam, w.sbar, w.Dbar,
+                     pl.n, pl.p, pl.g[0], pl.g[1], pl.g[2]);
+  launch_make_v(pl, w.cw.E, w.sbar, w.Wb, st);
+  if ((e = fft_grids(w.Wb, int64_t(pl.n) * pl.p, pl.g, +1, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(d_adj_finish, g3, dim3(kDW), 0, st, w.Wb, w.zbar, w.thbar, rho, pl.k, pl.p, D);
+  return hipGetLastError();
+}
+
+static hipError_t finish_taps(const Plan& pl, DiffWs& w, float* dd, bool accumulate, hipStream_t st) {
+  hipError_t e = fft_grids(w.Dbar, pl.p, pl.g, +1, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(d_crop_taps, dim3(dblk(pl.msz), pl.k), dim3(kDW), 0, st, w.Dbar, dd, pl.k, pl.g[0], pl.g[1],
+                     pl.g[2], pl.fs[0], pl.fs[1], pl.fs[2], accumulate ? 1 : 0);
+  return hipGetLastError();
+}
+
+int run_unrolled(const Plan& pl, const float* b, const float* d, float beta, const float* rho, int iters, int every,
+                 float* z, float* ckpt, void* ws, hipStream_t st) {
+  DiffWs w;
+  carve_diff(pl, every, ws, &w);
+  const int64_t nz = int64_t(pl.n) * pl.k * pl.dsz;
+  if (setup_spectra(pl, b, d, w.cw, st) != hipSuccess) return CSC_EHIP;
+  hipLaunchKernelGGL(d_zero, dim3(dblk(nz)), dim3(kDW), 0, st, z, nz);
+  hipLaunchKernelGGL(d_zero, dim3(dblk(nz)), dim3(kDW), 0, st, w.ths, nz);
+  for (int it = 0; it < iters; ++it) {
+    if (ckpt && it % every == 0) {
+      float* c = ckpt + int64_t(it / every) * 2 * nz;
+      hipLaunchKernelGGL(d_copy, dim3(dblk(nz)), dim3(kDW), 0, st, c, z, nz);
+      hipLaunchKernelGGL(d_copy, dim3(dblk(nz)), dim3(kDW), 0, st, c + nz, w.ths, nz);
+    }
+    if (lit_forward(pl, w, z, w.ths, z, w.ths, rho, beta, st, true) != hipSuccess) return CSC_EHIP;
+  }
+  return hipGetLastError() == hipSuccess ? CSC_OK : CSC_EHIP;
+}
+
+int run_backward(const Plan& pl, const float* b, const float* d, float beta, const float* rho, int iters, int every,
+                 const float* ckpt, const float* zbar_in, float* dd, double* dbeta, void* ws, hipStream_t st) {
+  DiffWs w;
+  carve_diff(pl, every, ws, &w);
+  const int64_t D = pl.dsz, nz = int64_t(pl.n) * pl.k * D;
+  if (setup_spectra(pl, b, d, w.cw, st) != hipSuccess) return CSC_EHIP;
+  hipLaunchKernelGGL(d_copy, dim3(dblk(nz)), dim3(kDW), 0, st, w.zbar, zbar_in, nz);
+  hipLaunchKernelGGL(d_zero, dim3(dblk(nz)), dim3(kDW), 0, st, w.thbar, nz);
+  hipLaunchKernelGGL(d_zero, dim3(dblk(int64_t(pl.p) * D * 2)), dim3(kDW), 0, st, (float*)w.Dbar,
+                     int64_t(pl.p) * D * 2);
+  hipLaunchKernelGGL(d_zero_d, dim3(dblk(w.nbpart)), dim3(kDW), 0, st, w.bpart, w.nbpart);
+  const int nseg = (iters + every - 1) / every;
+  for (int sgi = nseg - 1; sgi >= 0; --sgi) {
+    const int c0 = sgi * every, len = (iters - c0 < every) ? iters - c0 : every;
+    const float* ck = ckpt + int64_t(sgi) * 2 * nz;
+    float* s0 = w.seg;
+    hipLaunchKernelGGL(d_copy, dim3(dblk(nz)), dim3(kDW), 0, st, s0, ck, nz);
+    hipLaunchKernelGGL(d_copy, dim3(dblk(nz)), dim3(kDW), 0, st, s0 + nz, ck + nz, nz);
+    for (int i = 1; i < len; ++i) {
+      const float* zi = w.seg + int64_t(i - 1) * 2 * nz;
+      float* zo = w.seg + int64_t(i) * 2 * nz;
+      if (lit_forward(pl, w, zi, zi + nz, zo, zo + nz, rho, beta, st, true) != hipSuccess) return CSC_EHIP;
+    }
+    for (int i = len - 1; i >= 0; --i) {
+      const float* zi = w.seg + int64_t(i) * 2 * nz;
+      if (adjoint_iter(pl, w, zi, zi + nz, rho, beta, st) != hipSuccess) return CSC_EHIP;
+    }
+  }
+  if (finish_taps(pl, w, dd, false, st) != hipSuccess) return CSC_EHIP;
+  hipLaunchKernelGGL(d_sum, dim3(1), dim3(64), 0, st, w.bpart, w.nbpart, dbeta);
+  return hipGetLastError() == hipSuccess ? CSC_OK : CSC_EHIP;
+}
+
+int run_loss_grad(const Plan& pl, const float* b, const float* d, const float* z, float beta, double* loss,
+                  float* zbar, float* dd, double* dbeta, void* ws, hipStream_t st) {
+  DiffWs w;
+  carve_diff(pl, 1, ws, &w);
+  const int64_t D = pl.dsz;
+  const dim3 g3(dblk(D), pl.p, pl.n);
+  if (setup_spectra(pl, b, d, w.cw, st) != hipSuccess) return CSC_EHIP;
+  if (forward_maps(pl, z, w.cw, w.cw.rpri, st) != hipSuccess) return CSC_EHIP;
+  launch_objective_tail(pl, w.cw, beta, loss, st);
+  launch_sym_reduce(pl, w.cw.part, w.cw.ngp, w.cw.yh, st);
+  const int64_t ns = int64_t(pl.n) * D;
+  hipLaunchKernelGGL(d_sub, dim3(dblk(ns)), dim3(kDW), 0, st, w.cw.yh, w.cw.xh, w.lam, ns);  // res hat
+  launch_make_v(pl, w.cw.E, w.lam, w.Vb, st);
+  if (fft_grids(w.Vb, int64_t(pl.n) * pl.p, pl.g, +1, st) != hipSuccess) return CSC_EHIP;
+  hipLaunchKernelGGL(d_zbar_loss, g3, dim3(kDW), 0, st, w.Vb, z, zbar, beta, pl.k, pl.p, D);
+  hipLaunchKernelGGL(d_pack_z, g3, dim3(kDW), 0, st, z, w.Wb, pl.k, pl.p, D);
+  if (fft_grids(w.Wb, int64_t(pl.n) * pl.p, pl.g, -1, st) != hipSuccess) return CSC_EHIP;
+  hipLaunchKernelGGL(d_zero, dim3(dblk(int64_t(pl.p) * D * 2)), dim3(kDW), 0, st, (float*)w.Dbar,
+                     int64_t(pl.p) * D * 2);
+  hipLaunchKernelGGL(d_dbar, dim3(dblk(D), pl.p), dim3(kDW), 0, st, w.Wb, (const float2*)nullptr, w.cw.E, w.lam,
+                     (const float2*)nullptr, w.Dbar, pl.n, pl.p, pl.g[0], pl.g[1], pl.g[2]);
+  if (finish_taps(pl, w, dd, false, st) != hipSuccess) return CSC_EHIP;
+  hipLaunchKernelGGL(d_sum, dim3(1), dim3(64), 0, st, w.cw.rpri, int64_t(pl.n) * w.cw.npri, dbeta);
+  return hipGetLastError() == hipSuccess ? CSC_OK : CSC_EHIP;
+}
+
+}  // namespace dcsc

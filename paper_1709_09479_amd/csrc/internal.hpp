@@ -57,6 +57,26 @@ hipError_t fft_grids(float2* data, int64_t count, const int g[3], int dir, hipSt
 // Whether the fused single-tile kernels exist for this (H, W).
 bool tile_supported(int h, int w);
 
+// Workspace of the coding / objective paths (carved from the caller's block).
+struct CodeWs {
+  float2 *E, *G, *xh, *yh, *Th, *lam, *part, *buf;
+  double *rpri, *rdual, *opart;
+  float* rho;
+  int npri, ndual, ngp;  // partial counts per image; pair groups written to part
+};
+size_t carve_code(const Plan& pl, void* base, CodeWs* w);
+// Filter pair spectra E, Gram blocks G and image spectra xhat.
+hipError_t setup_spectra(const Plan& pl, const float* b, const float* d, CodeWs& w, hipStream_t st);
+// part <- per-group spectral contributions sum_p DFT(maps pair) conj(E_p);
+// l1 <- partial sums of |maps| ([N][npri]).
+hipError_t forward_maps(const Plan& pl, const float* maps, CodeWs& w, double* l1, hipStream_t st);
+// buf[n][p] = sum_j lam[n][j] E[j][p]
+void launch_make_v(const Plan& pl, const float2* E, const float2* lam, float2* buf, hipStream_t st);
+// dst[n][j](f) = (Y(f) + conj(Y(-f)))/2, Y = sum of the ng groups of part
+void launch_sym_reduce(const Plan& pl, const float2* part, int ng, float2* dst, hipStream_t st);
+// objective from part (after forward_maps) and l1 partials in w.rpri
+void launch_objective_tail(const Plan& pl, CodeWs& w, float beta, double* out, hipStream_t st);
+
 // Launch tracing.  While enabled (csc_trace_enable), a TraceScope brackets
 // the launches made in its lifetime with a pair of HIP events recorded on
 // the launching stream; csc_trace_read sums the elapsed times per class.

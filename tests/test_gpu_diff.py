@@ -1,0 +1,102 @@
+"""Differentiable unrolled coding on the GPU: forward parity with the FP64
+oracle, loss gradients, and gradients with respect to the filters and beta
+against the oracle's reverse pass (itself pinned by FP64 finite differences
+in test_oracle.py).  Gradient tolerance: 1e-3 of max |grad| (float32
+forward and adjoint through 30 iterations)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+GRAD_RTOL = 1e-3
+
+
+def T(x, grad=False):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+    return t.requires_grad_(grad)
+
+
+def N(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def test_unrolled_forward_matches_oracle(lib):
+    cfg = synth.CONFIGS["small"]
+    b, d = synth.make_inputs(cfg, n=2)
+    z = lib.unrolled_code(T(b), T(d), cfg.beta, cfg.rho, 12, 5)
+    ref = oracle.code(b, d, cfg.beta, cfg.rho, 12)["z"]
+    assert np.count_nonzero(ref) > 0
+    assert np.abs(N(z) - ref).max() <= 1e-4
+
+
+def test_loss_grad_matches_oracle(lib):
+    import torch
+    b, d = synth.make_inputs(synth.CONFIGS["small"], n=2)
+    z0 = oracle.code(b, d, 1.0, 10.0, 8)["z"].astype(np.float32)
+    dt, zt = T(d, True), T(z0, True)
+    beta = torch.tensor(0.7, dtype=torch.float64, requires_grad=True)
+    L = lib.csc_loss(T(b), dt, zt, beta)
+    L.backward()
+    f, dz, dd, db = oracle.objective_grad(b, d, z0, 0.7)
+    assert abs(L.item() - f) <= 1e-5 * abs(f)
+    assert np.abs(N(zt.grad) - dz).max() <= 1e-4 * max(1.0, np.abs(dz).max())
+    assert np.abs(N(dt.grad) - dd).max() <= 1e-5 * np.abs(dd).max()
+    assert abs(beta.grad.item() - db) <= 1e-5 * db
+
+
+def unrolled_grad(lib, b, d, beta, rho, iters, every):
+    import torch
+    dt = T(d, True)
+    bt = torch.tensor(beta, dtype=torch.float64, requires_grad=True)
+    z = lib.unrolled_code(T(b), dt, bt, rho, iters, every)
+    L = lib.csc_loss(T(b), dt, z, bt)
+    L.backward()
+    return L.item(), N(dt.grad), bt.grad.item()
+
+
+def test_gradient_fd_instance_vs_oracle(lib):
+    """2 x 32x32 images, K = 4 filters 11x11, 30 iterations, checkpoint every 5."""
+    cfg = synth.CONFIGS["unrolled_fd"]
+    b, d = synth.make_inputs(cfg)
+    L, gd, gb = unrolled_grad(lib, b, d, cfg.beta, cfg.rho, cfg.t_in, 5)
+    Lr, gdr, gbr = oracle.code_loss_grad(b, d, cfg.beta, cfg.rho, cfg.t_in)
+    scale = max(np.abs(gdr).max(), abs(gbr))
+    assert abs(L - Lr) <= 1e-5 * abs(Lr)
+    assert np.abs(gd - gdr).max() <= GRAD_RTOL * scale, np.abs(gd - gdr).max() / scale
+    assert abs(gb - gbr) <= GRAD_RTOL * scale
+
+
+def test_gradient_larger_instance_vs_oracle(lib):
+    rng = np.random.default_rng(4)
+    b = np.stack([synth.contrast_normalize(synth.one_over_f(rng, (64, 64)))[None] * 30 for _ in range(2)])
+    d = synth.unit_filters(8, 1, (11, 11), 77)
+    L, gd, gb = unrolled_grad(lib, b, d, 1.0, 10.0, 10, 4)
+    Lr, gdr, gbr = oracle.code_loss_grad(b, d, 1.0, 10.0, 10)
+    scale = max(np.abs(gdr).max(), abs(gbr))
+    assert np.abs(gd - gdr).max() <= GRAD_RTOL * scale
+    assert abs(gb - gbr) <= GRAD_RTOL * scale
+
+
+def test_checkpoint_interval_does_not_change_gradient(lib):
+    cfg = synth.CONFIGS["unrolled_fd"]
+    b, d = synth.make_inputs(cfg)
+    ref = unrolled_grad(lib, b, d, cfg.beta, cfg.rho, 12, 1)
+    for every in (3, 5, 12):
+        got = unrolled_grad(lib, b, d, cfg.beta, cfg.rho, 12, every)
+        assert np.array_equal(got[1], ref[1]) and got[2] == ref[2], every
+
+
+def test_zero_iterations(lib):
+    import torch
+    cfg = synth.CONFIGS["unrolled_fd"]
+    b, d = synth.make_inputs(cfg)
+    dt = T(d, True)
+    z = lib.unrolled_code(T(b), dt, 1.0, 10.0, 0, 5)
+    assert torch.count_nonzero(z).item() == 0
+    L = lib.csc_loss(T(b), dt, z, 1.0)
+    L.backward()
+    assert torch.count_nonzero(dt.grad).item() == 0

@@ -470,3 +470,73 @@ def test_gradient_tensor_matches_finite_differences():
         assert abs(fd - gd[idx]) <= 1e-6 * scale
     fd_b = (loss(d, beta + h) - loss(d, beta - h)) / (2 * h)
     assert abs(fd_b - gb) <= 1e-6 * scale
+
+
+def test_objective_grad_finite_differences():
+    rng = np.random.default_rng(3)
+    grid, fs, K, J = (8, 8), (3, 3), 3, 2
+    d = rand_filters(K, J, fs, rng)
+    z = rng.standard_normal((2, K) + grid) * (rng.random((2, K) + grid) < 0.4)
+    b = rng.standard_normal((2, J) + grid)
+    beta = 0.6
+    f, dz, dd, db = oracle.objective_grad(b, d, z, beta)
+    assert abs(f - oracle.objective(b, d, z, beta)[1]) < 1e-12 * abs(f)
+    h = 1e-6
+    for idx in [(0, 0, 0, 0), (1, 1, 2, 1), (2, 0, 1, 2)]:
+        dp = d.copy(); dp[idx] += h
+        dm = d.copy(); dm[idx] -= h
+        fd = (oracle.objective(b, dp, z, beta)[1] - oracle.objective(b, dm, z, beta)[1]) / (2 * h)
+        assert abs(fd - dd[idx]) < 1e-6 * max(1.0, abs(fd))
+    nz = np.argwhere(z != 0)
+    for idx in [tuple(nz[0]), tuple(nz[5])]:
+        zp = z.copy(); zp[idx] += h
+        zm = z.copy(); zm[idx] -= h
+        fd = (oracle.objective(b, d, zp, beta)[1] - oracle.objective(b, d, zm, beta)[1]) / (2 * h)
+        assert abs(fd - dz[idx]) < 1e-6 * max(1.0, abs(fd))
+    assert db == np.abs(z).sum()
+
+
+@pytest.mark.slow
+def test_gradient_fd_on_unrolled_instance():
+    """The unrolled-coding FD instance (2 x 32x32 images, K = 4 11x11 filters,
+    30 iterations, rho = 10, beta = 1): oracle reverse pass vs FP64 central
+    differences on a subset of taps and beta."""
+    import synth
+    cfg = synth.CONFIGS["unrolled_fd"]
+    b, d = synth.make_inputs(cfg)
+    b = b.astype(np.float64)
+    d = d.astype(np.float64)
+    # every clip argument keeps a margin far above the FD perturbation
+    from oracle.csc import _dual_solve, _fft, _gram, _ifft_real, filter_spectra
+    dh = filter_spectra(d, b.shape[2:])
+    G = _gram(dh)
+    xh = _fft(b, 2)
+    z = np.zeros((b.shape[0], cfg.k) + b.shape[2:])
+    th = np.zeros_like(z)
+    margin = np.inf
+    for _ in range(cfg.t_in):
+        rhs = np.einsum("jk...,nk...->nj...", dh, _fft(th + z / cfg.rho, 2)) - xh / cfg.rho
+        lam = _dual_solve(G, rhs, np.full(b.shape[0], cfg.rho))
+        v = _ifft_real(np.einsum("jk...,nj...->nk...", np.conj(dh), lam), 2)
+        u = v - z / cfg.rho
+        margin = min(margin, np.min(np.abs(np.abs(u) - cfg.beta)))
+        th = np.clip(u, -cfg.beta, cfg.beta)
+        z = z + cfg.rho * (th - v)
+    assert margin > 1e-6
+    L, gd, gb = oracle.code_loss_grad(b, d, cfg.beta, cfg.rho, cfg.t_in)
+
+    def loss(dd, bb):
+        zz = oracle.code(b, dd, bb, cfg.rho, cfg.t_in)["z"]
+        return oracle.objective(b, dd, zz, bb)[1]
+
+    h = 1e-7
+    scale = max(np.abs(gd).max(), abs(gb))
+    rng = np.random.default_rng(0)
+    for _ in range(10):
+        idx = (int(rng.integers(cfg.k)), 0, int(rng.integers(11)), int(rng.integers(11)))
+        dp = d.copy(); dp[idx] += h
+        dm = d.copy(); dm[idx] -= h
+        fd = (loss(dp, cfg.beta) - loss(dm, cfg.beta)) / (2 * h)
+        assert abs(fd - gd[idx]) <= 1e-6 * scale, (idx, fd, gd[idx])
+    fd_b = (loss(d, cfg.beta + h) - loss(d, cfg.beta - h)) / (2 * h)
+    assert abs(fd_b - gb) <= 1e-6 * scale
