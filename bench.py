@@ -88,6 +88,51 @@ def bench_batched(dc, synth, np, torch, n_images):
     }
 
 
+def bench_backward(dc, synth, np, torch, reps=2):
+    """Differentiable form: N = 16 images 256x256, K = 100 filters 11x11,
+    30 unrolled ADMM iterations with checkpoints every 5, loss of eq:CSC;
+    forward + backward (gradients w.r.t. filters and beta) against the plain
+    solver (csc_code, 30 iterations) on the same inputs."""
+    cfg = synth.CONFIGS["unrolled"]
+    b, d0 = synth.make_inputs(cfg)
+    dev = torch.device("cuda:0")
+    bt = torch.from_numpy(b).to(dev)
+    d = torch.from_numpy(d0).to(dev)
+    beta = torch.tensor(cfg.beta, dtype=torch.float64, requires_grad=True)
+
+    def fwd_bwd():
+        dd = d.clone().requires_grad_(True)
+        z = dc.unrolled_code(bt, dd, beta, cfg.rho, cfg.t_in, 5)
+        L = dc.csc_loss(bt, dd, z, beta)
+        L.backward()
+        return L
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    ms_plain = timed(lambda: dc.code(bt, d, cfg.beta, cfg.rho, cfg.t_in), reps)
+    ms_fwd = timed(lambda: dc.unrolled_code(bt, d, cfg.beta, cfg.rho, cfg.t_in, 5), reps)
+    ms_fb = timed(fwd_bwd, reps)
+    cpit = cfg.n * cfg.k * cfg.grid[0] * cfg.grid[1] * cfg.t_in
+    return {
+        "workload": "N=16 images 256x256, K=100 11x11, beta=1, rho=10, 30 unrolled iterations, checkpoint every 5",
+        "plain_code_ms": ms_plain,
+        "unrolled_forward_ms": ms_fwd,
+        "forward_backward_ms": ms_fb,
+        "backward_ms": ms_fb - ms_fwd,
+        "plain_cp_it_per_s": cpit / (ms_plain / 1e3),
+        "forward_backward_vs_plain": ms_fb / ms_plain,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +141,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-images", type=int, default=2)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--batched-images", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -221,6 +267,8 @@ def main():
 
     if not args.no_batched:
         out["batched"] = bench_batched(dc, synth, np, torch, args.batched_images)
+    if not args.no_backward:
+        out["backward"] = bench_backward(dc, synth, np, torch)
 
     if not args.no_cpu_baseline:
         import oracle
