@@ -63,7 +63,11 @@ extern "C" {
 #define CSC_Z_ZERO 0x2u       /* csc_code: start from z = 0 (z is output only) */
 #define CSC_THETA_ZERO 0x4u   /* csc_code: start from theta = 0 (theta output only) */
 #define CSC_GAMMA_ZERO 0x8u   /* csc_learn: start from gamma = 0 (gamma output only) */
-#define CSC_USE_GRAPH 0x10u   /* csc_code_batched: capture once into a hipGraph, then replay */
+#define CSC_USE_GRAPH 0x10u   /* csc_code, csc_learn, csc_code_batched: capture the call
+                                 once into a hipGraph, replay it on later calls with
+                                 identical arguments (pointers, sizes, scalars, stream);
+                                 ignored on the NULL stream.  Buffer contents may change
+                                 between replays, pointers may not. */
 
 typedef struct csc_shape {
   int32_t abi_version; /* must equal CSC_ABI_VERSION */
@@ -105,8 +109,9 @@ size_t csc_workspace_bytes(const csc_shape* shape, int op, unsigned flags);
  *          CSC_THETA_ZERO the input contents are ignored.
  *   resid  NULL or [iters][N][3] float64: r_pri = ||theta' - D^T lambda'||,
  *          r_dual = rho ||D (theta' - theta)||, and the rho used.
- *   Errors: CSC_EINVAL for a bad shape, beta < 0, iters < 0, NULL b/d/rho/z;
- *           CSC_EWORKSPACE; CSC_EHIP.
+ *   flags  CSC_ADAPTIVE_RHO, CSC_Z_ZERO, CSC_THETA_ZERO, CSC_USE_GRAPH.
+ *   Errors: CSC_EINVAL for a bad shape, beta < 0, iters < 0, NULL b/d/rho/z,
+ *           unknown flags; CSC_EWORKSPACE; CSC_EHIP.
  */
 int csc_code(const csc_shape* shape, const float* b, const float* d, float beta,
              float* rho, int iters, unsigned flags, float* z, float* theta,
@@ -128,6 +133,7 @@ int csc_code(const csc_shape* shape, const float* b, const float* d, float beta,
  *   mu     [K] in/out multipliers (> 0 on entry).
  *   gamma  [N][J][grid] in/out dual variable (warm start unless
  *          CSC_GAMMA_ZERO).
+ *   flags  CSC_GAMMA_ZERO, CSC_USE_GRAPH.
  *   Errors: CSC_EINVAL for a bad shape, inner_iters < 1, cg_iters < 0, NULL
  *           pointers; CSC_EWORKSPACE; CSC_EHIP.
  */

@@ -162,7 +162,7 @@ def _workspace(shape: Shape, op: int, flags: int, device):
         _check(EINVAL)
     key = (str(device), op)
     buf = _WS.get(key)
-    if buf is None or buf.numel() < nbytes:
+    if buf is None or buf.numel() < nbytes + 256:
         buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
         _WS[key] = buf
     base = buf.data_ptr()
@@ -186,8 +186,39 @@ def _shape_of(b, d) -> Shape:
     return Shape.make(b.shape[0], b.shape[1], d.shape[0], tuple(b.shape[2:]), tuple(d.shape[2:2 + nd]))
 
 
+class _GraphStream:
+    """Runs a library call on a non-default stream (graph capture is not
+    possible on the NULL stream), ordered after and before the current one."""
+
+    def __init__(self, enabled: bool):
+        self.enabled = enabled
+
+    def __enter__(self):
+        torch = _torch()
+        self.cur = torch.cuda.current_stream()
+        if not self.enabled:
+            return self.cur.cuda_stream
+        global _SIDE_STREAM
+        if self.cur.cuda_stream != 0:
+            self.side = None
+            return self.cur.cuda_stream
+        if _SIDE_STREAM is None:
+            _SIDE_STREAM = torch.cuda.Stream()
+        self.side = _SIDE_STREAM
+        self.side.wait_stream(self.cur)
+        return self.side.cuda_stream
+
+    def __exit__(self, *exc):
+        if self.enabled and self.side is not None:
+            self.cur.wait_stream(self.side)
+        return False
+
+
+_SIDE_STREAM = None
+
+
 def code(b, d, beta: float, rho, iters: int, z=None, theta=None, adaptive: bool = False,
-         want_theta: bool = False, want_resid: bool = False):
+         want_theta: bool = False, want_resid: bool = False, graph: bool = False):
     """ADMM coding (eq:Inference_solution) for ``iters`` iterations.
 
     b [N][J][*grid], d [K][J][*fsupp]; rho: float or [N] tensor (updated in
@@ -218,16 +249,20 @@ def code(b, d, beta: float, rho, iters: int, z=None, theta=None, adaptive: bool 
     _need(rho_t, "rho")
     resid = torch.empty((iters, N, 3), dtype=torch.float64, device=dev) if (want_resid and iters > 0) else None
     ws, nbytes = _workspace(shape, OP_CODE, flags, dev)
-    rc = lib.csc_code(ctypes.byref(shape), _ptr(b), _ptr(d), float(beta), _ptr(rho_t), int(iters), flags,
-                      _ptr(z), _ptr(theta), _ptr(resid), ws, nbytes, _stream())
+    with _GraphStream(graph) as st:
+        rc = lib.csc_code(ctypes.byref(shape), _ptr(b), _ptr(d), float(beta), _ptr(rho_t), int(iters),
+                          flags | (USE_GRAPH if graph else 0), _ptr(z), _ptr(theta), _ptr(resid), ws, nbytes, st)
     _check(rc)
     return z, theta, resid, rho_t
 
 
-def learn(b, z, fsupp: Sequence[int], mu=None, gamma=None, inner_iters: int = 10, cg_iters: int = 10):
+def learn(b, z, fsupp: Sequence[int], mu=None, gamma=None, inner_iters: int = 10, cg_iters: int = 10,
+          out=None, graph: bool = False):
     """Dual dictionary learning (eq:Learning_gamma, eq:Learning_Solution,
     eq:mu_update).  Returns (d [K][J][*fsupp], mu [K], gamma [N][J][*grid]);
-    mu and gamma are updated in place when given."""
+    mu and gamma are updated in place when given; ``out`` receives d.  With
+    ``graph`` the call is captured once and replayed when called again with
+    the same tensors."""
     torch = _torch()
     lib = load()
     _need(b, "b")
@@ -244,10 +279,12 @@ def learn(b, z, fsupp: Sequence[int], mu=None, gamma=None, inner_iters: int = 10
         flags |= GAMMA_ZERO
     _need(mu, "mu")
     _need(gamma, "gamma")
-    d = torch.empty((K, J) + fsupp, dtype=torch.float32, device=dev)
+    d = out if out is not None else torch.empty((K, J) + fsupp, dtype=torch.float32, device=dev)
+    _need(d, "out")
     ws, nbytes = _workspace(shape, OP_LEARN, flags, dev)
-    rc = lib.csc_learn(ctypes.byref(shape), _ptr(b), _ptr(z), _ptr(d), _ptr(mu), _ptr(gamma), int(inner_iters),
-                       int(cg_iters), flags, ws, nbytes, _stream())
+    with _GraphStream(graph) as st:
+        rc = lib.csc_learn(ctypes.byref(shape), _ptr(b), _ptr(z), _ptr(d), _ptr(mu), _ptr(gamma),
+                           int(inner_iters), int(cg_iters), flags | (USE_GRAPH if graph else 0), ws, nbytes, st)
     _check(rc)
     return d, mu, gamma
 

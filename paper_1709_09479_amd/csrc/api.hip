@@ -2,6 +2,7 @@
 // planning, workspace sizing and dispatch to the coding / learning paths.
 #include <string.h>
 
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -86,6 +87,52 @@ static int check_ws(void* ws, size_t have, size_t need) {
   if (need == 0) return CSC_OK;
   if (!ws || have < need || (reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return CSC_EWORKSPACE;
   return CSC_OK;
+}
+
+// ------------------------------------------------------------ hipGraphs
+
+namespace {
+std::mutex g_graph_mu;
+std::map<std::vector<int64_t>, hipGraphExec_t> g_graph_cache;
+}  // namespace
+
+int graph_call(const std::vector<int64_t>& key, hipStream_t st, int (*enqueue)(void*), void* ctx) {
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  auto it = g_graph_cache.find(key);
+  if (it == g_graph_cache.end()) {
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return CSC_EHIP;
+    const int rc = enqueue(ctx);
+    const hipError_t ec = hipStreamEndCapture(st, &graph);
+    if (rc != CSC_OK || ec != hipSuccess) {
+      if (graph) hipGraphDestroy(graph);
+      return rc != CSC_OK ? rc : CSC_EHIP;
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (ei != hipSuccess) return CSC_EHIP;
+    if (g_graph_cache.size() >= 32) {
+      hipGraphExecDestroy(g_graph_cache.begin()->second);
+      g_graph_cache.erase(g_graph_cache.begin());
+    }
+    it = g_graph_cache.emplace(key, exec).first;
+  }
+  return hipGraphLaunch(it->second, st) == hipSuccess ? CSC_OK : CSC_EHIP;
+}
+
+static int64_t fbits(float v) {
+  uint32_t u;
+  memcpy(&u, &v, 4);
+  return u;
+}
+static int64_t pbits(const void* p) { return (int64_t)(uintptr_t)p; }
+
+static void shape_key(std::vector<int64_t>& k, const csc_shape* s) {
+  int dev = 0;
+  hipGetDevice(&dev);
+  k.insert(k.end(), {dev, s->n, s->j, s->k, s->ndim, s->grid[0], s->grid[1], s->grid[2], s->fsupp[0], s->fsupp[1],
+                     s->fsupp[2]});
 }
 
 // ------------------------------------------------------------- tracing
@@ -187,9 +234,35 @@ int csc_code(const csc_shape* shape, const float* b, const float* d, float beta,
   int rc = make_plan(shape, &pl);
   if (rc != CSC_OK) return rc;
   if (!b || !d || !rho || !z || iters < 0 || !(beta >= 0.0f)) return CSC_EINVAL;
-  if (flags & ~(CSC_ADAPTIVE_RHO | CSC_Z_ZERO | CSC_THETA_ZERO)) return CSC_EINVAL;
+  if (flags & ~(CSC_ADAPTIVE_RHO | CSC_Z_ZERO | CSC_THETA_ZERO | CSC_USE_GRAPH)) return CSC_EINVAL;
   if ((rc = check_ws(ws, ws_bytes, run_code_ws(pl))) != CSC_OK) return rc;
-  return run_code(pl, b, d, beta, rho, iters, flags, z, theta, resid, ws, static_cast<hipStream_t>(stream));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const unsigned f = flags & ~CSC_USE_GRAPH;
+  if (!(flags & CSC_USE_GRAPH) || st == nullptr)
+    return run_code(pl, b, d, beta, rho, iters, f, z, theta, resid, ws, st);
+  struct Ctx {
+    Plan* pl;
+    const float *b, *d;
+    float beta;
+    float* rho;
+    int iters;
+    unsigned f;
+    float *z, *theta;
+    double* resid;
+    void* ws;
+    hipStream_t st;
+  } c{&pl, b, d, beta, rho, iters, f, z, theta, resid, ws, st};
+  std::vector<int64_t> key{1};
+  shape_key(key, shape);
+  key.insert(key.end(), {pbits(b), pbits(d), fbits(beta), pbits(rho), iters, (int64_t)f, pbits(z), pbits(theta),
+                         pbits(resid), pbits(ws), (int64_t)ws_bytes, pbits(st)});
+  return graph_call(key, st,
+                    [](void* p) -> int {
+                      Ctx* c = static_cast<Ctx*>(p);
+                      return run_code(*c->pl, c->b, c->d, c->beta, c->rho, c->iters, c->f, c->z, c->theta, c->resid,
+                                      c->ws, c->st);
+                    },
+                    &c);
 }
 
 int csc_learn(const csc_shape* shape, const float* b, const float* z, float* d, float* mu, float* gamma,
@@ -198,9 +271,31 @@ int csc_learn(const csc_shape* shape, const float* b, const float* z, float* d, 
   int rc = make_plan(shape, &pl);
   if (rc != CSC_OK) return rc;
   if (!b || !z || !d || !mu || !gamma || inner_iters < 1 || cg_iters < 0) return CSC_EINVAL;
-  if (flags & ~CSC_GAMMA_ZERO) return CSC_EINVAL;
+  if (flags & ~(CSC_GAMMA_ZERO | CSC_USE_GRAPH)) return CSC_EINVAL;
   if ((rc = check_ws(ws, ws_bytes, run_learn_ws(pl))) != CSC_OK) return rc;
-  return run_learn(pl, b, z, d, mu, gamma, inner_iters, cg_iters, flags, ws, static_cast<hipStream_t>(stream));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const unsigned f = flags & ~CSC_USE_GRAPH;
+  if (!(flags & CSC_USE_GRAPH) || st == nullptr)
+    return run_learn(pl, b, z, d, mu, gamma, inner_iters, cg_iters, f, ws, st);
+  struct Ctx {
+    Plan* pl;
+    const float *b, *z;
+    float *d, *mu, *gamma;
+    int li, ci;
+    unsigned f;
+    void* ws;
+    hipStream_t st;
+  } c{&pl, b, z, d, mu, gamma, inner_iters, cg_iters, f, ws, st};
+  std::vector<int64_t> key{2};
+  shape_key(key, shape);
+  key.insert(key.end(), {pbits(b), pbits(z), pbits(d), pbits(mu), pbits(gamma), inner_iters, cg_iters, (int64_t)f,
+                         pbits(ws), (int64_t)ws_bytes, pbits(st)});
+  return graph_call(key, st,
+                    [](void* p) -> int {
+                      Ctx* c = static_cast<Ctx*>(p);
+                      return run_learn(*c->pl, c->b, c->z, c->d, c->mu, c->gamma, c->li, c->ci, c->f, c->ws, c->st);
+                    },
+                    &c);
 }
 
 size_t csc_unrolled_workspace_bytes(const csc_shape* shape, int every) {

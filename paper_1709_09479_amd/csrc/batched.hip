@@ -138,34 +138,51 @@ static int enqueue_batch(const BatchPlan& bp, const csc_batch* bt, const float* 
   return hipGetLastError() == hipSuccess ? CSC_OK : CSC_EHIP;
 }
 
-// -------------------------------------------------------------- graph cache
-
-struct GraphKey {
-  std::vector<int64_t> v;
-  bool operator<(const GraphKey& o) const { return v < o.v; }
+struct BatchCall {
+  const BatchPlan* bp;
+  const csc_batch* bt;
+  const float *b, *d;
+  float beta, rho;
+  int iters;
+  unsigned flags;
+  float* z;
+  char* ws;
+  hipStream_t st;
 };
 
-static std::mutex g_graph_mu;
-static std::map<GraphKey, hipGraphExec_t> g_graphs;
+static int enqueue_batch_ctx(void* p) {
+  BatchCall* c = static_cast<BatchCall*>(p);
+  return enqueue_batch(*c->bp, c->bt, c->b, c->d, c->beta, c->rho, c->iters, c->flags, c->z, c->ws, c->st);
+}
 
-static GraphKey make_key(const csc_batch* bt, const float* b, const float* d, float beta, float rho, int iters,
-                         unsigned flags, float* z, void* ws, size_t ws_bytes, hipStream_t st) {
-  GraphKey k;
+static std::vector<int64_t> batch_key(const csc_batch* bt, const float* b, const float* d, float beta, float rho,
+                                      int iters, unsigned flags, float* z, void* ws, size_t ws_bytes,
+                                      hipStream_t st) {
   int dev = 0;
   hipGetDevice(&dev);
   uint32_t bb, rr;
   memcpy(&bb, &beta, 4);
   memcpy(&rr, &rho, 4);
-  k.v = {dev, (int64_t)(uintptr_t)b, (int64_t)(uintptr_t)d, (int64_t)(uintptr_t)z, (int64_t)(uintptr_t)ws,
-         (int64_t)ws_bytes, (int64_t)(uintptr_t)st, bb, rr, iters, (int64_t)flags, bt->n, bt->k, bt->fsupp[0],
-         bt->fsupp[1]};
+  std::vector<int64_t> k = {3, dev, (int64_t)(uintptr_t)b, (int64_t)(uintptr_t)d, (int64_t)(uintptr_t)z,
+                            (int64_t)(uintptr_t)ws, (int64_t)ws_bytes, (int64_t)(uintptr_t)st, bb, rr, iters,
+                            (int64_t)flags, bt->n, bt->k, bt->fsupp[0], bt->fsupp[1]};
   for (int i = 0; i < bt->n; ++i) {
-    k.v.push_back(bt->grid[2 * i]);
-    k.v.push_back(bt->grid[2 * i + 1]);
-    k.v.push_back(bt->b_off[i]);
-    k.v.push_back(bt->z_off[i]);
+    k.push_back(bt->grid[2 * i]);
+    k.push_back(bt->grid[2 * i + 1]);
+    k.push_back(bt->b_off[i]);
+    k.push_back(bt->z_off[i]);
   }
-  k.v.push_back(bt->ppg ? 1 : 0);
+  if (bt->ppg) {
+    // one entry per class
+    int ncls = 0;
+    {
+      BatchPlan tmp;
+      if (plan_batch(bt, &tmp) == CSC_OK) ncls = (int)tmp.cls.size();
+    }
+    for (int c = 0; c < ncls; ++c) k.push_back(bt->ppg[c]);
+  } else {
+    k.push_back(-1);
+  }
   return k;
 }
 
@@ -207,29 +224,9 @@ int csc_code_batched(const csc_batch* batch, const float* b, const float* d, flo
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (!(flags & CSC_USE_GRAPH) || st == nullptr)
     return enqueue_batch(bp, batch, b, d, beta, rho, iters, flags, z, static_cast<char*>(ws), st);
-  const GraphKey key = make_key(batch, b, d, beta, rho, iters, flags, z, ws, ws_bytes, st);
-  std::lock_guard<std::mutex> lk(g_graph_mu);
-  auto it = g_graphs.find(key);
-  if (it == g_graphs.end()) {
-    hipGraph_t graph = nullptr;
-    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return CSC_EHIP;
-    rc = enqueue_batch(bp, batch, b, d, beta, rho, iters, flags, z, static_cast<char*>(ws), st);
-    const hipError_t ec = hipStreamEndCapture(st, &graph);
-    if (rc != CSC_OK || ec != hipSuccess) {
-      if (graph) hipGraphDestroy(graph);
-      return rc != CSC_OK ? rc : CSC_EHIP;
-    }
-    hipGraphExec_t exec = nullptr;
-    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
-    if (ei != hipSuccess) return CSC_EHIP;
-    if (g_graphs.size() >= 16) {
-      hipGraphExecDestroy(g_graphs.begin()->second);
-      g_graphs.erase(g_graphs.begin());
-    }
-    it = g_graphs.emplace(key, exec).first;
-  }
-  return hipGraphLaunch(it->second, st) == hipSuccess ? CSC_OK : CSC_EHIP;
+  BatchCall call{&bp, batch, b, d, beta, rho, iters, flags & ~CSC_USE_GRAPH, z, static_cast<char*>(ws), st};
+  return graph_call(batch_key(batch, b, d, beta, rho, iters, flags, z, ws, ws_bytes, st), st, enqueue_batch_ctx,
+                    &call);
 }
 
 int csc_batch_autotune(const csc_batch* batch, const float* b, const float* d, float beta, float rho, int iters,

@@ -4,6 +4,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/dualcsc.h"
 
 namespace dcsc {
@@ -76,6 +78,11 @@ void launch_make_v(const Plan& pl, const float2* E, const float2* lam, float2* b
 void launch_sym_reduce(const Plan& pl, const float2* part, int ng, float2* dst, hipStream_t st);
 // objective from part (after forward_maps) and l1 partials in w.rpri
 void launch_objective_tail(const Plan& pl, CodeWs& w, float beta, double* out, hipStream_t st);
+
+// hipGraph capture/replay keyed by every argument of a call.  `enqueue`
+// enqueues the call on `st`; the first call with a key captures it, later
+// calls replay the executable graph.  Returns a CSC_* code.
+int graph_call(const std::vector<int64_t>& key, hipStream_t st, int (*enqueue)(void*), void* ctx);
 
 // Launch tracing.  While enabled (csc_trace_enable), a TraceScope brackets
 // the launches made in its lifetime with a pair of HIP events recorded on

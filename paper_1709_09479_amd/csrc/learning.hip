@@ -12,6 +12,8 @@
 // order.  Maps and filters travel in pairs (2p, 2p+1) as the real and
 // imaginary parts of one complex grid; a pair spectrum C unpacks as
 //     zhat_2p(f) = (C(f) + conj(C(-f)))/2,  zhat_2p+1(f) = -i (C(f) - conj(C(-f)))/2.
+#include <algorithm>
+
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -20,6 +22,10 @@ namespace dcsc {
 hipError_t fft_grids(float2* data, int64_t count, const int g[3], int dir, hipStream_t st);
 
 constexpr int kLW = 256;
+
+#ifndef LEARN_PRUNED
+#define LEARN_PRUNED 1
+#endif
 
 static unsigned lblk(int64_t n, int b = kLW) { return (unsigned)((n + b - 1) / b); }
 
@@ -189,6 +195,297 @@ __global__ __launch_bounds__(kLW) void l_passB(const float2* __restrict__ Zh, co
   }
 }
 
+// ------------------------------------- pruned 2-D operator (single frame)
+// With the support S keeping m1 < M1, m2 < M2 (both at most kPruneMax), the
+// projection u = S^T S IDFT(t) / (2 mu) and its DFT need only partial DFTs:
+//   rows    s[f1][m2]  = sum_f2 t[f1][f2] e^{+2 pi i f2 m2 / W}
+//   columns u[m1][m2]  = (1/D) sum_f1 s[f1][m2] e^{+2 pi i f1 m1 / H}, scaled
+//                        by 1/(2 mu_2p) (real part) and 1/(2 mu_2p+1) (imag)
+//   back    r[m1][f2]  = sum_m2 u[m1][m2] e^{-2 pi i f2 m2 / W}
+//           U[f1][f2]  = sum_m1 r[m1][f2] e^{-2 pi i f1 m1 / H}
+// The row stage runs inside pass A and the last stage inside pass B, so the
+// full grids t and U never reach memory.  For real maps the spectrum at -f
+// is the conjugate of that at f: a thread that owns f also produces -f from
+// the same loads.
+
+constexpr int kPruneMax = 16;  // largest support side handled by the pruned path
+
+// exp(sign 2 pi i k / L) from an LDS copy of the 256-entry table
+__device__ __forceinline__ float2 twl(const float2* tw, int k, int L, int sign) {
+  float2 w = tw[(k * (256 / L)) & 255];
+  if (sign > 0) w.y = -w.y;
+  return w;
+}
+
+// Canonical half of an H x W spectrum: rows 0..H/2, and w <= W/2 on the
+// self-mirrored rows 0 and H/2.  fm is the index of -f.
+__device__ __forceinline__ bool canon2(int i, int H, int W, int& f, int& fm) {
+  const int lw = __builtin_ctz(W);
+  const int h = i >> lw, w = i & (W - 1);
+  if (h > H / 2) return false;
+  if ((h == 0 || h == H / 2) && w > W / 2) return false;
+  f = (h << lw) | w;
+  fm = ((((H - h) & (H - 1))) << lw) | ((W - w) & (W - 1));
+  return true;
+}
+
+// Pass A and the row stage.  A workgroup of 256 threads owns R = 256/W
+// canonical rows f1 (and their mirrors H - f1) of one pair p; every thread
+// forms t_k,j = sum_n conj(zhat_k^n) v_j^n at (f1, f2) and, by conjugation,
+// at -(f1, f2), pair-packed as t_2p + i t_2p+1.  The block parks the 2R rows
+// in LDS and evaluates the 2R x M2 row sums with g lanes per output.  S1 is
+// [J][P][H][M2].
+template <int J>
+__global__ __launch_bounds__(256) void l_passA_rows(const float2* __restrict__ Zh, const float2* __restrict__ v,
+                                                    float2* __restrict__ S1, int N, int P, int H, int W, int M2,
+                                                    int g) {
+  __shared__ float2 tw[256];
+  __shared__ float2 ts[512];  // [slot][f2]; slots R..2R-1 hold the mirrored rows
+  load_twiddles(tw);
+  const int lw = __builtin_ctz(W), R = 256 >> lw, D = H * W;
+  const int rs = threadIdx.x >> lw, f2 = threadIdx.x & (W - 1);
+  const int f1 = blockIdx.x * R + rs;
+  const int p = blockIdx.y;
+  const bool act = f1 <= H / 2;
+  const int f = act ? (f1 << lw) | f2 : 0;
+  const int fm = act ? ((((H - f1) & (H - 1))) << lw) | ((W - f2) & (W - 1)) : 0;
+  // v are spectra of real signals, so t(-f) = conj(t(f)) for every filter
+  // and only v(f) is read
+  float2 ta[J], tb[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) ta[j] = tb[j] = make_float2(0.f, 0.f);
+  if (act) {
+    constexpr int U4 = 4;  // images per step, loads issued together
+    for (int n = 0; n < N; n += U4) {
+      float2 zf[U4], zm[U4], x[U4][J];
+#pragma unroll
+      for (int u = 0; u < U4; ++u) {
+        zf[u] = zm[u] = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int j = 0; j < J; ++j) x[u][j] = make_float2(0.f, 0.f);
+        if (n + u < N) {
+          const float2* zp = Zh + (int64_t(n + u) * P + p) * D;
+          zf[u] = zp[f];
+          zm[u] = zp[fm];
+#pragma unroll
+          for (int j = 0; j < J; ++j) x[u][j] = v[(int64_t(n + u) * J + j) * D + f];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U4; ++u) {
+        float2 za, zb;
+        unpack_pair(zf[u], zm[u], za, zb);
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+          ta[j] = cadd(ta[j], cmulc(x[u][j], za));
+          tb[j] = cadd(tb[j], cmulc(x[u][j], zb));
+        }
+      }
+    }
+  }
+  const int O = 2 * R * M2, lanes = g, l = threadIdx.x & (g - 1);
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    ts[rs * W + f2] = act ? make_float2(ta[j].x - tb[j].y, ta[j].y + tb[j].x) : make_float2(0.f, 0.f);
+    ts[(R + rs) * W + ((W - f2) & (W - 1))] =
+        act ? make_float2(ta[j].x + tb[j].y, tb[j].x - ta[j].y) : make_float2(0.f, 0.f);
+    __syncthreads();
+    // every output slot o = (row slot, m2) takes g lanes, each summing every g-th f2
+    for (int ob = threadIdx.x / lanes; ob - threadIdx.x / lanes < O; ob += 256 / lanes) {
+      const int o = ob < O ? ob : O - 1;
+      const int slot = o / M2, m2 = o % M2;
+      float2 acc = make_float2(0.f, 0.f);
+      for (int c = l; c < W; c += lanes) acc = cadd(acc, cmul(ts[slot * W + c], twl(tw, (c * m2) & (W - 1), W, +1)));
+      for (int off = lanes >> 1; off > 0; off >>= 1) {
+        acc.x += __shfl_down(acc.x, off, lanes);
+        acc.y += __shfl_down(acc.y, off, lanes);
+      }
+      const int r1 = blockIdx.x * R + (slot < R ? slot : slot - R);
+      const bool keep = ob < O && l == 0 && r1 <= H / 2 && !(slot >= R && (r1 == 0 || r1 == H / 2));
+      if (keep) {
+        const int row = slot < R ? r1 : H - r1;
+        S1[((int64_t(j) * P + p) * H + row) * M2 + m2] = acc;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Column and back-row stages for `cr` rows m1 of one (pair, channel):
+// R3[j][p][m1][f2].
+__global__ __launch_bounds__(256) void l_prune_mid(const float2* __restrict__ S1, float2* __restrict__ R3,
+                                                   const float* __restrict__ mu, int K, int P, int H, int W, int M1,
+                                                   int M2, int cr, int g) {
+  __shared__ float2 tw[256];
+  __shared__ float2 s[256 * kPruneMax];
+  __shared__ float2 u[kPruneMax * kPruneMax];
+  const int p = blockIdx.x, j = blockIdx.y, m0 = blockIdx.z * cr;
+  const int rows = min(cr, M1 - m0);
+  load_twiddles(tw);
+  const float2* s_g = S1 + (int64_t(j) * P + p) * H * M2;
+  for (int i = threadIdx.x; i < H * M2; i += blockDim.x) s[i] = s_g[i];
+  __syncthreads();
+  const float invD = 1.0f / (float)(H * W);
+  const float sa = invD / (2.0f * mu[2 * p]);
+  const float sb = (2 * p + 1 < K) ? invD / (2.0f * mu[2 * p + 1]) : 0.f;
+  // columns: u[m1][m2] = (1/D) sum_f1 s[f1][m2] e^{+2 pi i f1 m1 / H}, scaled
+  const int O = rows * M2, l = threadIdx.x & (g - 1);
+  for (int ob = threadIdx.x / g; ob - threadIdx.x / g < O; ob += 256 / g) {
+    const int o = ob < O ? ob : O - 1;
+    const int m1 = m0 + o / M2, m2 = o % M2;
+    float2 acc = make_float2(0.f, 0.f);
+    for (int f1 = l; f1 < H; f1 += g) acc = cadd(acc, cmul(s[f1 * M2 + m2], twl(tw, (f1 * m1) & (H - 1), H, +1)));
+    for (int off = g >> 1; off > 0; off >>= 1) {
+      acc.x += __shfl_down(acc.x, off, g);
+      acc.y += __shfl_down(acc.y, off, g);
+    }
+    if (ob < O && l == 0) u[o] = make_float2(acc.x * sa, acc.y * sb);
+  }
+  __syncthreads();
+  // back rows: r[m1][f2] = sum_m2 u[m1][m2] e^{-2 pi i f2 m2 / W}
+  float2* r_g = R3 + ((int64_t(j) * P + p) * M1 + m0) * W;
+  for (int q = threadIdx.x; q < rows * W; q += blockDim.x) {
+    const int r = q / W, f2 = q % W;
+    float2 a = make_float2(0.f, 0.f);
+    for (int m2 = 0; m2 < M2; ++m2) a = cadd(a, cmul(u[r * M2 + m2], twl(tw, (f2 * m2) & (W - 1), W, -1)));
+    r_g[q] = a;
+  }
+}
+
+// Last stage at the canonical frequencies: Uc[j][p][i] = (U_2p, U_2p+1) at
+// the canonical frequency i (pair unpacked), U(f) = sum_m1 r[m1][f2]
+// e^{-2 pi i f1 m1 / H}.  A workgroup stages r = R3[j][p] in LDS and covers
+// `cpb` canonical indices.
+__global__ __launch_bounds__(256) void l_prune_cols(const float2* __restrict__ R3, float4* __restrict__ Uc, int P,
+                                                    int H, int W, int M1, int cpb) {
+  __shared__ float2 tw[256];
+  __shared__ float2 r[kPruneMax * 256];
+  const int p = blockIdx.y, j = blockIdx.z, nc = (H / 2 + 1) * W;
+  load_twiddles(tw);
+  const float2* r_g = R3 + (int64_t(j) * P + p) * M1 * W;
+  for (int i = threadIdx.x; i < M1 * W; i += 256) r[i] = r_g[i];
+  __syncthreads();
+  const int lw = __builtin_ctz(W);
+  float4* out = Uc + (int64_t(j) * P + p) * nc;
+  const int i1 = min(nc, (int)(blockIdx.x + 1) * cpb);
+  for (int i = blockIdx.x * cpb + threadIdx.x; i < i1; i += 256) {
+    int f, fm;
+    if (!canon2(i, H, W, f, fm)) continue;
+    const int f1 = f >> lw, f2 = f & (W - 1), f2m = (W - f2) & (W - 1);
+    float2 a = make_float2(0.f, 0.f), am = make_float2(0.f, 0.f);
+    for (int m1 = 0; m1 < M1; ++m1) {
+      const float2 w = twl(tw, (f1 * m1) & (H - 1), H, -1);  // at -f: conj(w)
+      a = cadd(a, cmul(r[m1 * W + f2], w));
+      am = cadd(am, cmulc(r[m1 * W + f2m], w));
+    }
+    float2 ua, ub;
+    unpack_pair(a, am, ua, ub);
+    out[i] = make_float4(ua.x, ua.y, ub.x, ub.y);
+  }
+}
+
+// Pass B on the canonical half.  A workgroup of kBW wavefronts owns 64
+// canonical frequencies and a chunk of `nbc` images; wavefront w sums the
+// pairs p in [w P / kBW, (w+1) P / kBW).  The wavefront partials meet in LDS
+// and are added in a fixed order:
+//   q^n_j = v^n_j + sum_p (zhat_2p^n U_2p,j + zhat_2p+1^n U_2p+1,j)
+// and the value at -f is the conjugate (real maps, real u).  With xh, q
+// becomes -x - q.  Dot partials (sum over the block's frequencies of
+// Re(v conj q), or |q|^2 with xh, over the block's images) go to
+// dots[j nblk + block] with nblk = gridDim.x gridDim.y.
+constexpr int kBW = 8;
+
+template <int J>
+constexpr int passb_nb() {
+  return J == 1 ? 8 : (J == 2 ? 4 : 2);
+}
+
+template <int J>
+__global__ __launch_bounds__(64 * kBW) void l_passB_c(const float2* __restrict__ Zh, const float4* __restrict__ Uc,
+                                                      const float2* __restrict__ v, float2* __restrict__ q,
+                                                      const float2* __restrict__ xh, double* __restrict__ dots, int N,
+                                                      int P, int H, int W, int nbc) {
+  constexpr int NB = passb_nb<J>(), NI = NB * J;  // items per lane: (image, channel)
+  __shared__ float2 part[kBW][NI][64];
+  __shared__ double wsum[NI];
+  const int D = H * W, nc = (H / 2 + 1) * W;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int n0 = blockIdx.y * nbc, nb = min(nbc, N - n0);
+  const int i = blockIdx.x * 64 + lane;
+  int f = 0, fm = 0;
+  const bool own = canon2(i, H, W, f, fm);
+  float2 acc[NB][J];
+#pragma unroll
+  for (int u = 0; u < NB; ++u)
+#pragma unroll
+    for (int j = 0; j < J; ++j) acc[u][j] = make_float2(0.f, 0.f);
+  const int p0 = (wv * P) / kBW, p1 = ((wv + 1) * P) / kBW;
+  if (own) {
+    for (int p = p0; p < p1; ++p) {
+      const float2* zp = Zh + (int64_t(n0) * P + p) * D;
+      float2 zf[NB], zm[NB];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        zf[u] = zm[u] = make_float2(0.f, 0.f);
+        if (u < nb) {
+          zf[u] = zp[int64_t(u) * P * D + f];
+          zm[u] = zp[int64_t(u) * P * D + fm];
+        }
+      }
+      float4 U[J];
+#pragma unroll
+      for (int j = 0; j < J; ++j) U[j] = Uc[(int64_t(j) * P + p) * nc + i];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        float2 za, zb;
+        unpack_pair(zf[u], zm[u], za, zb);
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+          acc[u][j] = cadd(acc[u][j], cadd(cmul(za, make_float2(U[j].x, U[j].y)), cmul(zb, make_float2(U[j].z, U[j].w))));
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < NB; ++u)
+#pragma unroll
+    for (int j = 0; j < J; ++j) part[wv][u * J + j][lane] = acc[u][j];
+  __syncthreads();
+  const bool self = f == fm;
+  for (int it = wv; it < NI; it += kBW) {
+    const int j = it % J, u = it / J;
+    float2 a = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int w = 0; w < kBW; ++w) a = cadd(a, part[w][it][lane]);
+    double sv = 0.0;
+    if (own && u < nb) {
+      const int64_t base = (int64_t(n0 + u) * J + j) * D;
+      for (int side = 0; side < (self ? 1 : 2); ++side) {
+        const int ff = side ? fm : f;
+        const float2 vv = v[base + ff];
+        float2 qq = cadd(vv, side ? cconj(a) : a);
+        if (xh) {
+          const float2 x = xh[base + ff];
+          qq = make_float2(-x.x - qq.x, -x.y - qq.y);
+          sv += (double)qq.x * qq.x + (double)qq.y * qq.y;
+        } else {
+          sv += (double)vv.x * qq.x + (double)vv.y * qq.y;
+        }
+        q[base + ff] = qq;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) sv += __shfl_down(sv, off, 64);
+    if (lane == 0) wsum[it] = sv;
+  }
+  __syncthreads();
+  if (threadIdx.x < J) {
+    const int j = threadIdx.x;
+    double t = 0.0;
+    for (int u = 0; u < nb; ++u) t += wsum[u * J + j];
+    dots[int64_t(j) * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x] = t;
+  }
+}
+
 // Fixed-order sum of `cnt` partials by one block (all threads get the total).
 __device__ __forceinline__ double sum_partials(const double* __restrict__ p, int cnt, double* red, double* bcast) {
   double s = 0.0;
@@ -315,16 +612,47 @@ __global__ __launch_bounds__(kLW) void l_mu_update(float* __restrict__ d, float*
     else hipLaunchKernelGGL(KERNEL<3>, grid, block, 0, st, __VA_ARGS__);              \
   } while (0)
 
+static bool pruned2d(const Plan& pl) {
+#if LEARN_PRUNED
+  return pl.g[0] == 1 && pl.fs[1] <= kPruneMax && pl.fs[2] <= kPruneMax;
+#else
+  (void)pl;
+  return false;
+#endif
+}
+
+// 64-frequency blocks covering the canonical half of the spectrum
+static unsigned canon_blocks(const Plan& pl) { return lblk(int64_t(pl.g[1] / 2 + 1) * pl.g[2], 64); }
+
+static int pow2_floor(int x) {
+  int r = 1;
+  while (2 * r <= x) r *= 2;
+  return r;
+}
+
+// lanes per output for `outs` outputs of `len`-term sums on 256 threads
+static int lanes_for(int outs, int len) { return std::max(1, std::min(std::min(64, len), pow2_floor(256 / outs))); }
+
+static int passb_nb_host(int J) { return J == 1 ? 8 : (J == 2 ? 4 : 2); }
+static int passb_chunks(const Plan& pl) { return (pl.n + passb_nb_host(pl.j) - 1) / passb_nb_host(pl.j); }
+
+static int dot_parts(const Plan& pl) {
+  return pruned2d(pl) ? (int)canon_blocks(pl) * passb_chunks(pl) : pl.n * (int)lblk(pl.dsz);
+}
+
 struct LearnWs {
-  float2 *Zh, *xh, *gh, *rh, *ph, *qh, *Tp;
-  double *dots, *rr;  // dots: [J][N][nblk]; rr: [cg_slots][J]
-  int npart;
+  float2 *Zh, *xh, *gh, *rh, *ph, *qh, *Tp, *S1, *R3;
+  float4* Uc;   // pruned path: U at the canonical frequencies, pair unpacked
+  double *dots, *rr;  // dots: pass-B partials then residual partials; rr: [4][J]
+  int nB;  // pruned path: pass-B partials per channel (one per workgroup)
+  int npartB, npartS;  // partial counts per channel: pass B, vector-update kernel
 };
 
 static size_t carve_learn(const Plan& pl, void* base, LearnWs* w) {
   Carver c(base);
   const int64_t D = pl.dsz, N = pl.n, J = pl.j, P = pl.p;
-  w->npart = int(N * lblk(D));
+  w->npartB = dot_parts(pl);
+  w->npartS = int(N * lblk(D));
   w->Zh = c.take<float2>(N * P * D);
   w->xh = c.take<float2>(N * J * D);
   w->gh = c.take<float2>(N * J * D);
@@ -332,8 +660,12 @@ static size_t carve_learn(const Plan& pl, void* base, LearnWs* w) {
   w->ph = c.take<float2>(N * J * D);
   w->qh = c.take<float2>(N * J * D);
   w->Tp = c.take<float2>(J * P * D);
-  w->dots = c.take<double>(J * w->npart * 2);
+  w->S1 = c.take<float2>(J * P * int64_t(pl.g[1]) * pl.fs[2]);
+  w->R3 = c.take<float2>(J * P * int64_t(pl.fs[1]) * pl.g[2]);
+  w->Uc = c.take<float4>(J * P * int64_t(pl.g[1] / 2 + 1) * pl.g[2]);
+  w->dots = c.take<double>(J * (int64_t(w->npartB) + std::max(w->npartB, w->npartS)));
   w->rr = c.take<double>(4 * J);
+  w->nB = (int)canon_blocks(pl) * passb_chunks(pl);
   return c.off;
 }
 
@@ -361,11 +693,37 @@ static bool crop_tile_launch(const Plan& pl, float2* Tp, const float* mu, hipStr
   return false;
 }
 
-// Up <- DFT(S^T S IDFT(pass A of v) / (2 mu))
+// ------------------------------------------------ pruned operator (host)
+// U for A v: pass A with the row stage, the column and back-row stages into
+// R3, the last stage into Uc.
+static hipError_t pruned_zt_proj(const Plan& pl, LearnWs& w, const float2* v, const float* mu, hipStream_t st) {
+  const int H = pl.g[1], W = pl.g[2], R = 256 / W, M1 = pl.fs[1], M2 = pl.fs[2];
+  TraceScope trace(kTraceLearnOp, st);
+  LJ(l_passA_rows, pl.j, dim3((H / 2 + R) / R, pl.p), dim3(256), st, w.Zh, v, w.S1, pl.n, pl.p, H, W, M2,
+     lanes_for(2 * R * M2, W));
+  const int cr = 4;
+  hipLaunchKernelGGL(l_prune_mid, dim3(pl.p, pl.j, (M1 + cr - 1) / cr), dim3(256), 0, st, w.S1, w.R3, mu, pl.k, pl.p,
+                     H, W, M1, M2, cr, lanes_for(cr * M2, H));
+  const int nc = (H / 2 + 1) * W, cpb = 512;
+  hipLaunchKernelGGL(l_prune_cols, dim3((nc + cpb - 1) / cpb, pl.p, pl.j), dim3(256), 0, st, w.R3, w.Uc, pl.p, H, W,
+                     M1, cpb);
+  return hipGetLastError();
+}
+
+// q = v + Z U (pass B); with xh: q = -x - (v + Z U).  Partials to `part`
+// ([J][nB]).
+static void pruned_passB(const Plan& pl, LearnWs& w, const float2* v, float2* q, const float2* xh, double* part,
+                         hipStream_t st) {
+  const int chunks = passb_chunks(pl), nbc = (pl.n + chunks - 1) / chunks;
+  LJ(l_passB_c, pl.j, dim3(canon_blocks(pl), chunks), dim3(64 * kBW), st, w.Zh, w.Uc, v, q, xh, part, pl.n, pl.p,
+     pl.g[1], pl.g[2], nbc);
+}
+
+// Up <- DFT(S^T S IDFT(pass A of v) / (2 mu)).
 static hipError_t apply_zt_proj(const Plan& pl, LearnWs& w, const float2* v, const float* mu, hipStream_t st) {
   const int64_t D = pl.dsz;
-  TraceScope trace(kTraceLearnOp, st);
   const int T = pl.g[0], H = pl.g[1], W = pl.g[2];
+  TraceScope trace(kTraceLearnOp, st);
   LJ(l_passA, pl.j, dim3(lblk(D), pl.p), dim3(kLW), st, w.Zh, v, w.Tp, pl.n, pl.p, T, H, W);
   if (crop_tile_launch(pl, w.Tp, mu, st)) return hipGetLastError();
   hipError_t e = fft_grids(w.Tp, int64_t(pl.j) * pl.p, pl.g, +1, st);
@@ -373,6 +731,13 @@ static hipError_t apply_zt_proj(const Plan& pl, LearnWs& w, const float2* v, con
   hipLaunchKernelGGL(l_crop_scale, dim3(lblk(D), pl.p, pl.j), dim3(kLW), 0, st, w.Tp, mu, pl.k, pl.p, T, H, W,
                      pl.fs[0], pl.fs[1], pl.fs[2]);
   return fft_grids(w.Tp, int64_t(pl.j) * pl.p, pl.g, -1, st);
+}
+
+// q = v + Z Up (pass B); with xh: q = -x - (v + Z Up).  Dot partials to dots.
+static void apply_passB(const Plan& pl, LearnWs& w, const float2* v, float2* q, const float2* xh, double* dots,
+                        hipStream_t st) {
+  const int T = pl.g[0], H = pl.g[1], W = pl.g[2];
+  LJ(l_passB, pl.j, dim3(lblk(pl.dsz), pl.n), dim3(kLW), st, w.Zh, w.Tp, v, q, xh, dots, pl.n, pl.p, T, H, W);
 }
 
 int run_learn(const Plan& pl, const float* b, const float* z, float* d, float* mu, float* gamma, int inner_iters,
@@ -394,23 +759,39 @@ int run_learn(const Plan& pl, const float* b, const float* z, float* d, float* m
 
   const dim3 vgrid(lblk(D), pl.n);
   double* pap = w.dots;
-  double* rrp = w.dots + J * w.npart;
+  double* rrp = w.dots + J * w.npartB;
   double* rr_a = w.rr;
   double* rr_b = w.rr + J;
+  const bool pruned = pruned2d(pl);
   for (int it = 0; it < inner_iters; ++it) {
-    // r = -x - A gamma ; p = r ; rr = |r|^2
-    if ((e = apply_zt_proj(pl, w, w.gh, mu, st)) != hipSuccess) return CSC_EHIP;
-    LJ(l_passB, pl.j, vgrid, dim3(kLW), st, w.Zh, w.Tp, w.gh, w.rh, w.xh, rrp, pl.n, pl.p, T, H, W);
-    LJ(l_cg_dir, pl.j, vgrid, dim3(kLW), st, w.ph, w.rh, rr_a, rrp, w.npart, rr_a, 1, D);
-    for (int q = 0; q < cg_iters; ++q) {
-      if ((e = apply_zt_proj(pl, w, w.ph, mu, st)) != hipSuccess) return CSC_EHIP;
-      LJ(l_passB, pl.j, vgrid, dim3(kLW), st, w.Zh, w.Tp, w.ph, w.qh, (const float2*)nullptr, pap, pl.n, pl.p, T, H,
-         W);
-      LJ(l_cg_step, pl.j, vgrid, dim3(kLW), st, w.gh, w.rh, w.ph, w.qh, rr_a, pap, w.npart, rrp, pl.n, D);
-      LJ(l_cg_dir, pl.j, vgrid, dim3(kLW), st, w.ph, w.rh, rr_a, rrp, w.npart, rr_b, 0, D);
-      double* t = rr_a;
-      rr_a = rr_b;
-      rr_b = t;
+    if (pruned) {
+      // r = -x - A gamma ; p = r ; rr = |r|^2
+      if ((e = pruned_zt_proj(pl, w, w.gh, mu, st)) != hipSuccess) return CSC_EHIP;
+      pruned_passB(pl, w, w.gh, w.rh, w.xh, rrp, st);
+      LJ(l_cg_dir, pl.j, vgrid, dim3(kLW), st, w.ph, w.rh, rr_a, rrp, w.nB, rr_a, 1, D);
+      for (int q = 0; q < cg_iters; ++q) {
+        if ((e = pruned_zt_proj(pl, w, w.ph, mu, st)) != hipSuccess) return CSC_EHIP;
+        pruned_passB(pl, w, w.ph, w.qh, nullptr, pap, st);
+        LJ(l_cg_step, pl.j, vgrid, dim3(kLW), st, w.gh, w.rh, w.ph, w.qh, rr_a, pap, w.nB, rrp, pl.n, D);
+        LJ(l_cg_dir, pl.j, vgrid, dim3(kLW), st, w.ph, w.rh, rr_a, rrp, w.npartS, rr_b, 0, D);
+        double* t = rr_a;
+        rr_a = rr_b;
+        rr_b = t;
+      }
+    } else {
+      // r = -x - A gamma ; p = r ; rr = |r|^2
+      if ((e = apply_zt_proj(pl, w, w.gh, mu, st)) != hipSuccess) return CSC_EHIP;
+      apply_passB(pl, w, w.gh, w.rh, w.xh, rrp, st);
+      LJ(l_cg_dir, pl.j, vgrid, dim3(kLW), st, w.ph, w.rh, rr_a, rrp, w.npartB, rr_a, 1, D);
+      for (int q = 0; q < cg_iters; ++q) {
+        if ((e = apply_zt_proj(pl, w, w.ph, mu, st)) != hipSuccess) return CSC_EHIP;
+        apply_passB(pl, w, w.ph, w.qh, nullptr, pap, st);
+        LJ(l_cg_step, pl.j, vgrid, dim3(kLW), st, w.gh, w.rh, w.ph, w.qh, rr_a, pap, w.npartB, rrp, pl.n, D);
+        LJ(l_cg_dir, pl.j, vgrid, dim3(kLW), st, w.ph, w.rh, rr_a, rrp, w.npartS, rr_b, 0, D);
+        double* t = rr_a;
+        rr_a = rr_b;
+        rr_b = t;
+      }
     }
     // d_k = -S Z_k^T gamma / (2 mu_k) ; mu_k <- mu_k ||d_k||
     LJ(l_passA, pl.j, dim3(lblk(D), pl.p), dim3(kLW), st, w.Zh, w.gh, w.Tp, pl.n, pl.p, T, H, W);
