@@ -26,6 +26,21 @@ constexpr int kLW = 256;
 #ifndef LEARN_PRUNED
 #define LEARN_PRUNED 1
 #endif
+#ifndef LEARN_A_U4
+#define LEARN_A_U4 4  // pass A: images whose loads are issued together
+#endif
+#ifndef LEARN_B_NB1
+#define LEARN_B_NB1 10  // pass B: largest image chunk for one channel
+#endif
+#ifndef LEARN_BW
+#define LEARN_BW 16  // pass B: wavefronts per workgroup
+#endif
+#ifndef LEARN_MID_CR
+#define LEARN_MID_CR 2  // column stage: rows m1 per workgroup
+#endif
+#ifndef LEARN_COLS_CPB
+#define LEARN_COLS_CPB 512  // last stage: canonical frequencies per workgroup
+#endif
 
 static unsigned lblk(int64_t n, int b = kLW) { return (unsigned)((n + b - 1) / b); }
 
@@ -255,7 +270,7 @@ __global__ __launch_bounds__(256) void l_passA_rows(const float2* __restrict__ Z
 #pragma unroll
   for (int j = 0; j < J; ++j) ta[j] = tb[j] = make_float2(0.f, 0.f);
   if (act) {
-    constexpr int U4 = 4;  // images per step, loads issued together
+    constexpr int U4 = LEARN_A_U4;
     for (int n = 0; n < N; n += U4) {
       float2 zf[U4], zm[U4], x[U4][J];
 #pragma unroll
@@ -312,10 +327,12 @@ __global__ __launch_bounds__(256) void l_passA_rows(const float2* __restrict__ Z
 }
 
 // Column and back-row stages for `cr` rows m1 of one (pair, channel):
-// R3[j][p][m1][f2].
+// R3[j][p][m1][f2].  With d given, the column stage alone recovers the
+// filters instead (eq:Learning_Solution): d_k,j[m] = -u_k,j[m] for the two
+// filters of the pair, and R3 is not written.
 __global__ __launch_bounds__(256) void l_prune_mid(const float2* __restrict__ S1, float2* __restrict__ R3,
-                                                   const float* __restrict__ mu, int K, int P, int H, int W, int M1,
-                                                   int M2, int cr, int g) {
+                                                   const float* __restrict__ mu, float* __restrict__ d, int K, int J,
+                                                   int P, int H, int W, int M1, int M2, int cr, int g) {
   __shared__ float2 tw[256];
   __shared__ float2 s[256 * kPruneMax];
   __shared__ float2 u[kPruneMax * kPruneMax];
@@ -339,8 +356,17 @@ __global__ __launch_bounds__(256) void l_prune_mid(const float2* __restrict__ S1
       acc.x += __shfl_down(acc.x, off, g);
       acc.y += __shfl_down(acc.y, off, g);
     }
-    if (ob < O && l == 0) u[o] = make_float2(acc.x * sa, acc.y * sb);
+    if (ob < O && l == 0) {
+      if (d) {
+        const int64_t msz = int64_t(M1) * M2, m = int64_t(m1) * M2 + m2;
+        d[(int64_t(2 * p) * J + j) * msz + m] = -acc.x * sa;
+        if (2 * p + 1 < K) d[(int64_t(2 * p + 1) * J + j) * msz + m] = -acc.y * sb;
+      } else {
+        u[o] = make_float2(acc.x * sa, acc.y * sb);
+      }
+    }
   }
+  if (d) return;
   __syncthreads();
   // back rows: r[m1][f2] = sum_m2 u[m1][m2] e^{-2 pi i f2 m2 / W}
   float2* r_g = R3 + ((int64_t(j) * P + p) * M1 + m0) * W;
@@ -393,11 +419,11 @@ __global__ __launch_bounds__(256) void l_prune_cols(const float2* __restrict__ R
 // becomes -x - q.  Dot partials (sum over the block's frequencies of
 // Re(v conj q), or |q|^2 with xh, over the block's images) go to
 // dots[j nblk + block] with nblk = gridDim.x gridDim.y.
-constexpr int kBW = 8;
+constexpr int kBW = LEARN_BW;
 
 template <int J>
 constexpr int passb_nb() {
-  return J == 1 ? 8 : (J == 2 ? 4 : 2);
+  return J == 1 ? LEARN_B_NB1 : (J == 2 ? 4 : 2);
 }
 
 template <int J>
@@ -633,7 +659,7 @@ static int pow2_floor(int x) {
 // lanes per output for `outs` outputs of `len`-term sums on 256 threads
 static int lanes_for(int outs, int len) { return std::max(1, std::min(std::min(64, len), pow2_floor(256 / outs))); }
 
-static int passb_nb_host(int J) { return J == 1 ? 8 : (J == 2 ? 4 : 2); }
+static int passb_nb_host(int J) { return J == 1 ? LEARN_B_NB1 : (J == 2 ? 4 : 2); }
 static int passb_chunks(const Plan& pl) { return (pl.n + passb_nb_host(pl.j) - 1) / passb_nb_host(pl.j); }
 
 static int dot_parts(const Plan& pl) {
@@ -701,12 +727,23 @@ static hipError_t pruned_zt_proj(const Plan& pl, LearnWs& w, const float2* v, co
   TraceScope trace(kTraceLearnOp, st);
   LJ(l_passA_rows, pl.j, dim3((H / 2 + R) / R, pl.p), dim3(256), st, w.Zh, v, w.S1, pl.n, pl.p, H, W, M2,
      lanes_for(2 * R * M2, W));
-  const int cr = 4;
-  hipLaunchKernelGGL(l_prune_mid, dim3(pl.p, pl.j, (M1 + cr - 1) / cr), dim3(256), 0, st, w.S1, w.R3, mu, pl.k, pl.p,
-                     H, W, M1, M2, cr, lanes_for(cr * M2, H));
-  const int nc = (H / 2 + 1) * W, cpb = 512;
+  const int cr = LEARN_MID_CR;
+  hipLaunchKernelGGL(l_prune_mid, dim3(pl.p, pl.j, (M1 + cr - 1) / cr), dim3(256), 0, st, w.S1, w.R3, mu, nullptr,
+                     pl.k, pl.j, pl.p, H, W, M1, M2, cr, lanes_for(cr * M2, H));
+  const int nc = (H / 2 + 1) * W, cpb = LEARN_COLS_CPB;
   hipLaunchKernelGGL(l_prune_cols, dim3((nc + cpb - 1) / cpb, pl.p, pl.j), dim3(256), 0, st, w.R3, w.Uc, pl.p, H, W,
                      M1, cpb);
+  return hipGetLastError();
+}
+
+// d_k = -S Z_k^T gamma / (2 mu_k) through pass A and the column stage.
+static hipError_t pruned_drecover(const Plan& pl, LearnWs& w, const float* mu, float* d, hipStream_t st) {
+  const int H = pl.g[1], W = pl.g[2], R = 256 / W, M1 = pl.fs[1], M2 = pl.fs[2];
+  LJ(l_passA_rows, pl.j, dim3((H / 2 + R) / R, pl.p), dim3(256), st, w.Zh, w.gh, w.S1, pl.n, pl.p, H, W, M2,
+     lanes_for(2 * R * M2, W));
+  const int cr = LEARN_MID_CR;
+  hipLaunchKernelGGL(l_prune_mid, dim3(pl.p, pl.j, (M1 + cr - 1) / cr), dim3(256), 0, st, w.S1, w.R3, mu, d, pl.k,
+                     pl.j, pl.p, H, W, M1, M2, cr, lanes_for(cr * M2, H));
   return hipGetLastError();
 }
 
@@ -794,10 +831,14 @@ int run_learn(const Plan& pl, const float* b, const float* z, float* d, float* m
       }
     }
     // d_k = -S Z_k^T gamma / (2 mu_k) ; mu_k <- mu_k ||d_k||
-    LJ(l_passA, pl.j, dim3(lblk(D), pl.p), dim3(kLW), st, w.Zh, w.gh, w.Tp, pl.n, pl.p, T, H, W);
-    if ((e = fft_grids(w.Tp, J * pl.p, pl.g, +1, st)) != hipSuccess) return CSC_EHIP;
-    hipLaunchKernelGGL(l_drecover, dim3(lblk(pl.msz), pl.k, pl.j), dim3(kLW), 0, st, w.Tp, mu, d, pl.k, pl.j, pl.p,
-                       T, H, W, pl.fs[0], pl.fs[1], pl.fs[2]);
+    if (pruned) {
+      if ((e = pruned_drecover(pl, w, mu, d, st)) != hipSuccess) return CSC_EHIP;
+    } else {
+      LJ(l_passA, pl.j, dim3(lblk(D), pl.p), dim3(kLW), st, w.Zh, w.gh, w.Tp, pl.n, pl.p, T, H, W);
+      if ((e = fft_grids(w.Tp, J * pl.p, pl.g, +1, st)) != hipSuccess) return CSC_EHIP;
+      hipLaunchKernelGGL(l_drecover, dim3(lblk(pl.msz), pl.k, pl.j), dim3(kLW), 0, st, w.Tp, mu, d, pl.k, pl.j,
+                         pl.p, T, H, W, pl.fs[0], pl.fs[1], pl.fs[2]);
+    }
     const bool last = it == inner_iters - 1;
     hipLaunchKernelGGL(l_mu_update, dim3(pl.k), dim3(kLW), 0, st, d, mu, int64_t(J) * pl.msz, 1, last ? 1 : 0);
   }
