@@ -38,15 +38,18 @@ static int tile_occupancy(int64_t d) {
 }
 
 void set_grouping(Plan* p, int ppg_override) {
-  if (!p->lds) {
+  if (!p->lds && !p->split) {
     p->ppg = 1;
     p->ng = 1;
     return;
   }
   int64_t ppg = ppg_override;
   if (ppg <= 0) {
-    const int64_t slots = 256LL * tile_occupancy(p->dsz);
-    ppg = (int64_t(p->n) * p->p + slots / 2) / slots;
+    // fused: one workgroup per (group, image); split: row-phase workgroups
+    // per (row chunk, group, image), about four resident per CU
+    const int64_t units = int64_t(p->n) * p->p * (p->split ? split_row_blocks(*p) : 1);
+    const int64_t slots = 256LL * (p->split ? 4 : tile_occupancy(p->dsz));
+    ppg = (units + slots / 2) / slots;
   }
   if (ppg < 1) ppg = 1;
   if (ppg > p->p) ppg = p->p;
@@ -78,6 +81,7 @@ int make_plan(const csc_shape* s, Plan* pl) {
   p.dsz = int64_t(p.g[0]) * p.g[1] * p.g[2];
   p.msz = int64_t(p.fs[0]) * p.fs[1] * p.fs[2];
   p.lds = (p.g[0] == 1) && tile_supported(p.g[1], p.g[2]);
+  p.split = !p.lds && split_supported(p.g[0], p.g[1], p.g[2]);
   set_grouping(&p, 0);
   *pl = p;
   return CSC_OK;

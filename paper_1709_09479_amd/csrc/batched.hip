@@ -244,7 +244,7 @@ int csc_batch_autotune(const csc_batch* batch, const float* b, const float* d, f
   for (int ci = 0; ci < (int)bp.cls.size(); ++ci) {
     BatchClass& c = bp.cls[ci];
     ppg_out[ci] = c.pl.ppg;
-    if (!c.pl.lds) continue;
+    if (!c.pl.lds && !c.pl.split) continue;
     float best = 1e30f;
     for (int cv : cand) {
       if (cv > c.pl.p) break;

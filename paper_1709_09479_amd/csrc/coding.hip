@@ -60,10 +60,6 @@ __device__ __forceinline__ void group_sums(const float2* __restrict__ part, int6
   ym = cadd(cadd(m[0], m[1]), cadd(m[2], m[3]));
 }
 
-// Start of image n's code maps ([K][grid]) and of its image ([J][grid]).
-__device__ __forceinline__ int64_t map_base(const int64_t* __restrict__ zoff, int n, int K, int64_t D) {
-  return zoff ? zoff[n] : int64_t(n) * K * D;
-}
 
 // ------------------------------------------------------------------ set-up
 
@@ -709,8 +705,8 @@ static bool fused_dispatch(const Plan& pl, const float2* E, const float2* lam, f
 size_t carve_code(const Plan& pl, void* base, CodeWs* w) {
   Carver c(base);
   const int64_t D = pl.dsz, N = pl.n, J = pl.j, P = pl.p;
-  w->ngp = pl.lds ? pl.ng : 1;
-  w->npri = pl.lds ? pl.ng : int(P * nblk(D));
+  w->ngp = (pl.lds || pl.split) ? pl.ng : 1;
+  w->npri = pl.lds ? pl.ng : pl.split ? int(P * split_col_blocks(pl)) : int(P * nblk(D));
   w->ndual = (int)nblk(D);
   w->E = c.take<float2>(J * P * D);
   w->G = c.take<float2>(D * J * J);
@@ -757,6 +753,8 @@ hipError_t forward_maps(const Plan& pl, const float* maps, CodeWs& w, double* l1
       return hipErrorInvalidValue;
     return hipGetLastError();
   }
+  if (pl.split)
+    return split_maps(pl, w.E, w.lam, w.buf, const_cast<float*>(maps), nullptr, w.rho, 0.f, w.part, l1, 1, st);
   hipLaunchKernelGGL(k_pack_maps, dim3(nblk(D), pl.p, pl.n), dim3(kEW), 0, st, maps, pl.zoff, w.buf, l1, pl.k,
                      pl.p, D);
   hipError_t e = fft_grids(w.buf, int64_t(pl.n) * pl.p, pl.g, -1, st);
@@ -774,6 +772,7 @@ static hipError_t iterate_maps(const Plan& pl, CodeWs& w, float* z, float* theta
       return hipErrorInvalidValue;
     return hipGetLastError();
   }
+  if (pl.split) return split_maps(pl, w.E, w.lam, w.buf, z, theta, w.rho, beta, w.part, w.rpri, 0, st);
   LAUNCH_J(k_make_v, pl.j, dim3(nblk(D), pl.p, pl.n), dim3(kEW), st, w.E, w.lam, w.buf, pl.p, D);
   hipError_t e = fft_grids(w.buf, int64_t(pl.n) * pl.p, pl.g, +1, st);
   if (e != hipSuccess) return e;

@@ -354,6 +354,11 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return t;
 }
 
+// Start of image n's code maps ([K][grid]) and of its image ([J][grid]).
+__device__ __forceinline__ int64_t map_base(const int64_t* __restrict__ zoff, int n, int K, int64_t D) {
+  return zoff ? zoff[n] : int64_t(n) * K * D;
+}
+
 __device__ __forceinline__ float soft_thresh(float u, float t) {
   const float a = fabsf(u) - t;
   return a > 0.0f ? copysignf(a, u) : 0.0f;

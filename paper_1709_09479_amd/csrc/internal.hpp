@@ -21,6 +21,7 @@ struct Plan {
   int64_t dsz = 0;                 // pixels per grid
   int64_t msz = 0;                 // taps per filter channel
   bool lds = false;                // whole grid fits one LDS tile (fused path)
+  bool split = false;              // 2-D grid beyond one tile: row / column / row phases
   int ng = 1;                      // pair groups per image in the fused kernel
   int ppg = 1;                     // pairs per group
   // Optional device tables (batched form): element offset of image n's
@@ -37,6 +38,17 @@ void set_grouping(Plan* pl, int ppg_override);
 constexpr int kTileMax = 16384;
 
 int make_plan(const csc_shape* s, Plan* pl);
+
+// Large 2-D grids (128 x 256, 256 x 128, 256 x 256): the coding map work in
+// three phases (split.hip).  Column / row workgroups per grid:
+bool split_supported(int T, int H, int W);
+int split_col_blocks(const Plan& pl);
+int split_row_blocks(const Plan& pl);
+// mode 0: one ADMM map iteration (z, theta as in the fused kernel, residual
+// partials to rpart [N][P * col_blocks]); mode 1: forward transform of the
+// maps z and reduction into part (l1 partials to rpart).
+hipError_t split_maps(const Plan& pl, const float2* E, const float2* lam, float2* buf, float* z, float* theta,
+                      const float* rho, float beta, float2* part, double* rpart, int mode, hipStream_t st);
 
 // Workspace carving: aligned sub-buffers of one caller-provided block.
 struct Carver {

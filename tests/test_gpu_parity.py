@@ -70,8 +70,12 @@ def test_code_small_config(lib, name):
     ((32, 64), 6, 1, 2),        # rectangular tile
     ((16, 16), 3, 1, 2),        # smallest tile
     ((8, 32), 4, 1, 2),         # side 8: global path
-    ((256, 256), 4, 1, 1),      # global path, two-pass axis FFT
-    ((128, 256), 3, 1, 1),      # global path, rectangular
+    ((256, 256), 4, 1, 1),      # split path (row / column / row phases)
+    ((128, 256), 3, 1, 1),      # split path, rectangular
+    ((256, 128), 5, 1, 2),      # split path, tall, odd K
+    ((256, 256), 25, 1, 8),     # split path, two pairs per row-phase group, last group partial, odd K
+    ((128, 256), 4, 2, 2),      # split path, J = 2
+    ((256, 256), 5, 3, 1),      # split path, J = 3, odd K
     ((64, 64), 6, 3, 2),        # tensor CSC, J = 3 (tile path)
     ((64, 64), 4, 2, 2),        # J = 2
     ((8, 16, 16), 4, 3, 1),     # 3-D volume, J = 3 (global path)
@@ -85,6 +89,23 @@ def test_code_shapes(lib, grid, k, j, n):
     assert density(ref["z"]) > 0.005
     err = np.abs(N(z) - ref["z"]).max()
     assert err <= code_tol(ref["z"]), (err, code_tol(ref["z"]))
+
+
+def test_code_split_warm_start_theta(lib):
+    """Warm start (z and theta both enter through the forward-only phase)
+    and theta output on a 256 x 256 grid."""
+    b, d = rand_case(7, 2, 1, 6, (256, 256), (11, 11))
+    beta, rho = 1.0, 5.0
+    first = oracle.code(b, d, beta, rho, 4)
+    z0, th0 = first["z"].astype(np.float32), first["theta"].astype(np.float32)
+    ref = oracle.code(b, d, beta, rho, 5, z0=z0, theta0=th0)
+    z, th, resid, _ = lib.code(T(b), T(d), beta, rho, 5, z=T(z0), theta=T(th0), want_resid=True)
+    assert density(ref["z"]) > 0.005
+    assert np.abs(N(z) - ref["z"]).max() <= code_tol(ref["z"])
+    assert np.abs(N(th) - ref["theta"]).max() <= code_tol(ref["theta"])
+    r = N(resid)
+    np.testing.assert_allclose(r[:, :, 0], ref["resid"][:, :, 0], rtol=1e-3, atol=1e-5)
+    np.testing.assert_allclose(r[:, :, 1], ref["resid"][:, :, 1], rtol=1e-3, atol=1e-5)
 
 
 def test_code_warm_start_theta_and_residuals(lib):
