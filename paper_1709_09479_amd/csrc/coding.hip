@@ -39,25 +39,29 @@ __device__ __forceinline__ int64_t neg_index(int64_t fl, int T, int H, int W) {
 // by four interleaved accumulators, so that the loads overlap).
 __device__ __forceinline__ void group_sums(const float2* __restrict__ part, int64_t stride_g, int ng, int64_t f,
                                            int64_t fn, float2& y, float2& ym) {
-  float2 a[4], m[4];
+  constexpr int U = 8;  // independent partial sums (loads in flight)
+  float2 a[U], m[U];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) a[u] = m[u] = make_float2(0.f, 0.f);
+  for (int u = 0; u < U; ++u) a[u] = m[u] = make_float2(0.f, 0.f);
   int g = 0;
-  for (; g + 4 <= ng; g += 4) {
+  for (; g + U <= ng; g += U) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
       const float2* pp = part + (g + u) * stride_g;
       a[u] = cadd(a[u], pp[f]);
       m[u] = cadd(m[u], pp[fn]);
     }
   }
-  for (int u = 0; g < ng; ++g, ++u) {
-    const float2* pp = part + g * stride_g;
-    a[u] = cadd(a[u], pp[f]);
-    m[u] = cadd(m[u], pp[fn]);
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (g + u < ng) {
+      const float2* pp = part + (g + u) * stride_g;
+      a[u] = cadd(a[u], pp[f]);
+      m[u] = cadd(m[u], pp[fn]);
+    }
   }
-  y = cadd(cadd(a[0], a[1]), cadd(a[2], a[3]));
-  ym = cadd(cadd(m[0], m[1]), cadd(m[2], m[3]));
+  y = cadd(cadd(cadd(a[0], a[1]), cadd(a[2], a[3])), cadd(cadd(a[4], a[5]), cadd(a[6], a[7])));
+  ym = cadd(cadd(cadd(m[0], m[1]), cadd(m[2], m[3])), cadd(cadd(m[4], m[5]), cadd(m[6], m[7])));
 }
 
 
@@ -170,7 +174,9 @@ __global__ void k_fill_f(float* __restrict__ dst, int64_t count, float v) {
   if (i < count) dst[i] = v;
 }
 
-// dst[n][j](f) = (Y(f) + conj(Y(-f)))/2 with Y = sum_g part[n][g][j].
+// dst[n][j](f) = (Y(f) + conj(Y(-f)))/2 with Y = sum_g part[n][g][j].  The
+// thread of the lower index of each pair (f, -f) writes both values (the
+// second is the conjugate of the first), so part is read once.
 template <int J>
 __global__ void k_sym_reduce(const float2* __restrict__ part, float2* __restrict__ dst, int ng, int T, int H,
                              int W) {
@@ -179,11 +185,14 @@ __global__ void k_sym_reduce(const float2* __restrict__ part, float2* __restrict
   const int n = blockIdx.y;
   if (f >= D) return;
   const int64_t fn = neg_index(f, T, H, W);
+  if (fn < f) return;
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     float2 y, ym;
     group_sums(part + (int64_t(n) * ng * J + j) * D, int64_t(J) * D, ng, f, fn, y, ym);
-    dst[(int64_t(n) * J + j) * D + f] = make_float2(0.5f * (y.x + ym.x), 0.5f * (y.y - ym.y));
+    const float2 s = make_float2(0.5f * (y.x + ym.x), 0.5f * (y.y - ym.y));
+    dst[(int64_t(n) * J + j) * D + f] = s;
+    dst[(int64_t(n) * J + j) * D + fn] = cconj(s);
   }
 }
 
@@ -275,7 +284,9 @@ __global__ void k_solve(const float2* __restrict__ G, const float2* __restrict__
 
 // After the forward pass of iteration i: yhat' = sym(sum_g part), Thhat' =
 // G lam + (yhat' - yhat)/rho_i, partial sums of |Thhat' - Thhat|^2 (the dual
-// residual by Parseval) and, when the step size is fixed, the next lam.
+// residual by Parseval) and, when the step size is fixed, the next lam.  The
+// thread of the lower index of each pair (f, -f) does both frequencies, so
+// part is read once.
 template <int J>
 __global__ __launch_bounds__(kEW) void k_spec(const float2* __restrict__ part, const float2* __restrict__ G,
                                               const float2* __restrict__ xh, float2* __restrict__ yh,
@@ -287,41 +298,49 @@ __global__ __launch_bounds__(kEW) void k_spec(const float2* __restrict__ part, c
   const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int n = blockIdx.y;
   double ds = 0.0;
-  if (f < D) {
-    const int64_t fn = neg_index(f, T, H, W);
+  const int64_t fn = f < D ? neg_index(f, T, H, W) : 0;
+  if (f < D && fn >= f) {  // the pair (f, -f) is handled once, by its lower index
     const float rho = rho_cur[n], inv_rho = 1.0f / rho;
-    const float2* Gf = G + f * J * J;
-    float2 ynew[J], l[J], thn[J];
+    float2 ys[J];  // yhat' at f; at -f it is the conjugate
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       float2 y, ym;
       group_sums(part + (int64_t(n) * ng * J + j) * D, int64_t(J) * D, ng, f, fn, y, ym);
-      ynew[j] = make_float2(0.5f * (y.x + ym.x), 0.5f * (y.y - ym.y));
-      l[j] = lam[(int64_t(n) * J + j) * D + f];
+      ys[j] = make_float2(0.5f * (y.x + ym.x), 0.5f * (y.y - ym.y));
     }
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-      float2 gl = make_float2(0.f, 0.f);
-#pragma unroll
-      for (int c = 0; c < J; ++c) gl = cadd(gl, cmul(Gf[j * J + c], l[c]));
-      const int64_t o = (int64_t(n) * J + j) * D + f;
-      const float2 yo = yh[o], tho = Th[o];
-      thn[j] = make_float2(gl.x + (ynew[j].x - yo.x) * inv_rho, gl.y + (ynew[j].y - yo.y) * inv_rho);
-      const double dx = (double)thn[j].x - tho.x, dy = (double)thn[j].y - tho.y;
-      ds += dx * dx + dy * dy;
-      yh[o] = ynew[j];
-      Th[o] = thn[j];
-    }
-    if (solve_next) {
-      float2 r[J];
+    for (int side = 0; side < (fn == f ? 1 : 2); ++side) {
+      const int64_t ff = side ? fn : f;
+      const float2* Gf = G + ff * J * J;
+      float2 ynew[J], l[J], thn[J];
 #pragma unroll
       for (int j = 0; j < J; ++j) {
-        const float2 x = xh[(int64_t(n) * J + j) * D + f];
-        r[j] = make_float2(thn[j].x + (ynew[j].x - x.x) * inv_rho, thn[j].y + (ynew[j].y - x.y) * inv_rho);
+        ynew[j] = side ? cconj(ys[j]) : ys[j];
+        l[j] = lam[(int64_t(n) * J + j) * D + ff];
       }
-      dual_solve<J>(Gf, inv_rho, r, l);
 #pragma unroll
-      for (int j = 0; j < J; ++j) lam[(int64_t(n) * J + j) * D + f] = l[j];
+      for (int j = 0; j < J; ++j) {
+        float2 gl = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int c = 0; c < J; ++c) gl = cadd(gl, cmul(Gf[j * J + c], l[c]));
+        const int64_t o = (int64_t(n) * J + j) * D + ff;
+        const float2 yo = yh[o], tho = Th[o];
+        thn[j] = make_float2(gl.x + (ynew[j].x - yo.x) * inv_rho, gl.y + (ynew[j].y - yo.y) * inv_rho);
+        const double dx = (double)thn[j].x - tho.x, dy = (double)thn[j].y - tho.y;
+        ds += dx * dx + dy * dy;
+        yh[o] = ynew[j];
+        Th[o] = thn[j];
+      }
+      if (solve_next) {
+        float2 r[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+          const float2 x = xh[(int64_t(n) * J + j) * D + ff];
+          r[j] = make_float2(thn[j].x + (ynew[j].x - x.x) * inv_rho, thn[j].y + (ynew[j].y - x.y) * inv_rho);
+        }
+        dual_solve<J>(Gf, inv_rho, r, l);
+#pragma unroll
+        for (int j = 0; j < J; ++j) lam[(int64_t(n) * J + j) * D + ff] = l[j];
+      }
     }
   }
   const double t = block_sum(ds, red);
@@ -379,7 +398,9 @@ constexpr int fused_threads(int t, int j) {
 
 enum { kModeIter = 0, kModeForward = 1 };
 
-// One workgroup per (pair group g, image n).  kModeIter: for every pair p of
+// One workgroup per (pair group g, image n), handed out by xcd_item so that
+// the workgroups of one XCD share pair groups (and their filter spectra in
+// that XCD's L2) across the images.  kModeIter: for every pair p of
 // the group, back-project lam (V = sum_j lam_j E_jp), inverse 2-D FFT, soft
 // threshold step on the two maps (z updated in place, optional theta),
 // forward 2-D FFT, and accumulate Y_j += C conj(E_jp).  kModeForward: only
@@ -406,7 +427,8 @@ __global__ __launch_bounds__(fused_threads(H * W, J)) void k_fused(
   __shared__ float2 tile[H * WP];
   __shared__ float2 tw[256];
   __shared__ double red[NT / 64];
-  const int g = blockIdx.x, n = blockIdx.y;
+  const int N = (int)(gridDim.x / ng), item = xcd_item((int)blockIdx.x, (int)gridDim.x);
+  const int g = item / N, n = item % N;
   load_twiddles(tw);
   float2 acc[kRegAcc ? P8::JPT : 1][kRegAcc ? P8::R : 1];
   if constexpr (kRegAcc) {
@@ -632,16 +654,22 @@ __global__ __launch_bounds__(kEW) void k_obj_spec(const float2* __restrict__ par
   const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int n = blockIdx.y;
   double s = 0.0;
-  if (f < D) {
-    const int64_t fn = neg_index(f, T, H, W);
+  const int64_t fn = f < D ? neg_index(f, T, H, W) : 0;
+  if (f < D && fn >= f) {  // the pair (f, -f) once, by its lower index
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       float2 y, ym;
       group_sums(part + (int64_t(n) * ng * J + j) * D, int64_t(J) * D, ng, f, fn, y, ym);
+      const double sx = 0.5 * ((double)y.x + ym.x), sy = 0.5 * ((double)y.y - ym.y);  // yhat at f
       const float2 x = xh[(int64_t(n) * J + j) * D + f];
-      const double rx = (double)x.x - 0.5 * ((double)y.x + ym.x);
-      const double ry = (double)x.y - 0.5 * ((double)y.y - ym.y);
+      double rx = (double)x.x - sx, ry = (double)x.y - sy;
       s += rx * rx + ry * ry;
+      if (fn != f) {  // yhat(-f) = conj(yhat(f))
+        const float2 xm = xh[(int64_t(n) * J + j) * D + fn];
+        rx = (double)xm.x - sx;
+        ry = (double)xm.y + sy;
+        s += rx * rx + ry * ry;
+      }
     }
   }
   const double t = block_sum(s, red);
@@ -677,7 +705,7 @@ static unsigned nblk(int64_t n, int b = kEW) { return (unsigned)((n + b - 1) / b
 template <int J, int MODE>
 static bool fused_launch(const Plan& pl, const float2* E, const float2* lam, float* z, float* theta,
                          const float* rho, float beta, float2* part, double* rpart, hipStream_t st) {
-  const dim3 grid(pl.ng, pl.n);
+  const dim3 grid(pl.ng * pl.n);
   const int h = pl.g[1], w = pl.g[2];
 #define FL(HH, WW)                                                                                         \
   if (h == HH && w == WW) {                                                                                \

@@ -359,6 +359,18 @@ __device__ __forceinline__ int64_t map_base(const int64_t* __restrict__ zoff, in
   return zoff ? zoff[n] : int64_t(n) * K * D;
 }
 
+// Work item of workgroup `id` of a 1-D grid of `total` workgroups when the
+// items (in the caller's order) go to the 8 XCDs of the chip in contiguous
+// ranges.  Workgroups are dispatched to the XCDs round-robin, so id % 8 names
+// the XCD and id / 8 the position within its range.  A bijection on
+// [0, total) for any total.
+__device__ __forceinline__ int xcd_item(int id, int total) {
+  constexpr int kXcd = 8;
+  const int q = total / kXcd, r = total % kXcd;
+  const int x = id % kXcd, s = id / kXcd;
+  return x * q + (x < r ? x : r) + s;
+}
+
 __device__ __forceinline__ float soft_thresh(float u, float t) {
   const float a = fabsf(u) - t;
   return a > 0.0f ? copysignf(a, u) : 0.0f;

@@ -31,7 +31,11 @@ __global__ __launch_bounds__(kSplitNT) void k_split_rows_inv(const float2* __res
   __shared__ float2 tile[RB * WP];
   __shared__ float2 tw[256];
   load_twiddles(tw);
-  const int rc = blockIdx.x, p = blockIdx.y, n = blockIdx.z;
+  // items (row chunk, pair)-major, images fastest, spread over the XCDs so
+  // that the images of one XCD share rows of E in its L2
+  const int N = (int)(gridDim.x / (unsigned)(P * (H / RB)));
+  const int item = xcd_item((int)blockIdx.x, (int)gridDim.x);
+  const int n = item % N, p = (item / N) % P, rc = item / N / P;
   const int64_t D = int64_t(H) * W, row0 = int64_t(rc) * RB;
   const float2* lamn = lam + int64_t(n) * J * D;
   const float2* Ep[J];
@@ -178,7 +182,9 @@ __global__ __launch_bounds__(kSplitNT) void k_split_rows_fwd(const float2* __res
   __shared__ float2 tile[RB * WP];
   __shared__ float2 tw[256];
   load_twiddles(tw);
-  const int rc = blockIdx.x, gi = blockIdx.y, n = blockIdx.z;
+  const int N = (int)(gridDim.x / (unsigned)(ng * (H / RB)));
+  const int item = xcd_item((int)blockIdx.x, (int)gridDim.x);  // as in the inverse row phase
+  const int n = item % N, gi = (item / N) % ng, rc = item / N / ng;
   const int64_t D = int64_t(H) * W, row0 = int64_t(rc) * RB;
   const int p0 = gi * ppg, p1 = min(P, p0 + ppg);
   float2 acc[J][Q1::JPT][Q1::R];
@@ -243,7 +249,7 @@ static hipError_t split_iter_j(const Plan& pl, const float2* E, const float2* la
   const int H = pl.g[1], W = pl.g[2];
   const dim3 blk(kSplitNT);
   if (mode == 0) {
-    const dim3 g1(split_row_blocks(pl), pl.p, pl.n);
+    const dim3 g1(split_row_blocks(pl) * pl.p * pl.n);
     if (W == 256) hipLaunchKernelGGL((k_split_rows_inv<256, J>), g1, blk, 0, st, E, lam, buf, pl.p, H);
     else hipLaunchKernelGGL((k_split_rows_inv<128, J>), g1, blk, 0, st, E, lam, buf, pl.p, H);
   }
@@ -259,7 +265,7 @@ static hipError_t split_iter_j(const Plan& pl, const float2* E, const float2* la
     else
       hipLaunchKernelGGL((k_split_cols<128, 1>), g2, blk, 0, st, buf, z, nullptr, pl.zoff, rho, 0.f, rpart, pl.k, pl.p, W);
   }
-  const dim3 g3(split_row_blocks(pl), pl.ng, pl.n);
+  const dim3 g3(split_row_blocks(pl) * pl.ng * pl.n);
   if (W == 256) hipLaunchKernelGGL((k_split_rows_fwd<256, J>), g3, blk, 0, st, E, buf, part, pl.p, H, pl.ppg, pl.ng);
   else hipLaunchKernelGGL((k_split_rows_fwd<128, J>), g3, blk, 0, st, E, buf, part, pl.p, H, pl.ppg, pl.ng);
   return hipGetLastError();
