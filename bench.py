@@ -5,14 +5,21 @@ Workload (synthetic stand-in for the paper's grayscale image sets): N = 10
 contrast-normalised 1/f images of 100 x 100 zero-padded to 128 x 128, K = 100
 filters of 11 x 11, beta = 1, adaptive rho from 10.  One step is one outer
 alternation of Alg. 1: 10 ADMM coding iterations (warm-started), the learning
-subproblem (10 multiplier updates x 10 CG iterations, warm-started gamma;
-replayed from a hipGraph captured on the first step) and the objective.  Inputs are resident in HBM before timing starts.
+subproblem (10 multiplier updates x 10 CG iterations, warm-started gamma) and
+the objective.  Inputs are resident in HBM before timing starts.
 
 Printed: one JSON line.  ``value`` = code-pixel-iterations per second over the
 whole step (N * K * H * W * coding iterations / step time).  ``roofline``
-covers the dominant kernel (the fused per-iteration coding kernel), its
-duration measured with HIP events on its own stream during the timed steps.
-``cpu_baseline`` times the FP64 oracle on a bounded sample of the same step.
+covers the kernel with the largest share of the step (learning pass A), its
+launch duration measured with HIP events on its own stream during the timed
+steps; ``roofline_extra`` gives the same for learning pass B and the fused
+coding kernel.  ``traffic`` is taken from the committed rocprofv3 counter
+summary when the library sources still match the ones it was measured on,
+else null.  ``cpu_baseline`` times the FP64 oracle on a bounded sample of
+the same step.
+
+``--calibrate-copy MIB`` only runs a plain device copy of that size (the
+reference kernel for scaling the FETCH_SIZE / WRITE_SIZE counters).
 """
 import argparse
 import json
@@ -24,6 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+TRACE_EVERY = 8                # timed steps bracket every 8th launch of a traced kernel
 FP32_VECTOR_TFLOPS = 157.3     # MI355X fp32 vector (packed); 78.6 unpacked
 
 
@@ -31,6 +39,72 @@ def alg_bytes_per_iter(n, j, k, d):
     """Bytes one coding iteration must move: z read + write (float32), the
     filter spectra once (half spectra, complex64), per-image spectra."""
     return 8 * n * k * d + 4 * j * k * d + 12 * n * j * d
+
+
+def alg_bytes_pass_a(n, j, k, h, w, m2):
+    """Bytes one learning pass A must move: the N x ceil(K/2) code pair spectra
+    (4 N K D), the CG vector at the canonical half of the frequencies
+    (8 N J (H/2+1) W) and the row-stage output (8 J ceil(K/2) H M2)."""
+    p = (k + 1) // 2
+    return 8 * n * p * h * w + 8 * n * j * (h // 2 + 1) * w + 8 * j * p * h * m2
+
+
+def alg_bytes_pass_b(n, j, k, h, w):
+    """Bytes one learning pass B must move: the code pair spectra (4 N K D),
+    the projected filter spectra at the canonical frequencies (16 J P
+    (H/2+1) W), the CG vector read and the result written (16 N J D)."""
+    p = (k + 1) // 2
+    return 8 * n * p * h * w + 16 * j * p * (h // 2 + 1) * w + 16 * n * j * h * w
+
+
+def csrc_digest():
+    """sha256 over the library sources (the kernels the counters describe)."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_1709_09479_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(src)):
+        if name.endswith((".hip", ".hpp", ".py")):
+            h.update(name.encode())
+            with open(os.path.join(src, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def counter_traffic(kernel):
+    """HBM bytes per launch of `kernel` from profiles/learn_step_hbm_bytes.md
+    (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, scaled by the factors a
+    plain copy kernel gives), or None when the sources have changed since."""
+    path = os.path.join(ROOT, "profiles", "learn_step_hbm_bytes.md")
+    try:
+        lines = open(path).read().splitlines()
+    except OSError:
+        return None
+    kv, rows = {}, {}
+    for ln in lines:
+        ln = ln.strip()
+        if ln.startswith("csrc_sha256 = ") or ln.startswith("fetch_scale = ") or ln.startswith("write_scale = "):
+            key, val = ln.split(" = ", 1)
+            kv[key] = val.strip()
+        elif ln.startswith("kernel "):
+            parts = ln.split()
+            vals = dict(x.split("=") for x in parts[2:])
+            rows[parts[1]] = (float(vals["fetch_kib"]), float(vals["write_kib"]))
+    if kv.get("csrc_sha256") != csrc_digest() or kernel not in rows:
+        return None
+    fk, wk = rows[kernel]
+    return 1024.0 * (fk * float(kv["fetch_scale"]) + wk * float(kv["write_scale"]))
+
+
+def calibrate_copy(mib):
+    """A plain device copy of `mib` MiB, three times (counter calibration)."""
+    import torch
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_mib": mib, "bytes_each_way": n * 4}))
 
 
 def bench_batched(dc, synth, np, torch, n_images):
@@ -143,11 +217,16 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--batched-images", type=int, default=256)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on one GPU only (the build targets a single MI355X); "
               "got --gpus %d" % args.gpus, file=sys.stderr)
         sys.exit(2)
+
+    if args.calibrate_copy > 0:
+        calibrate_copy(args.calibrate_copy)
+        return
 
     import numpy as np
     import torch
@@ -172,13 +251,13 @@ def main():
         s["z"], s["theta"], _, s["rho"] = dc.code(bt, s["d"], cfg.beta, s["rho"], cfg.t_in, z=s["z"],
                                                   theta=s["theta"], adaptive=True, want_theta=True)
         s["d"], s["mu"], s["gamma"] = dc.learn(bt, s["z"], cfg.fsupp, s["mu"], s["gamma"], cfg.learn_inner,
-                                               cfg.learn_cg, out=s["d"], graph=True)
+                                               cfg.learn_cg, out=s["d"])
         s["obj"] = dc.objective(bt, s["d"], s["z"], cfg.beta)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    dc.trace_enable(True)
+    dc.trace_enable(True, every=TRACE_EVERY)
     stream = torch.cuda.current_stream()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -193,7 +272,8 @@ def main():
     ms_step = ms_total / args.steps
     maps_ms, maps_cnt = dc.trace_read(dc.TRACE_CODE_MAPS)
     spec_ms, spec_cnt = dc.trace_read(dc.TRACE_CODE_SPEC)
-    lop_ms, lop_cnt = dc.trace_read(dc.TRACE_LEARN_OP)
+    la_ms, la_cnt = dc.trace_read(dc.TRACE_LEARN_A)
+    lb_ms, lb_cnt = dc.trace_read(dc.TRACE_LEARN_B)
 
     cpit_step = N * K * D * cfg.t_in
     value = cpit_step / (ms_step / 1e3)
@@ -218,6 +298,33 @@ def main():
     bytes_launch = alg_bytes_per_iter(N, J, K, D)
     achieved = bytes_launch / (fused_avg_ms / 1e3) / 1e9
     flop_launch = (5 * np.log2(D) + 16) * N * K * D
+    fused_traffic = counter_traffic("k_fused<128,128,1,0>")
+
+    def hbm_roofline(kernel, alg_bytes, ms_total, count, traffic):
+        avg = ms_total / max(1, count)
+        ach = alg_bytes / (avg / 1e3) / 1e9
+        return {"kernel": kernel, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "avg_launch_ms": avg, "launches": count,
+                "alg_bytes_per_launch": alg_bytes}
+
+    roof_a = hbm_roofline("l_passA_rows<1> (learning pass A: sum over images of conj(zhat) p, row stage of "
+                          "the support projection)", alg_bytes_pass_a(N, J, K, H, W, cfg.fsupp[1]), la_ms,
+                          la_cnt, counter_traffic("l_passA_rows<1>"))
+    roof_b = hbm_roofline("l_passB_c<1> (learning pass B: p + sum over filters of zhat U)",
+                          alg_bytes_pass_b(N, J, K, H, W), lb_ms, lb_cnt, counter_traffic("l_passB_c<1>"))
+    roof_fused = {
+        "kernel": "k_fused<128,128,1,iter> (back-projection + inverse FFT + soft threshold + forward FFT)",
+        "bound": "hbm",
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS,
+        "traffic": fused_traffic,
+        "avg_launch_ms": fused_avg_ms,
+        "launches": maps_cnt,
+        "alg_bytes_per_launch": bytes_launch,
+        "alu_tflops": flop_launch / (fused_avg_ms / 1e3) / 1e12,
+    }
 
     out = {
         "metric": "ADMM coding iters/sec (N·K·pixels/s) + HBM GB/s; batched & backward vs plain",
@@ -239,28 +346,18 @@ def main():
             "n": N, "j": J, "k": K, "grid": [H, W], "fsupp": list(cfg.fsupp), "t_in": cfg.t_in,
             "learn_inner": cfg.learn_inner, "learn_cg": cfg.learn_cg,
         },
-        "roofline": {
-            "kernel": "k_fused<128,128,1,iter> (back-projection + inverse FFT + soft threshold + forward FFT)",
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
-            "avg_launch_ms": fused_avg_ms,
-            "launches": maps_cnt,
-            "alg_bytes_per_launch": bytes_launch,
-            "alu_tflops": flop_launch / (fused_avg_ms / 1e3) / 1e12,
-        },
+        "roofline": roof_a,
+        "roofline_extra": {"learning_pass_b": roof_b, "coding_fused": roof_fused},
         "coding_only": {
             "ms_per_call": code_ms,
             "cp_it_per_s": cpit_step / (code_ms / 1e3),
             "alg_gbps": bytes_launch * cfg.t_in / (code_ms / 1e3) / 1e9,
         },
-        "breakdown_ms_per_step": {
-            "coding_map_kernel": maps_ms / args.steps,
-            "coding_spectral": spec_ms / args.steps,
-            "learning_op_first_half": lop_ms / args.steps,
+        "traced_avg_launch_ms": {
+            "coding_map_kernel": maps_ms / max(1, maps_cnt),
+            "coding_spectral": spec_ms / max(1, spec_cnt),
+            "learning_pass_a": la_ms / max(1, la_cnt),
+            "learning_pass_b": lb_ms / max(1, lb_cnt),
         },
         "objective_last": float(state["obj"][-1].item()),
     }

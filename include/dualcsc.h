@@ -251,17 +251,22 @@ int csc_batch_autotune(const csc_batch* batch, const float* b, const float* d,
                        int max_classes);
 
 /*
- * Launch tracing (for benchmarks and profiling).  csc_trace_enable(1) clears
- * the record and starts bracketing the launches of the traced kernel classes
- * with HIP events on the stream they are launched on (at most 8192 records;
- * later launches are not recorded); csc_trace_enable(0) stops recording.
+ * Launch tracing (for benchmarks and profiling).  csc_trace_enable(n), n >= 1,
+ * clears the record and starts bracketing every n-th launch of each traced
+ * kernel class (the 1st, (n+1)-th, ...) with HIP events on the stream it is
+ * launched on (at most 8192 records; later launches are not recorded).  Each
+ * bracket costs a few microseconds of stream time, so benchmarks sample with
+ * n > 1.  csc_trace_enable(0) stops recording; n < 0 is CSC_EINVAL.
  * csc_trace_read waits for the recorded events and returns the summed
  * duration in milliseconds and the number of records of class `cls`:
  *   0 = coding map kernel (back-projection, inverse FFT, soft threshold,
  *       forward FFT: one launch per ADMM iteration on single-tile grids),
  *   1 = coding per-frequency kernels (spectral reduce and dual solve),
- *   2 = learning operator, first half (pass A over the code spectra and the
- *       filter-support projection; one record per operator application).
+ *   2 = learning pass A kernel (sum over images of conj(zhat) times the CG
+ *       vector, eq:Learning_gamma; one record per launch),
+ *   3 = learning pass B kernel (sum over filters of zhat times the projected
+ *       filter spectra; one record per launch).
+ * Calls captured into a hipGraph (CSC_USE_GRAPH) record nothing.
  * Errors: CSC_EINVAL (bad class or NULL outputs), CSC_EHIP.
  */
 int csc_trace_enable(int on);

@@ -305,12 +305,15 @@ def objective(b, d, z, beta: float):
     return out
 
 
-TRACE_CODE_MAPS, TRACE_CODE_SPEC, TRACE_LEARN_OP = 0, 1, 2
+TRACE_CODE_MAPS, TRACE_CODE_SPEC, TRACE_LEARN_A, TRACE_LEARN_B = 0, 1, 2, 3
 
 
-def trace_enable(on: bool = True) -> None:
-    """Start (clearing earlier records) or stop event tracing of launches."""
-    _check(load().csc_trace_enable(1 if on else 0))
+def trace_enable(on: bool = True, every: int = 1) -> None:
+    """Start (clearing earlier records) or stop event tracing of launches;
+    with ``every`` = n only every n-th launch of each class is bracketed."""
+    if every < 1:
+        raise ValueError("every must be >= 1")
+    _check(load().csc_trace_enable(int(every) if on else 0))
 
 
 def trace_read(cls: int) -> Tuple[float, int]:

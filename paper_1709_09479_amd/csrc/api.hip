@@ -145,6 +145,8 @@ namespace {
 constexpr int kTraceSlots = 8192;
 std::mutex g_trace_mu;
 bool g_trace_on = false;
+int g_trace_every = 1;           // bracket every n-th launch of each class
+int g_cls_seen[kTraceClasses];   // launches seen per class since enabling
 std::vector<hipEvent_t> g_ev_start, g_ev_stop;
 std::vector<int> g_ev_cls;
 int g_ev_used = 0;
@@ -155,6 +157,7 @@ TraceScope::TraceScope(int cls, hipStream_t st) : cls_(cls), st_(st), slot_(-1) 
   if (!g_trace_on || g_ev_used >= kTraceSlots) return;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(st_, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+  if (g_cls_seen[cls]++ % g_trace_every != 0) return;
   slot_ = g_ev_used++;
   g_ev_cls[slot_] = cls;
   hipEventRecord(g_ev_start[slot_], st_);
@@ -173,6 +176,7 @@ extern "C" {
 int csc_abi_version(void) { return CSC_ABI_VERSION; }
 
 int csc_trace_enable(int on) {
+  if (on < 0) return CSC_EINVAL;
   std::lock_guard<std::mutex> lk(g_trace_mu);
   if (on && g_ev_start.empty()) {
     g_ev_start.resize(kTraceSlots);
@@ -187,7 +191,11 @@ int csc_trace_enable(int on) {
     }
   }
   g_trace_on = on != 0;
-  if (on) g_ev_used = 0;
+  if (on) {
+    g_ev_used = 0;
+    g_trace_every = on;
+    for (int c = 0; c < kTraceClasses; ++c) g_cls_seen[c] = 0;
+  }
   return CSC_OK;
 }
 

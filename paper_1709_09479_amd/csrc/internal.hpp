@@ -99,7 +99,7 @@ int graph_call(const std::vector<int64_t>& key, hipStream_t st, int (*enqueue)(v
 // Launch tracing.  While enabled (csc_trace_enable), a TraceScope brackets
 // the launches made in its lifetime with a pair of HIP events recorded on
 // the launching stream; csc_trace_read sums the elapsed times per class.
-enum TraceClass { kTraceCodeMaps = 0, kTraceCodeSpec = 1, kTraceLearnOp = 2, kTraceClasses = 4 };
+enum TraceClass { kTraceCodeMaps = 0, kTraceCodeSpec = 1, kTraceLearnA = 2, kTraceLearnB = 3, kTraceClasses = 4 };
 struct TraceScope {
   TraceScope(int cls, hipStream_t st);
   ~TraceScope();

@@ -724,9 +724,11 @@ static bool crop_tile_launch(const Plan& pl, float2* Tp, const float* mu, hipStr
 // R3, the last stage into Uc.
 static hipError_t pruned_zt_proj(const Plan& pl, LearnWs& w, const float2* v, const float* mu, hipStream_t st) {
   const int H = pl.g[1], W = pl.g[2], R = 256 / W, M1 = pl.fs[1], M2 = pl.fs[2];
-  TraceScope trace(kTraceLearnOp, st);
-  LJ(l_passA_rows, pl.j, dim3((H / 2 + R) / R, pl.p), dim3(256), st, w.Zh, v, w.S1, pl.n, pl.p, H, W, M2,
-     lanes_for(2 * R * M2, W));
+  {
+    TraceScope trace(kTraceLearnA, st);
+    LJ(l_passA_rows, pl.j, dim3((H / 2 + R) / R, pl.p), dim3(256), st, w.Zh, v, w.S1, pl.n, pl.p, H, W, M2,
+       lanes_for(2 * R * M2, W));
+  }
   const int cr = LEARN_MID_CR;
   hipLaunchKernelGGL(l_prune_mid, dim3(pl.p, pl.j, (M1 + cr - 1) / cr), dim3(256), 0, st, w.S1, w.R3, mu, nullptr,
                      pl.k, pl.j, pl.p, H, W, M1, M2, cr, lanes_for(cr * M2, H));
@@ -739,8 +741,11 @@ static hipError_t pruned_zt_proj(const Plan& pl, LearnWs& w, const float2* v, co
 // d_k = -S Z_k^T gamma / (2 mu_k) through pass A and the column stage.
 static hipError_t pruned_drecover(const Plan& pl, LearnWs& w, const float* mu, float* d, hipStream_t st) {
   const int H = pl.g[1], W = pl.g[2], R = 256 / W, M1 = pl.fs[1], M2 = pl.fs[2];
-  LJ(l_passA_rows, pl.j, dim3((H / 2 + R) / R, pl.p), dim3(256), st, w.Zh, w.gh, w.S1, pl.n, pl.p, H, W, M2,
-     lanes_for(2 * R * M2, W));
+  {
+    TraceScope trace(kTraceLearnA, st);
+    LJ(l_passA_rows, pl.j, dim3((H / 2 + R) / R, pl.p), dim3(256), st, w.Zh, w.gh, w.S1, pl.n, pl.p, H, W, M2,
+       lanes_for(2 * R * M2, W));
+  }
   const int cr = LEARN_MID_CR;
   hipLaunchKernelGGL(l_prune_mid, dim3(pl.p, pl.j, (M1 + cr - 1) / cr), dim3(256), 0, st, w.S1, w.R3, mu, d, pl.k,
                      pl.j, pl.p, H, W, M1, M2, cr, lanes_for(cr * M2, H));
@@ -752,6 +757,7 @@ static hipError_t pruned_drecover(const Plan& pl, LearnWs& w, const float* mu, f
 static void pruned_passB(const Plan& pl, LearnWs& w, const float2* v, float2* q, const float2* xh, double* part,
                          hipStream_t st) {
   const int chunks = passb_chunks(pl), nbc = (pl.n + chunks - 1) / chunks;
+  TraceScope trace(kTraceLearnB, st);
   LJ(l_passB_c, pl.j, dim3(canon_blocks(pl), chunks), dim3(64 * kBW), st, w.Zh, w.Uc, v, q, xh, part, pl.n, pl.p,
      pl.g[1], pl.g[2], nbc);
 }
@@ -760,8 +766,10 @@ static void pruned_passB(const Plan& pl, LearnWs& w, const float2* v, float2* q,
 static hipError_t apply_zt_proj(const Plan& pl, LearnWs& w, const float2* v, const float* mu, hipStream_t st) {
   const int64_t D = pl.dsz;
   const int T = pl.g[0], H = pl.g[1], W = pl.g[2];
-  TraceScope trace(kTraceLearnOp, st);
-  LJ(l_passA, pl.j, dim3(lblk(D), pl.p), dim3(kLW), st, w.Zh, v, w.Tp, pl.n, pl.p, T, H, W);
+  {
+    TraceScope trace(kTraceLearnA, st);
+    LJ(l_passA, pl.j, dim3(lblk(D), pl.p), dim3(kLW), st, w.Zh, v, w.Tp, pl.n, pl.p, T, H, W);
+  }
   if (crop_tile_launch(pl, w.Tp, mu, st)) return hipGetLastError();
   hipError_t e = fft_grids(w.Tp, int64_t(pl.j) * pl.p, pl.g, +1, st);
   if (e != hipSuccess) return e;
@@ -774,6 +782,7 @@ static hipError_t apply_zt_proj(const Plan& pl, LearnWs& w, const float2* v, con
 static void apply_passB(const Plan& pl, LearnWs& w, const float2* v, float2* q, const float2* xh, double* dots,
                         hipStream_t st) {
   const int T = pl.g[0], H = pl.g[1], W = pl.g[2];
+  TraceScope trace(kTraceLearnB, st);
   LJ(l_passB, pl.j, dim3(lblk(pl.dsz), pl.n), dim3(kLW), st, w.Zh, w.Tp, v, q, xh, dots, pl.n, pl.p, T, H, W);
 }
 

@@ -122,3 +122,16 @@ def test_binding_refuses_cpu_tensors():
     d = torch.zeros(2, 1, 3, 3)
     with pytest.raises(dc.DualCSCError):
         dc.code(b, d, 1.0, 1.0, 2)
+
+
+def test_trace_argument_errors():
+    """A negative sampling period is rejected before any HIP call; reading an
+    unknown class or into NULL outputs is CSC_EINVAL."""
+    lib = dc.load()
+    assert lib.csc_trace_enable(-1) == -1
+    ms, cnt = ctypes.c_double(), ctypes.c_int()
+    assert lib.csc_trace_read(4, ctypes.byref(ms), ctypes.byref(cnt)) == -1
+    assert lib.csc_trace_read(-1, ctypes.byref(ms), ctypes.byref(cnt)) == -1
+    assert lib.csc_trace_read(0, None, ctypes.byref(cnt)) == -1
+    with pytest.raises(ValueError):
+        dc.trace_enable(True, every=0)

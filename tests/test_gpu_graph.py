@@ -53,3 +53,19 @@ def test_code_graph_replays_equal_eager(lib):
         assert torch.equal(z, z_e), rep
         lib.learn(bt, z_e, cfg.fsupp, None, None, 1, 2)
         torch.cuda.synchronize()
+
+
+def test_trace_sampling_counts(lib):
+    """csc_trace_enable(n) brackets the 1st, (n+1)-th, ... launch of a class:
+    7 coding iterations give 7 records with n = 1 and 3 with n = 3."""
+    import torch
+    rng = np.random.default_rng(3)
+    b = torch.from_numpy(rng.standard_normal((2, 1, 64, 64)).astype(np.float32)).cuda()
+    d = torch.from_numpy(rng.standard_normal((4, 1, 11, 11)).astype(np.float32)).cuda()
+    for every, want in ((1, 7), (3, 3)):
+        lib.trace_enable(True, every=every)
+        lib.code(b, d, 1.0, 5.0, 7)
+        torch.cuda.synchronize()
+        lib.trace_enable(False)
+        ms, cnt = lib.trace_read(lib.TRACE_CODE_MAPS)
+        assert cnt == want and ms > 0.0
