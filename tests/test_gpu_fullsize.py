@@ -1,0 +1,162 @@
+"""Parity at the full sizes of the benchmarked workloads, in the launch
+configurations bench.py times, on outputs the FP64 oracle can compute:
+
+* the learning-alternation step (10 x 128^2, K=100): coding with adaptive rho
+  (the GPU's rho schedule replayed by the oracle), learning from the GPU's
+  codes, and the objective, all on the full workload;
+* the batched form (256 ragged images, K=64, 30 iterations, hipGraph replay):
+  coding is independent per image, so sampled images of the full batch are
+  compared with the oracle run on those images alone;
+* the differentiable form (16 x 256^2, K=100, 30 unrolled iterations,
+  checkpoints every 5): the forward codes of a sampled image, the filter and
+  beta gradients of one image against the oracle's reverse pass, and the
+  full-batch gradient against the sum of the gradients of two halves of the
+  batch (the loss is a sum over images whose codes do not interact);
+* tensor CSC at its full size (32 x RGB 128^2, K=64): sampled images; the
+  RGB video volume (16 x 128 x 128, K=64) in full.
+
+Tolerances as in test_gpu_parity.py (codes 1e-4, or 3e-6 * max|z| for large
+codes; objective 1e-5 relative) and test_gpu_diff.py (gradients 1e-3 of
+max |grad|)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+CODE_TOL = 1e-4
+OBJ_RTOL = 1e-5
+GRAD_RTOL = 1e-3
+
+
+def T(x, grad=False):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+    return t.requires_grad_(grad)
+
+
+def N(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def code_tol(z_ref):
+    return max(CODE_TOL, 3e-6 * float(np.abs(z_ref).max()))
+
+
+def test_learning_step_full_workload(lib):
+    """One outer step of the benchmark: 10 images 128^2, K=100, adaptive rho,
+    10 coding iterations, learning 10 x 10, objective."""
+    import torch
+    cfg = synth.CONFIGS["learn"]
+    b, d0 = synth.make_inputs(cfg)
+    bt = T(b)
+    rho0 = torch.full((cfg.n,), cfg.rho0, dtype=torch.float32, device="cuda")
+    z, theta, resid, rho = lib.code(bt, T(d0), cfg.beta, rho0, cfg.t_in, adaptive=True, want_theta=True,
+                                    want_resid=True)
+    sched = np.concatenate([N(resid)[:, :, 2], N(rho)[None]], axis=0)
+    ref = oracle.code(b, d0, cfg.beta, cfg.rho0, cfg.t_in, rho_schedule=sched)
+    assert np.count_nonzero(ref["z"]) / ref["z"].size > 0.01
+    assert np.abs(N(z) - ref["z"]).max() <= code_tol(ref["z"])
+    assert np.abs(N(theta) - ref["theta"]).max() <= code_tol(ref["theta"])
+
+    mu = torch.ones(cfg.k, dtype=torch.float32, device="cuda")
+    d, mu1, gamma = lib.learn(bt, z, cfg.fsupp, mu, None, cfg.learn_inner, cfg.learn_cg)
+    zf = N(z).astype(np.float32)
+    d_ref, mu_ref, _ = oracle.learn(b, zf, cfg.fsupp, np.ones(cfg.k), None, cfg.learn_inner, cfg.learn_cg)
+    assert np.abs(N(d) - d_ref).max() <= 1e-4 * max(1.0, np.abs(d_ref).max())
+    np.testing.assert_allclose(N(mu1), mu_ref, rtol=1e-4)
+
+    obj = N(lib.objective(bt, d, z, cfg.beta))
+    per, tot = oracle.objective(b, N(d).astype(np.float32), zf, cfg.beta)
+    np.testing.assert_allclose(obj[:-1], per, rtol=OBJ_RTOL)
+    assert abs(obj[-1] - tot) <= OBJ_RTOL * abs(tot)
+
+
+def test_batched_full_workload_sampled(lib):
+    """All 256 ragged images in one hipGraph-replayed call; images from the
+    largest, a rectangular and a small grid class against the oracle."""
+    import torch
+    cfg = synth.CONFIGS["batched"]
+    imgs, grids, d0 = synth.ragged_inputs(cfg)
+    padded = []
+    for im, g in zip(imgs, grids):
+        t = torch.zeros((1,) + g, dtype=torch.float32)
+        t[:, :im.shape[1], :im.shape[2]] = torch.from_numpy(im)
+        padded.append(t.cuda())
+    pb = lib.PackedBatch(padded, cfg.k)
+    z = torch.empty(pb.z_numel, dtype=torch.float32, device="cuda")
+    lib.code_batched(pb, T(d0), cfg.beta, cfg.rho, cfg.t_in, z=z, graph=True)   # capture + replay
+    lib.code_batched(pb, T(d0), cfg.beta, cfg.rho, cfg.t_in, z=z, graph=True)   # replay
+    zs = pb.z_views(z)
+    picks = []
+    for want in ((256, 256), (128, 256), (256, 64), (64, 64)):
+        idx = [i for i, g in enumerate(grids) if g == want]
+        if idx:
+            picks.append(idx[0])
+    assert len(picks) >= 3
+    for i in picks:
+        ref = oracle.code(padded[i].cpu().numpy()[None], d0, cfg.beta, cfg.rho, cfg.t_in)["z"][0]
+        assert np.count_nonzero(ref) / ref.size > 0.005, grids[i]
+        assert np.abs(zs[i].cpu().numpy() - ref).max() <= code_tol(ref), grids[i]
+
+
+def test_unrolled_full_workload(lib):
+    """16 x 256^2, K=100, 30 unrolled iterations, checkpoints every 5."""
+    import torch
+    cfg = synth.CONFIGS["unrolled"]
+    b, d0 = synth.make_inputs(cfg)
+    every = 5
+
+    def grad(bsub):
+        dt = T(d0, True)
+        bet = torch.tensor(cfg.beta, dtype=torch.float64, requires_grad=True)
+        z = lib.unrolled_code(T(bsub), dt, bet, cfg.rho, cfg.t_in, every)
+        L = lib.csc_loss(T(bsub), dt, z, bet)
+        L.backward()
+        return L.item(), N(dt.grad), bet.grad.item(), z
+
+    L, gd, gb, z = grad(b)
+    ref = oracle.code(b[:1], d0, cfg.beta, cfg.rho, cfg.t_in)["z"]
+    assert np.count_nonzero(ref) / ref.size > 0.005
+    assert np.abs(N(z[:1]) - ref).max() <= code_tol(ref)
+
+    # the batch gradient is the sum of the gradients of its halves
+    La, gda, gba, _ = grad(b[:8])
+    Lb, gdb, gbb, _ = grad(b[8:])
+    scale = max(np.abs(gd).max(), abs(gb))
+    assert abs(L - (La + Lb)) <= 1e-5 * abs(L)
+    assert np.abs(gd - (gda + gdb)).max() <= 1e-4 * scale
+    assert abs(gb - (gba + gbb)) <= 1e-4 * scale
+
+    # one image against the oracle's reverse pass
+    L0, gd0, gb0, _ = grad(b[:1])
+    Lr, gdr, gbr = oracle.code_loss_grad(b[:1], d0, cfg.beta, cfg.rho, cfg.t_in)
+    scale0 = max(np.abs(gdr).max(), abs(gbr))
+    assert abs(L0 - Lr) <= 1e-5 * abs(Lr)
+    assert np.abs(gd0 - gdr).max() <= GRAD_RTOL * scale0, np.abs(gd0 - gdr).max() / scale0
+    assert abs(gb0 - gbr) <= GRAD_RTOL * scale0
+
+
+def test_tensor_full_size_sampled(lib):
+    """32 RGB images 128^2, K=64 filters 11x11x3, 20 iterations: the first
+    and the last image against the oracle."""
+    cfg = synth.CONFIGS["tensor"]
+    b, d0 = synth.make_inputs(cfg)
+    z = N(lib.code(T(b), T(d0), cfg.beta, cfg.rho, cfg.t_in)[0])
+    for i in (0, cfg.n - 1):
+        ref = oracle.code(b[i:i + 1], d0, cfg.beta, cfg.rho, cfg.t_in)["z"]
+        assert np.count_nonzero(ref) / ref.size > 0.005
+        assert np.abs(z[i:i + 1] - ref).max() <= code_tol(ref), i
+
+
+def test_video_full_size(lib):
+    """One RGB volume 16 x 128 x 128, K=64 filters 3 x 11 x 11 x 3, 20
+    iterations (3-D grids take the axis-pass path)."""
+    cfg = synth.CONFIGS["video"]
+    b, d0 = synth.make_inputs(cfg)
+    z = N(lib.code(T(b), T(d0), cfg.beta, cfg.rho, cfg.t_in)[0])
+    ref = oracle.code(b, d0, cfg.beta, cfg.rho, cfg.t_in)["z"]
+    assert np.count_nonzero(ref) / ref.size > 0.005
+    assert np.abs(z - ref).max() <= code_tol(ref)
