@@ -19,7 +19,9 @@ else null.  ``cpu_baseline`` times the FP64 oracle on a bounded sample of
 the same step.
 
 ``--calibrate-copy MIB`` only runs a plain device copy of that size (the
-reference kernel for scaling the FETCH_SIZE / WRITE_SIZE counters).
+reference kernel for scaling the FETCH_SIZE / WRITE_SIZE counters);
+``--profile-leg`` runs only the timed calls of the batched leg or of the
+plain solver of the differentiable leg, for counter collection.
 """
 import argparse
 import json
@@ -71,28 +73,27 @@ def csrc_digest():
 
 
 def counter_traffic(kernel):
-    """HBM bytes per launch of `kernel` from profiles/learn_step_hbm_bytes.md
-    (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, scaled by the factors a
-    plain copy kernel gives), or None when the sources have changed since."""
-    path = os.path.join(ROOT, "profiles", "learn_step_hbm_bytes.md")
-    try:
-        lines = open(path).read().splitlines()
-    except OSError:
-        return None
-    kv, rows = {}, {}
-    for ln in lines:
-        ln = ln.strip()
-        if ln.startswith("csrc_sha256 = ") or ln.startswith("fetch_scale = ") or ln.startswith("write_scale = "):
-            key, val = ln.split(" = ", 1)
-            kv[key] = val.strip()
-        elif ln.startswith("kernel "):
-            parts = ln.split()
-            vals = dict(x.split("=") for x in parts[2:])
-            rows[parts[1]] = (float(vals["fetch_kib"]), float(vals["write_kib"]))
-    if kv.get("csrc_sha256") != csrc_digest() or kernel not in rows:
-        return None
-    fk, wk = rows[kernel]
-    return 1024.0 * (fk * float(kv["fetch_scale"]) + wk * float(kv["write_scale"]))
+    """HBM bytes per launch (or per call, for a whole leg) of `kernel` from the
+    counter summaries profiles/*_hbm_bytes.md (FETCH_SIZE and WRITE_SIZE in
+    KiB, scaled by the factors a plain copy kernel gives), or None when the
+    library sources have changed since the counters were taken."""
+    import glob
+    digest = csrc_digest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_hbm_bytes.md"))):
+        kv, rows = {}, {}
+        for ln in open(path).read().splitlines():
+            ln = ln.strip()
+            if ln.startswith(("csrc_sha256 = ", "fetch_scale = ", "write_scale = ")):
+                key, val = ln.split(" = ", 1)
+                kv[key] = val.strip()
+            elif ln.startswith("kernel "):
+                parts = ln.split()
+                vals = dict(x.split("=") for x in parts[2:])
+                rows[parts[1]] = (float(vals["fetch_kib"]), float(vals["write_kib"]))
+        if kernel in rows and kv.get("csrc_sha256") == digest:
+            fk, wk = rows[kernel]
+            return 1024.0 * (fk * float(kv["fetch_scale"]) + wk * float(kv["write_scale"]))
+    return None
 
 
 def calibrate_copy(mib):
@@ -107,7 +108,7 @@ def calibrate_copy(mib):
     print(json.dumps({"calibrate_copy_mib": mib, "bytes_each_way": n * 4}))
 
 
-def bench_batched(dc, synth, np, torch, n_images):
+def bench_batched(dc, synth, np, torch, n_images, plain=True):
     """Ragged batch: 256 images with sides drawn from 48..256 (padded to the
     next power of two), K = 64 shared 11x11 filters, beta = 1, rho = 10,
     30 ADMM iterations; one csc_code_batched call replayed from its hipGraph,
@@ -135,6 +136,22 @@ def bench_batched(dc, synth, np, torch, n_images):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
+    pix_pad = sum(g[0] * g[1] for g in grids)
+    pix_raw = sum(im.shape[1] * im.shape[2] for im in imgs)
+    bytes_iter = sum(alg_bytes_per_iter(c, 1, cfg.k, g[0] * g[1]) for g, c in classes)
+    out = {
+        "workload": "%d ragged images (sides 48..256, padded to powers of two), K=%d 11x11, beta=1, rho=10, "
+                    "%d iterations, hipGraph replay" % (len(imgs), cfg.k, it),
+        "grid_classes": [[g[0], g[1], c] for g, c in classes],
+        "ms_per_call": ms,
+        "cp_it_per_s_padded": cfg.k * pix_pad * it / (ms / 1e3),
+        "cp_it_per_s_unpadded": cfg.k * pix_raw * it / (ms / 1e3),
+        "alg_gbps": bytes_iter * it / (ms / 1e3) / 1e9,
+    }
+    traffic = counter_traffic("batched_call")
+    out["measured_gbps"] = None if traffic is None else traffic / (ms / 1e3) / 1e9
+    if not plain:
+        return out
     # plain solver, one call per image
     stack = [p[None] for p in padded]
     dc.code(stack[0], dt, cfg.beta, cfg.rho, it)
@@ -146,23 +163,12 @@ def bench_batched(dc, synth, np, torch, n_images):
     p1.record()
     torch.cuda.synchronize()
     ms_plain = p0.elapsed_time(p1)
-    pix_pad = sum(g[0] * g[1] for g in grids)
-    pix_raw = sum(im.shape[1] * im.shape[2] for im in imgs)
-    bytes_iter = sum(alg_bytes_per_iter(c, 1, cfg.k, g[0] * g[1]) for g, c in classes)
-    return {
-        "workload": "%d ragged images (sides 48..256, padded to powers of two), K=%d 11x11, beta=1, rho=10, "
-                    "%d iterations, hipGraph replay" % (len(imgs), cfg.k, it),
-        "grid_classes": [[g[0], g[1], c] for g, c in classes],
-        "ms_per_call": ms,
-        "cp_it_per_s_padded": cfg.k * pix_pad * it / (ms / 1e3),
-        "cp_it_per_s_unpadded": cfg.k * pix_raw * it / (ms / 1e3),
-        "alg_gbps": bytes_iter * it / (ms / 1e3) / 1e9,
-        "plain_per_image_ms": ms_plain,
-        "speedup_vs_plain": ms_plain / ms,
-    }
+    out["plain_per_image_ms"] = ms_plain
+    out["speedup_vs_plain"] = ms_plain / ms
+    return out
 
 
-def bench_backward(dc, synth, np, torch, reps=2):
+def bench_backward(dc, synth, np, torch, reps=2, only_plain=False):
     """Differentiable form: N = 16 images 256x256, K = 100 filters 11x11,
     30 unrolled ADMM iterations with checkpoints every 5, loss of eq:CSC;
     forward + backward (gradients w.r.t. filters and beta) against the plain
@@ -193,6 +199,10 @@ def bench_backward(dc, synth, np, torch, reps=2):
         return e0.elapsed_time(e1) / n
 
     ms_plain = timed(lambda: dc.code(bt, d, cfg.beta, cfg.rho, cfg.t_in), reps)
+    traffic = counter_traffic("unrolled_plain_call")
+    alg = alg_bytes_per_iter(cfg.n, cfg.j, cfg.k, cfg.grid[0] * cfg.grid[1]) * cfg.t_in
+    if only_plain:
+        return {"plain_code_ms": ms_plain}
     ms_fwd = timed(lambda: dc.unrolled_code(bt, d, cfg.beta, cfg.rho, cfg.t_in, 5), reps)
     ms_fb = timed(fwd_bwd, reps)
     cpit = cfg.n * cfg.k * cfg.grid[0] * cfg.grid[1] * cfg.t_in
@@ -203,6 +213,8 @@ def bench_backward(dc, synth, np, torch, reps=2):
         "forward_backward_ms": ms_fb,
         "backward_ms": ms_fb - ms_fwd,
         "plain_cp_it_per_s": cpit / (ms_plain / 1e3),
+        "plain_alg_gbps": alg / (ms_plain / 1e3) / 1e9,
+        "plain_measured_gbps": None if traffic is None else traffic / (ms_plain / 1e3) / 1e9,
         "forward_backward_vs_plain": ms_fb / ms_plain,
     }
 
@@ -218,6 +230,8 @@ def main():
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--batched-images", type=int, default=256)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB")
+    ap.add_argument("--profile-leg", choices=["batched", "unrolled-plain"], default=None,
+                    help="run only the timed calls of one leg (for counter collection)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on one GPU only (the build targets a single MI355X); "
@@ -235,6 +249,12 @@ def main():
     import synth
 
     dc.load()
+    if args.profile_leg == "batched":
+        print(json.dumps(bench_batched(dc, synth, np, torch, args.batched_images, plain=False)))
+        return
+    if args.profile_leg == "unrolled-plain":
+        print(json.dumps(bench_backward(dc, synth, np, torch, only_plain=True)))
+        return
     cfg = synth.CONFIGS["learn"]
     b, d0 = synth.make_inputs(cfg)
     dev = torch.device("cuda:0")
