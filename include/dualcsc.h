@@ -118,6 +118,29 @@ int csc_code(const csc_shape* shape, const float* b, const float* d, float beta,
              double* resid, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * csc_code with a stopping rule (the convergence-driven mode; the paper runs
+ * its solvers to convergence rather than for a fixed count).  Iterates as
+ * csc_code for at most max_iters iterations and stops after the first
+ * iteration at which every image has
+ *   r_pri  <= tol sqrt(K * grid size)   and   r_dual <= tol sqrt(J * grid size)
+ * (r_pri, r_dual as in `resid`: the primal and dual residual norms of the
+ * ADMM of eq:Inference_ADMM; i.e. both RMS residuals below tol, the
+ * criterion of Boyd et al. 2011, Sec. 3.3.1, with zero relative tolerance).
+ * The decision is taken on the device; the launches after it return at once.
+ *   tol         > 0, finite.
+ *   theta       if given, holds theta after the last iteration carried out.
+ *   resid       if given, rows [0, iterations done) are written.
+ *   iters_done  NULL or a device int: the number of iterations carried out
+ *               (max_iters if the rule never fired).
+ *   flags       CSC_ADAPTIVE_RHO, CSC_Z_ZERO, CSC_THETA_ZERO.
+ *   Errors: as csc_code, and CSC_EINVAL for tol <= 0 or not finite.
+ */
+int csc_code_tol(const csc_shape* shape, const float* b, const float* d, float beta,
+                 float* rho, int max_iters, float tol, unsigned flags, float* z,
+                 float* theta, double* resid, int* iters_done, void* ws,
+                 size_t ws_bytes, void* stream);
+
+/*
  * Learning subproblem (eq:Learning) in the dual: for fixed multipliers mu,
  *   gamma = -(I + sum_k 1/(2 mu_k) Z_k S^T S Z_k^T)^-1 x      (eq:Learning_gamma)
  * by `cg_iters` conjugate-gradient iterations warm-started from gamma, then
@@ -140,6 +163,22 @@ int csc_code(const csc_shape* shape, const float* b, const float* d, float beta,
 int csc_learn(const csc_shape* shape, const float* b, const float* z, float* d,
               float* mu, float* gamma, int inner_iters, int cg_iters,
               unsigned flags, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * csc_learn with a CG stopping rule: each multiplier step runs at most max_cg
+ * CG iterations and stops once ||r_j|| <= cg_tol ||x_j|| for every channel j
+ * (the residual of eq:Learning_gamma relative to its right-hand side; warm
+ * starts make this fire after a few iterations, which the paper reports as
+ * the reason the CG cost is negligible).  cg_tol = 0 runs max_cg iterations.
+ *   cg_counts  NULL or a device int array [inner_iters]: the CG iterations
+ *              carried out in each multiplier step.
+ *   flags      CSC_GAMMA_ZERO.
+ *   Errors: as csc_learn, and CSC_EINVAL for cg_tol < 0 or not finite.
+ */
+int csc_learn_tol(const csc_shape* shape, const float* b, const float* z, float* d,
+                  float* mu, float* gamma, int inner_iters, int max_cg, float cg_tol,
+                  unsigned flags, int* cg_counts, void* ws, size_t ws_bytes,
+                  void* stream);
 
 /*
  * Objective of eq:CSC for given (d, z), summed over channels:

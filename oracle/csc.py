@@ -124,7 +124,7 @@ def _adapt_rho(rho, r_pri, r_dual, mu_b, tau_b):
 
 
 def code(b, d, beta, rho, iters, z0=None, theta0=None, adaptive=False,
-         rho_schedule=None, mu_b=10.0, tau_b=2.0):
+         rho_schedule=None, mu_b=10.0, tau_b=2.0, tol=None):
     """Coding subproblem by ADMM on its dual (eq:Inference_Dual,
     eq:Inference_ADMM), literal updates of eq:Inference_solution in the
     Fourier domain, run for a fixed number of iterations per image (the coding
@@ -139,7 +139,11 @@ def code(b, d, beta, rho, iters, z0=None, theta0=None, adaptive=False,
 
     rho: scalar or [N] (initial value).  ``rho_schedule`` [iters+1][N], if
     given, replaces the step used at each iteration (to replay a schedule).
-    Returns dict(z, theta, resid [iters][N][2], rho [iters+1][N]).
+    ``tol`` (convergence-driven mode): stop after the first iteration at which
+    every image has r_pri <= tol sqrt(K D) and r_dual <= tol sqrt(J D), i.e.
+    both RMS residuals at most tol (Boyd et al. 2011, Sec. 3.3.1, with zero
+    relative tolerance); ``iters`` is then the largest count.
+    Returns dict(z, theta, resid [done][N][2], rho [done+1][N], iters = done).
     """
     b = np.asarray(b, _f64)
     N, J = b.shape[:2]
@@ -178,9 +182,14 @@ def code(b, d, beta, rho, iters, z0=None, theta0=None, adaptive=False,
             rho_v = _adapt_rho(rho_v, r_pri, r_dual, mu_b, tau_b)
         sched.append(rho_v.copy())
         z, th = z_new, th_new
+        if tol is not None:
+            npix = float(np.prod(grid))
+            if np.all(r_pri <= tol * np.sqrt(K * npix)) and np.all(r_dual <= tol * np.sqrt(J * npix)):
+                break
+    done = len(resid)
     return {"z": z, "theta": th,
-            "resid": np.array(resid).reshape(iters, N, 2),
-            "rho": np.array(sched)}
+            "resid": np.array(resid).reshape(done, N, 2),
+            "rho": np.array(sched), "iters": done}
 
 
 def code_implicit(b, d, beta, rho, iters, z0=None, theta0=None):
@@ -227,28 +236,42 @@ def code_implicit(b, d, beta, rho, iters, z0=None, theta0=None):
     return {"z": z, "theta": theta}
 
 
-def _cg(apply_a, rhs, x0, iters):
+def _cg(apply_a, rhs, x0, iters, tol=None):
     """Conjugate gradient (Hestenes-Stiefel) for the SPD system of
-    eq:Learning_gamma, warm-started at x0, for a fixed number of iterations.
-    A zero residual or zero curvature stops the updates (step 0)."""
-    x = x0.copy()
-    r = rhs - apply_a(x)
-    p = r.copy()
-    rr = float((r * r).sum())
+    eq:Learning_gamma, one independent system per channel (rhs and x0 are
+    lists over channels, all stepped together), warm-started at x0, for
+    ``iters`` iterations.  A zero residual or zero curvature stops the updates
+    of that channel (step 0).  With ``tol`` the solve ends before any step
+    once every channel has ||r_j|| <= tol ||rhs_j||.  Returns (x, steps)."""
+    J = len(rhs)
+    x = [x0[j].copy() for j in range(J)]
+    r = [rhs[j] - apply_a(x[j]) for j in range(J)]
+    p = [r[j].copy() for j in range(J)]
+    rr = [float((r[j] * r[j]).sum()) for j in range(J)]
+    bb = [float((rhs[j] * rhs[j]).sum()) for j in range(J)]
+
+    def converged():
+        return tol is not None and all(rr[j] <= tol * tol * bb[j] for j in range(J))
+
+    steps = 0
     for _ in range(iters):
-        ap = apply_a(p)
-        pap = float((p * ap).sum())
-        alpha = rr / pap if pap > 0 else 0.0
-        x = x + alpha * p
-        r = r - alpha * ap
-        rr_new = float((r * r).sum())
-        beta_cg = rr_new / rr if rr > 0 else 0.0
-        p = r + beta_cg * p
-        rr = rr_new
-    return x
+        if converged():
+            break
+        for j in range(J):
+            ap = apply_a(p[j])
+            pap = float((p[j] * ap).sum())
+            alpha = rr[j] / pap if pap > 0 else 0.0
+            x[j] = x[j] + alpha * p[j]
+            r[j] = r[j] - alpha * ap
+            rr_new = float((r[j] * r[j]).sum())
+            beta_cg = rr_new / rr[j] if rr[j] > 0 else 0.0
+            p[j] = r[j] + beta_cg * p[j]
+            rr[j] = rr_new
+        steps += 1
+    return x, steps
 
 
-def learn(b, z, fsupp, mu, gamma=None, inner_iters=10, cg_iters=10):
+def learn(b, z, fsupp, mu, gamma=None, inner_iters=10, cg_iters=10, cg_tol=None, info=None):
     """Learning subproblem in the dual (eq:Learning_Dual .. eq:mu_update).
 
     For fixed multipliers mu, gamma solves (eq:Learning_gamma)
@@ -263,7 +286,12 @@ def learn(b, z, fsupp, mu, gamma=None, inner_iters=10, cg_iters=10):
 
     After the last multiplier update the filters are scaled into the unit
     ball, d_k / max(1, ||d_k||) (the constraint of eq:Learning).  A filter
-    whose norm is exactly zero leaves its multiplier unchanged.
+    whose norm is exactly zero leaves its multiplier unchanged.  With
+    ``cg_tol`` each CG solve ends once every channel's residual is at most
+    cg_tol times its right-hand side (``cg_iters`` is then the largest count;
+    it may also be a list with one count per multiplier update);
+    ``info``, if a dict, receives the CG steps of each multiplier update
+    under "cg_counts".
     Returns (d [K][J][*fsupp], mu [K], gamma [N][J][*grid]).
     """
     b = np.asarray(b, _f64)
@@ -291,25 +319,35 @@ def learn(b, z, fsupp, mu, gamma=None, inner_iters=10, cg_iters=10):
         return apply_a
 
     d = np.zeros((K, J) + tuple(fsupp))
-    for _ in range(inner_iters):
+    counts = []
+    its = list(cg_iters) if np.ndim(cg_iters) else [cg_iters] * inner_iters
+    for it in range(inner_iters):
         apply_a = make_a(mu)
+        g, steps = _cg(apply_a, [-b[:, j] for j in range(J)], [gamma[:, j] for j in range(J)], its[it], cg_tol)
+        counts.append(steps)
         for j in range(J):
-            gamma[:, j] = _cg(apply_a, -b[:, j], gamma[:, j], cg_iters)
+            gamma[:, j] = g[j]
             d[:, j] = -crop(zt(gamma[:, j]), fsupp) / (2.0 * mu).reshape(kshape)
         nrm = np.sqrt((d.reshape(K, -1) ** 2).sum(axis=1))
         mu = np.where(nrm > 0, mu * nrm, mu)
     nrm = np.sqrt((d.reshape(K, -1) ** 2).sum(axis=1))
     d = d / np.maximum(1.0, nrm).reshape((K,) + (1,) * (d.ndim - 1))
+    if isinstance(info, dict):
+        info["cg_counts"] = counts
     return d, mu, gamma
 
 
 def learn_dictionary(b, d0, beta, rho, t_in, t_out, inner_iters=10, cg_iters=10,
-                     adaptive=False):
+                     adaptive=False, tau=None, tol=None, cg_tol=None):
     """Alg. 1 (coordinate descent between the two dual subproblems): z and
     theta start at zero and are carried (warm) into every later coding call,
     d starts from d0, mu at 1 and gamma at 0; each outer step codes, then
-    learns.  Returns dict(d, z, theta, mu, gamma, objectives) where
-    objectives lists f(d, z) after each half step."""
+    learns.  Convergence-driven mode: ``tau`` ends the alternation after the
+    first outer step whose objective (after learning) changed by at most tau
+    relative to the previous step's (Sec. 4); ``tol`` and ``cg_tol`` are the
+    stopping rules of code() and learn().  Returns dict(d, z, theta, mu,
+    gamma, objectives, steps) where objectives lists f(d, z) after each half
+    step and steps is the number of outer steps taken."""
     b = np.asarray(b, _f64)
     d = np.asarray(d0, _f64)
     N = b.shape[0]
@@ -320,16 +358,20 @@ def learn_dictionary(b, d0, beta, rho, t_in, t_out, inner_iters=10, cg_iters=10,
     gamma = np.zeros_like(b)
     rho_v = np.broadcast_to(np.asarray(rho, _f64), (N,)).copy()
     objs = []
+    steps = 0
     for _ in range(t_out):
-        out = code(b, d, beta, rho_v, t_in, z, theta, adaptive=adaptive)
+        out = code(b, d, beta, rho_v, t_in, z, theta, adaptive=adaptive, tol=tol)
         z, theta = out["z"], out["theta"]
         if adaptive:
             rho_v = out["rho"][-1]
         objs.append(objective(b, d, z, beta)[1])
-        d, mu, gamma = learn(b, z, fsupp, mu, gamma, inner_iters, cg_iters)
+        d, mu, gamma = learn(b, z, fsupp, mu, gamma, inner_iters, cg_iters, cg_tol)
         objs.append(objective(b, d, z, beta)[1])
+        steps += 1
+        if tau is not None and len(objs) >= 4 and abs(objs[-1] - objs[-3]) <= tau * abs(objs[-3]):
+            break
     return {"d": d, "z": z, "theta": theta, "mu": mu, "gamma": gamma,
-            "objectives": objs}
+            "objectives": objs, "steps": steps}
 
 
 def objective_grad(b, d, z, beta):

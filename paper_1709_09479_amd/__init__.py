@@ -20,6 +20,7 @@ __all__ = [
     "DualCSCError", "load", "lib_path", "Shape", "code", "learn", "objective",
     "learn_dictionary", "workspace_bytes", "trace_enable", "trace_read", "ADAPTIVE_RHO", "Z_ZERO", "THETA_ZERO",
     "GAMMA_ZERO", "USE_GRAPH", "PackedBatch", "code_batched", "autotune_batched", "unrolled_code", "csc_loss",
+    "code_until", "learn_until",
 ]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -103,6 +104,10 @@ def load() -> ctypes.CDLL:
     lib.csc_code.argtypes = [sp, vp, vp, f32, vp, i32, u32, vp, vp, vp, vp, sz, vp]
     lib.csc_learn.restype = i32
     lib.csc_learn.argtypes = [sp, vp, vp, vp, vp, vp, i32, i32, u32, vp, sz, vp]
+    lib.csc_code_tol.restype = i32
+    lib.csc_code_tol.argtypes = [sp, vp, vp, f32, vp, i32, f32, u32, vp, vp, vp, vp, vp, sz, vp]
+    lib.csc_learn_tol.restype = i32
+    lib.csc_learn_tol.argtypes = [sp, vp, vp, vp, vp, vp, i32, i32, f32, u32, vp, vp, sz, vp]
     lib.csc_objective.restype = i32
     lib.csc_objective.argtypes = [sp, vp, vp, vp, f32, vp, vp, sz, vp]
     lib.csc_trace_enable.restype = i32
@@ -289,6 +294,73 @@ def learn(b, z, fsupp: Sequence[int], mu=None, gamma=None, inner_iters: int = 10
     return d, mu, gamma
 
 
+def code_until(b, d, beta: float, rho, max_iters: int, tol: float, z=None, theta=None, adaptive: bool = False,
+               want_theta: bool = False, want_resid: bool = False):
+    """ADMM coding until every image's RMS primal and dual residuals are at
+    most ``tol`` (at most ``max_iters`` iterations; the decision is taken on
+    the device).  Returns (z, theta or None, resid [done][N][3] or None, rho
+    tensor, done)."""
+    torch = _torch()
+    lib = load()
+    _need(b, "b")
+    _need(d, "d")
+    shape = _shape_of(b, d)
+    N, K = b.shape[0], d.shape[0]
+    dev = b.device
+    flags = ADAPTIVE_RHO if adaptive else 0
+    if z is None:
+        z = torch.empty((N, K) + tuple(b.shape[2:]), dtype=torch.float32, device=dev)
+        flags |= Z_ZERO
+    _need(z, "z")
+    if theta is None and want_theta:
+        theta = torch.empty_like(z)
+        flags |= THETA_ZERO
+    if theta is not None:
+        _need(theta, "theta")
+    rho_t = rho if isinstance(rho, torch.Tensor) else torch.full((N,), float(rho), dtype=torch.float32, device=dev)
+    _need(rho_t, "rho")
+    resid = torch.empty((max_iters, N, 3), dtype=torch.float64, device=dev) if (want_resid and max_iters > 0) else None
+    done = torch.zeros(1, dtype=torch.int32, device=dev)
+    ws, nbytes = _workspace(shape, OP_CODE, flags, dev)
+    st = torch.cuda.current_stream(dev).cuda_stream
+    _check(lib.csc_code_tol(ctypes.byref(shape), _ptr(b), _ptr(d), float(beta), _ptr(rho_t), int(max_iters),
+                            float(tol), flags, _ptr(z), _ptr(theta), _ptr(resid), _ptr(done), ws, nbytes,
+                            ctypes.c_void_p(st)))
+    n_done = int(done.item())
+    return z, theta, (resid[:n_done] if resid is not None else None), rho_t, n_done
+
+
+def learn_until(b, z, fsupp: Sequence[int], mu=None, gamma=None, inner_iters: int = 10, max_cg: int = 10,
+                cg_tol: float = 1e-3, out=None):
+    """Dual dictionary learning whose CG solves stop once every channel's
+    residual is at most ``cg_tol`` times its right-hand side.  Returns (d,
+    mu, gamma, CG steps per multiplier update as a list)."""
+    torch = _torch()
+    lib = load()
+    _need(b, "b")
+    _need(z, "z")
+    N, J, K = b.shape[0], b.shape[1], z.shape[1]
+    dev = b.device
+    fsupp = tuple(int(s) for s in fsupp)
+    shape = Shape.make(N, J, K, tuple(b.shape[2:]), fsupp)
+    flags = 0
+    if mu is None:
+        mu = torch.ones(K, dtype=torch.float32, device=dev)
+    if gamma is None:
+        gamma = torch.empty_like(b)
+        flags |= GAMMA_ZERO
+    _need(mu, "mu")
+    _need(gamma, "gamma")
+    d = out if out is not None else torch.empty((K, J) + fsupp, dtype=torch.float32, device=dev)
+    _need(d, "out")
+    counts = torch.zeros(inner_iters, dtype=torch.int32, device=dev)
+    ws, nbytes = _workspace(shape, OP_LEARN, flags, dev)
+    st = torch.cuda.current_stream(dev).cuda_stream
+    _check(lib.csc_learn_tol(ctypes.byref(shape), _ptr(b), _ptr(z), _ptr(d), _ptr(mu), _ptr(gamma), int(inner_iters),
+                             int(max_cg), float(cg_tol), flags, _ptr(counts), ws, nbytes, ctypes.c_void_p(st)))
+    return d, mu, gamma, [int(c) for c in counts.cpu()]
+
+
 def objective(b, d, z, beta: float):
     """eq:CSC objective: returns a float64 tensor [N + 1] (per image, total)."""
     torch = _torch()
@@ -325,11 +397,19 @@ def trace_read(cls: int) -> Tuple[float, int]:
 
 
 def learn_dictionary(b, d0, beta: float, rho, t_in: int, t_out: int, inner_iters: int = 10,
-                     cg_iters: int = 10, adaptive: bool = False, log_objective: bool = True):
+                     cg_iters: int = 10, adaptive: bool = False, log_objective: bool = True, tau=None, tol=None,
+                     cg_tol=None):
     """Alg. 1: alternate coding (warm-started z, theta) and learning
     (warm-started gamma, carried mu) for ``t_out`` outer steps.  Returns a dict
-    with d, z, theta, mu, gamma, rho and the objective after each half step
-    (float64 device tensors, read back only at the end)."""
+    with d, z, theta, mu, gamma, rho, the objective after each half step
+    (float64 device tensors) and the number of outer steps taken.
+
+    Convergence-driven mode: ``tau`` stops the alternation after the first
+    outer step whose objective (after learning) changed by at most tau
+    relative to the previous step's (this reads the objective back each
+    step); ``tol`` and ``cg_tol`` are the stopping rules of code_until and
+    learn_until (then ``t_in`` and ``cg_iters`` are the largest counts, and
+    the counts taken are returned under "coding_iters" and "cg_counts")."""
     torch = _torch()
     N, K = b.shape[0], d0.shape[0]
     d = d0.clone()
@@ -338,16 +418,37 @@ def learn_dictionary(b, d0, beta: float, rho, t_in: int, t_out: int, inner_iters
     mu = torch.ones(K, dtype=torch.float32, device=b.device)
     rho_t = rho if isinstance(rho, torch.Tensor) else torch.full((N,), float(rho), dtype=torch.float32,
                                                                  device=b.device)
-    objs = []
+    objs, code_its, cg_counts = [], [], []
+    log_objective = log_objective or tau is not None
+    steps = 0
     for _ in range(t_out):
-        z, theta, _, rho_t = code(b, d, beta, rho_t, t_in, z=z, theta=theta, adaptive=adaptive, want_theta=True)
+        if tol is not None:
+            z, theta, _, rho_t, n = code_until(b, d, beta, rho_t, t_in, tol, z=z, theta=theta, adaptive=adaptive,
+                                                want_theta=True)
+            code_its.append(n)
+        else:
+            z, theta, _, rho_t = code(b, d, beta, rho_t, t_in, z=z, theta=theta, adaptive=adaptive, want_theta=True)
         if log_objective:
             objs.append(objective(b, d, z, beta)[-1:].clone())
-        d, mu, gamma = learn(b, z, fsupp, mu, gamma, inner_iters, cg_iters)
+        if cg_tol is not None:
+            d, mu, gamma, c = learn_until(b, z, fsupp, mu, gamma, inner_iters, cg_iters, cg_tol)
+            cg_counts.append(c)
+        else:
+            d, mu, gamma = learn(b, z, fsupp, mu, gamma, inner_iters, cg_iters)
         if log_objective:
             objs.append(objective(b, d, z, beta)[-1:].clone())
-    return {"d": d, "z": z, "theta": theta, "mu": mu, "gamma": gamma, "rho": rho_t,
-            "objectives": torch.cat(objs) if objs else None}
+        steps += 1
+        if tau is not None and len(objs) >= 4:
+            f_new, f_old = float(objs[-1].item()), float(objs[-3].item())
+            if abs(f_new - f_old) <= tau * abs(f_old):
+                break
+    out = {"d": d, "z": z, "theta": theta, "mu": mu, "gamma": gamma, "rho": rho_t,
+           "objectives": torch.cat(objs) if objs else None, "steps": steps}
+    if tol is not None:
+        out["coding_iters"] = code_its
+    if cg_tol is not None:
+        out["cg_counts"] = cg_counts
+    return out
 
 
 # ------------------------------------------------------------------ batched

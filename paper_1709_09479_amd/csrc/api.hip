@@ -3,6 +3,7 @@
 #include <string.h>
 
 #include <map>
+#include <cmath>
 #include <mutex>
 #include <vector>
 
@@ -11,12 +12,14 @@
 namespace dcsc {
 
 int run_code(const Plan& pl, const float* b, const float* d, float beta, float* rho, int iters, unsigned flags,
-             float* z, float* theta, double* resid, void* ws, hipStream_t st);
+             float* z, float* theta, double* resid, void* ws, hipStream_t st, float tol = 0.0f,
+             int* iters_done = nullptr);
 size_t run_code_ws(const Plan& pl);
 int run_objective(const Plan& pl, const float* b, const float* d, const float* z, float beta, double* out, void* ws,
                   hipStream_t st);
 int run_learn(const Plan& pl, const float* b, const float* z, float* d, float* mu, float* gamma, int inner_iters,
-              int cg_iters, unsigned flags, void* ws, hipStream_t st);
+              int cg_iters, unsigned flags, void* ws, hipStream_t st, float cg_tol = 0.0f,
+              int* cg_counts = nullptr);
 size_t run_learn_ws(const Plan& pl);
 size_t run_diff_ws(const Plan& pl, int every);
 int run_unrolled(const Plan& pl, const float* b, const float* d, float beta, const float* rho, int iters, int every,
@@ -308,6 +311,35 @@ int csc_learn(const csc_shape* shape, const float* b, const float* z, float* d, 
                       return run_learn(*c->pl, c->b, c->z, c->d, c->mu, c->gamma, c->li, c->ci, c->f, c->ws, c->st);
                     },
                     &c);
+}
+
+int csc_code_tol(const csc_shape* shape, const float* b, const float* d, float beta, float* rho, int max_iters,
+                 float tol, unsigned flags, float* z, float* theta, double* resid, int* iters_done, void* ws,
+                 size_t ws_bytes, void* stream) {
+  Plan pl;
+  int rc = make_plan(shape, &pl);
+  if (rc != CSC_OK) return rc;
+  if (!b || !d || !rho || !z || max_iters < 0 || !(beta >= 0.0f) || !(tol > 0.0f) || !std::isfinite(tol))
+    return CSC_EINVAL;
+  if (flags & ~(CSC_ADAPTIVE_RHO | CSC_Z_ZERO | CSC_THETA_ZERO)) return CSC_EINVAL;
+  if ((rc = check_ws(ws, ws_bytes, run_code_ws(pl))) != CSC_OK) return rc;
+  return run_code(pl, b, d, beta, rho, max_iters, flags, z, theta, resid, ws, static_cast<hipStream_t>(stream), tol,
+                  iters_done);
+}
+
+int csc_learn_tol(const csc_shape* shape, const float* b, const float* z, float* d, float* mu, float* gamma,
+                  int inner_iters, int max_cg, float cg_tol, unsigned flags, int* cg_counts, void* ws,
+                  size_t ws_bytes, void* stream) {
+  Plan pl;
+  int rc = make_plan(shape, &pl);
+  if (rc != CSC_OK) return rc;
+  if (!b || !z || !d || !mu || !gamma || inner_iters < 1 || max_cg < 0 || !(cg_tol >= 0.0f) ||
+      !std::isfinite(cg_tol))
+    return CSC_EINVAL;
+  if (flags & ~CSC_GAMMA_ZERO) return CSC_EINVAL;
+  if ((rc = check_ws(ws, ws_bytes, run_learn_ws(pl))) != CSC_OK) return rc;
+  return run_learn(pl, b, z, d, mu, gamma, inner_iters, max_cg, flags, ws, static_cast<hipStream_t>(stream), cg_tol,
+                   cg_counts);
 }
 
 size_t csc_unrolled_workspace_bytes(const csc_shape* shape, int every) {

@@ -265,7 +265,8 @@ __device__ __forceinline__ void dual_solve(const float2* __restrict__ Gf, float 
 template <int J>
 __global__ void k_solve(const float2* __restrict__ G, const float2* __restrict__ xh, const float2* __restrict__ yh,
                         const float2* __restrict__ Th, const float* __restrict__ rho_cur, float2* __restrict__ lam,
-                        int64_t D) {
+                        int64_t D, const int* __restrict__ stop) {
+  if (stop && stop[0]) return;
   const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int n = blockIdx.y;
   if (f >= D) return;
@@ -292,7 +293,9 @@ __global__ __launch_bounds__(kEW) void k_spec(const float2* __restrict__ part, c
                                               const float2* __restrict__ xh, float2* __restrict__ yh,
                                               float2* __restrict__ Th, float2* __restrict__ lam,
                                               const float* __restrict__ rho_cur, double* __restrict__ rdual,
-                                              int ng, int T, int H, int W, int solve_next) {
+                                              int ng, int T, int H, int W, int solve_next,
+                                              const int* __restrict__ stop) {
+  if (stop && stop[0]) return;
   __shared__ double red[kEW / 64];
   const int64_t D = int64_t(T) * H * W;
   const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -352,7 +355,9 @@ __global__ __launch_bounds__(kEW) void k_spec(const float2* __restrict__ part, c
 // sqrt(sum |dThhat|^2 / D).  Partial sums are added in a fixed order.
 __global__ __launch_bounds__(64) void k_rho(const double* __restrict__ rpri, int npri,
                                             const double* __restrict__ rdual, int ndual, float* __restrict__ rho_cur,
-                                            double* __restrict__ resid, int it, int N, int64_t D, int adaptive) {
+                                            double* __restrict__ resid, int it, int N, int64_t D, int adaptive,
+                                            const int* __restrict__ stop, double* __restrict__ rres) {
+  if (stop && stop[0]) return;
   const int n = blockIdx.x, lane = threadIdx.x;
   double sp = 0.0, sd = 0.0;
   for (int i = lane; i < npri; i += 64) sp += rpri[int64_t(n) * npri + i];
@@ -372,12 +377,42 @@ __global__ __launch_bounds__(64) void k_rho(const double* __restrict__ rpri, int
     o[1] = r_dual;
     o[2] = (double)rho;
   }
+  if (rres) {
+    rres[2 * n] = r_pri;
+    rres[2 * n + 1] = r_dual;
+  }
   if (adaptive) {
     float nr = rho;
     if (r_pri > 10.0 * r_dual) nr = rho * 2.0f;
     else if (r_dual > 10.0 * r_pri) nr = rho * 0.5f;
     rho_cur[n] = nr;
   }
+}
+
+// Stopping rule of the tolerance mode (Boyd et al. 2011, Sec. 3.3.1 with a
+// zero relative tolerance): every image has r_pri <= thr_pri and r_dual <=
+// thr_dual (the RMS residuals times sqrt of the entry counts).  stop[0] is
+// the flag every later kernel of the call checks; stop[1] counts the
+// iterations carried out.
+__global__ void k_stop(const double* __restrict__ rres, int N, double thr_pri, double thr_dual,
+                       int* __restrict__ stop) {
+  if (blockIdx.x != 0 || threadIdx.x != 0 || stop[0]) return;
+  stop[1] += 1;
+  bool done = true;
+  for (int n = 0; n < N; ++n) done = done && rres[2 * n] <= thr_pri && rres[2 * n + 1] <= thr_dual;
+  if (done) stop[0] = 1;
+}
+
+__global__ void k_stop_init(int* __restrict__ stop) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) stop[0] = stop[1] = 0;
+}
+
+__global__ void k_stop_out(const int* __restrict__ stop, int* __restrict__ out) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[0] = stop[1];
+}
+
+__global__ void k_fill_i(int* __restrict__ out, int v) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[0] = v;
 }
 
 // ------------------------------------------------------- fused tile kernel
@@ -414,7 +449,9 @@ template <int H, int W, int J, int MODE>
 __global__ __launch_bounds__(fused_threads(H * W, J)) void k_fused(
     const float2* __restrict__ E, const float2* __restrict__ lam, float* __restrict__ z,
     float* __restrict__ theta, const int64_t* __restrict__ zoff, const float* __restrict__ rho_cur, float beta,
-    float2* __restrict__ part, double* __restrict__ rpart, int K, int P, int ppg, int ng) {
+    float2* __restrict__ part, double* __restrict__ rpart, int K, int P, int ppg, int ng,
+    const int* __restrict__ stop) {
+  if (stop && stop[0]) return;
   constexpr int D = H * W, NT = fused_threads(D, J), WP = tile_stride(W);
   using PL = TilePlan<H, W, NT, WP>;
   using P1 = typename PL::InvRow0;
@@ -577,7 +614,8 @@ __global__ __launch_bounds__(fused_threads(H * W, J)) void k_fused(
 // buf[n][p](f) = sum_j lam_j(f) E_jp(f)
 template <int J>
 __global__ void k_make_v(const float2* __restrict__ E, const float2* __restrict__ lam, float2* __restrict__ buf,
-                         int P, int64_t D) {
+                         int P, int64_t D, const int* __restrict__ stop) {
+  if (stop && stop[0]) return;
   const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int p = blockIdx.y, n = blockIdx.z;
   if (f >= D) return;
@@ -592,7 +630,9 @@ __global__ void k_make_v(const float2* __restrict__ E, const float2* __restrict_
 __global__ __launch_bounds__(kEW) void k_spatial(float2* __restrict__ buf, float* __restrict__ z,
                                                  float* __restrict__ theta, const int64_t* __restrict__ zoff,
                                                  const float* __restrict__ rho_cur,
-                                                 float beta, double* __restrict__ rpart, int K, int P, int64_t D) {
+                                                 float beta, double* __restrict__ rpart, int K, int P, int64_t D,
+                                                 const int* __restrict__ stop) {
+  if (stop && stop[0]) return;
   __shared__ double red[kEW / 64];
   const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int p = blockIdx.y, n = blockIdx.z;
@@ -627,7 +667,8 @@ __global__ __launch_bounds__(kEW) void k_spatial(float2* __restrict__ buf, float
 // part[n][0][j](f) = sum_p buf[n][p](f) conj(E_jp(f))
 template <int J>
 __global__ void k_accum(const float2* __restrict__ buf, const float2* __restrict__ E, float2* __restrict__ part,
-                        int P, int64_t D) {
+                        int P, int64_t D, const int* __restrict__ stop) {
+  if (stop && stop[0]) return;
   const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int n = blockIdx.y;
   if (f >= D) return;
@@ -704,13 +745,14 @@ static unsigned nblk(int64_t n, int b = kEW) { return (unsigned)((n + b - 1) / b
 
 template <int J, int MODE>
 static bool fused_launch(const Plan& pl, const float2* E, const float2* lam, float* z, float* theta,
-                         const float* rho, float beta, float2* part, double* rpart, hipStream_t st) {
+                         const float* rho, float beta, float2* part, double* rpart, hipStream_t st,
+                         const int* stop) {
   const dim3 grid(pl.ng * pl.n);
   const int h = pl.g[1], w = pl.g[2];
 #define FL(HH, WW)                                                                                         \
   if (h == HH && w == WW) {                                                                                \
     hipLaunchKernelGGL((k_fused<HH, WW, J, MODE>), grid, dim3(fused_threads(HH * WW, J)), 0, st, E, lam, z, \
-                       theta, pl.zoff, rho, beta, part, rpart, pl.k, pl.p, pl.ppg, pl.ng);               \
+                       theta, pl.zoff, rho, beta, part, rpart, pl.k, pl.p, pl.ppg, pl.ng, stop);         \
     return true;                                                                                           \
   }
   FL(16, 16) FL(16, 32) FL(16, 64) FL(16, 128) FL(16, 256)
@@ -724,10 +766,11 @@ static bool fused_launch(const Plan& pl, const float2* E, const float2* lam, flo
 
 template <int MODE>
 static bool fused_dispatch(const Plan& pl, const float2* E, const float2* lam, float* z, float* theta,
-                           const float* rho, float beta, float2* part, double* rpart, hipStream_t st) {
-  if (pl.j == 1) return fused_launch<1, MODE>(pl, E, lam, z, theta, rho, beta, part, rpart, st);
-  if (pl.j == 2) return fused_launch<2, MODE>(pl, E, lam, z, theta, rho, beta, part, rpart, st);
-  return fused_launch<3, MODE>(pl, E, lam, z, theta, rho, beta, part, rpart, st);
+                           const float* rho, float beta, float2* part, double* rpart, hipStream_t st,
+                           const int* stop = nullptr) {
+  if (pl.j == 1) return fused_launch<1, MODE>(pl, E, lam, z, theta, rho, beta, part, rpart, st, stop);
+  if (pl.j == 2) return fused_launch<2, MODE>(pl, E, lam, z, theta, rho, beta, part, rpart, st, stop);
+  return fused_launch<3, MODE>(pl, E, lam, z, theta, rho, beta, part, rpart, st, stop);
 }
 
 size_t carve_code(const Plan& pl, void* base, CodeWs* w) {
@@ -748,6 +791,8 @@ size_t carve_code(const Plan& pl, void* base, CodeWs* w) {
   w->rdual = c.take<double>(N * w->ndual);
   w->opart = c.take<double>(N * w->ndual);
   w->rho = c.take<float>(N);
+  w->rres = c.take<double>(2 * N);
+  w->stop = c.take<int>(2);
   return c.off;
 }
 
@@ -782,38 +827,40 @@ hipError_t forward_maps(const Plan& pl, const float* maps, CodeWs& w, double* l1
     return hipGetLastError();
   }
   if (pl.split)
-    return split_maps(pl, w.E, w.lam, w.buf, const_cast<float*>(maps), nullptr, w.rho, 0.f, w.part, l1, 1, st);
+    return split_maps(pl, w.E, w.lam, w.buf, const_cast<float*>(maps), nullptr, w.rho, 0.f, w.part, l1, 1, st,
+                      nullptr);
   hipLaunchKernelGGL(k_pack_maps, dim3(nblk(D), pl.p, pl.n), dim3(kEW), 0, st, maps, pl.zoff, w.buf, l1, pl.k,
                      pl.p, D);
   hipError_t e = fft_grids(w.buf, int64_t(pl.n) * pl.p, pl.g, -1, st);
   if (e != hipSuccess) return e;
-  LAUNCH_J(k_accum, pl.j, dim3(nblk(D), pl.n), dim3(kEW), st, w.buf, w.E, w.part, pl.p, D);
+  LAUNCH_J(k_accum, pl.j, dim3(nblk(D), pl.n), dim3(kEW), st, w.buf, w.E, w.part, pl.p, D, nullptr);
   return hipGetLastError();
 }
 
 // One ADMM iteration's map work: back-projection, soft threshold, forward.
-static hipError_t iterate_maps(const Plan& pl, CodeWs& w, float* z, float* theta, float beta, hipStream_t st) {
+static hipError_t iterate_maps(const Plan& pl, CodeWs& w, float* z, float* theta, float beta, hipStream_t st,
+                               const int* stop) {
   const int64_t D = pl.dsz;
   TraceScope trace(kTraceCodeMaps, st);
   if (pl.lds) {
-    if (!fused_dispatch<kModeIter>(pl, w.E, w.lam, z, theta, w.rho, beta, w.part, w.rpri, st))
+    if (!fused_dispatch<kModeIter>(pl, w.E, w.lam, z, theta, w.rho, beta, w.part, w.rpri, st, stop))
       return hipErrorInvalidValue;
     return hipGetLastError();
   }
-  if (pl.split) return split_maps(pl, w.E, w.lam, w.buf, z, theta, w.rho, beta, w.part, w.rpri, 0, st);
-  LAUNCH_J(k_make_v, pl.j, dim3(nblk(D), pl.p, pl.n), dim3(kEW), st, w.E, w.lam, w.buf, pl.p, D);
+  if (pl.split) return split_maps(pl, w.E, w.lam, w.buf, z, theta, w.rho, beta, w.part, w.rpri, 0, st, stop);
+  LAUNCH_J(k_make_v, pl.j, dim3(nblk(D), pl.p, pl.n), dim3(kEW), st, w.E, w.lam, w.buf, pl.p, D, stop);
   hipError_t e = fft_grids(w.buf, int64_t(pl.n) * pl.p, pl.g, +1, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_spatial, dim3(nblk(D), pl.p, pl.n), dim3(kEW), 0, st, w.buf, z, theta, pl.zoff, w.rho, beta,
-                     w.rpri, pl.k, pl.p, D);
+                     w.rpri, pl.k, pl.p, D, stop);
   e = fft_grids(w.buf, int64_t(pl.n) * pl.p, pl.g, -1, st);
   if (e != hipSuccess) return e;
-  LAUNCH_J(k_accum, pl.j, dim3(nblk(D), pl.n), dim3(kEW), st, w.buf, w.E, w.part, pl.p, D);
+  LAUNCH_J(k_accum, pl.j, dim3(nblk(D), pl.n), dim3(kEW), st, w.buf, w.E, w.part, pl.p, D, stop);
   return hipGetLastError();
 }
 
 int run_code(const Plan& pl, const float* b, const float* d, float beta, float* rho, int iters, unsigned flags,
-             float* z, float* theta, double* resid, void* ws, hipStream_t st) {
+             float* z, float* theta, double* resid, void* ws, hipStream_t st, float tol, int* iters_done) {
   CodeWs w;
   carve_code(pl, ws, &w);
   const int64_t D = pl.dsz, N = pl.n, J = pl.j;
@@ -840,29 +887,46 @@ int run_code(const Plan& pl, const float* b, const float* d, float beta, float* 
     if ((e = forward_maps(pl, theta, w, w.rpri, st)) != hipSuccess) return CSC_EHIP;
     LAUNCH_J(k_sym_reduce, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.part, w.Th, w.ngp, T, H, W);
   }
-  if (iters > 0) LAUNCH_J(k_solve, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.G, w.xh, w.yh, w.Th, w.rho, w.lam, D);
-  const bool need_rho = adaptive || resid != nullptr;
+  // tolerance mode: every launch of the iteration loop checks the stop flag,
+  // so iterations after convergence cost a launch each and no work
+  const bool tol_mode = tol > 0.0f;
+  const int* stop = tol_mode ? w.stop : nullptr;
+  if (tol_mode) hipLaunchKernelGGL(k_stop_init, dim3(1), dim3(64), 0, st, w.stop);
+  if (iters > 0)
+    LAUNCH_J(k_solve, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.G, w.xh, w.yh, w.Th, w.rho, w.lam, D, nullptr);
+  const bool need_rho = adaptive || resid != nullptr || tol_mode;
+  const double thr_pri = (double)tol * sqrt((double)pl.k * (double)D);
+  const double thr_dual = (double)tol * sqrt((double)J * (double)D);
   for (int it = 0; it < iters; ++it) {
     const bool last = it == iters - 1;
-    if ((e = iterate_maps(pl, w, z, last ? theta : nullptr, beta, st)) != hipSuccess) return CSC_EHIP;
+    // theta is written by the last iteration, or by every one when the loop may stop early
+    if ((e = iterate_maps(pl, w, z, (last || tol_mode) ? theta : nullptr, beta, st, stop)) != hipSuccess)
+      return CSC_EHIP;
     const int solve_next = (!last && !adaptive) ? 1 : 0;
-    TraceScope trace(kTraceCodeSpec, st);
-    LAUNCH_J(k_spec, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.part, w.G, w.xh, w.yh, w.Th, w.lam, w.rho, w.rdual,
-             w.ngp, T, H, W, solve_next);
+    {
+      TraceScope trace(kTraceCodeSpec, st);
+      LAUNCH_J(k_spec, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.part, w.G, w.xh, w.yh, w.Th, w.lam, w.rho,
+               w.rdual, w.ngp, T, H, W, solve_next, stop);
+    }
     if (need_rho)
       hipLaunchKernelGGL(k_rho, dim3((unsigned)N), dim3(64), 0, st, w.rpri, w.npri, w.rdual, w.ndual, w.rho, resid,
-                         it, (int)N, D, adaptive ? 1 : 0);
+                         it, (int)N, D, adaptive ? 1 : 0, stop, tol_mode ? w.rres : nullptr);
+    if (tol_mode) hipLaunchKernelGGL(k_stop, dim3(1), dim3(64), 0, st, w.rres, (int)N, thr_pri, thr_dual, w.stop);
     if (adaptive && !last)
-      LAUNCH_J(k_solve, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.G, w.xh, w.yh, w.Th, w.rho, w.lam, D);
+      LAUNCH_J(k_solve, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.G, w.xh, w.yh, w.Th, w.rho, w.lam, D, stop);
   }
   if (adaptive) hipLaunchKernelGGL(k_copy_f, dim3(nblk(N)), dim3(kEW), 0, st, rho, w.rho, N);
+  if (iters_done) {
+    if (tol_mode) hipLaunchKernelGGL(k_stop_out, dim3(1), dim3(64), 0, st, w.stop, iters_done);
+    else hipLaunchKernelGGL(k_fill_i, dim3(1), dim3(64), 0, st, iters_done, iters);
+  }
   return hipGetLastError() == hipSuccess ? CSC_OK : CSC_EHIP;
 }
 
 size_t run_code_ws(const Plan& pl) { return code_ws_bytes(pl); }
 
 void launch_make_v(const Plan& pl, const float2* E, const float2* lam, float2* buf, hipStream_t st) {
-  LAUNCH_J(k_make_v, pl.j, dim3(nblk(pl.dsz), pl.p, pl.n), dim3(kEW), st, E, lam, buf, pl.p, pl.dsz);
+  LAUNCH_J(k_make_v, pl.j, dim3(nblk(pl.dsz), pl.p, pl.n), dim3(kEW), st, E, lam, buf, pl.p, pl.dsz, nullptr);
 }
 
 void launch_sym_reduce(const Plan& pl, const float2* part, int ng, float2* dst, hipStream_t st) {

@@ -47,8 +47,10 @@ int split_row_blocks(const Plan& pl);
 // mode 0: one ADMM map iteration (z, theta as in the fused kernel, residual
 // partials to rpart [N][P * col_blocks]); mode 1: forward transform of the
 // maps z and reduction into part (l1 partials to rpart).
+// With `stop` (tolerance mode) the kernels return at once when stop[0] is set.
 hipError_t split_maps(const Plan& pl, const float2* E, const float2* lam, float2* buf, float* z, float* theta,
-                      const float* rho, float beta, float2* part, double* rpart, int mode, hipStream_t st);
+                      const float* rho, float beta, float2* part, double* rpart, int mode, hipStream_t st,
+                      const int* stop);
 
 // Workspace carving: aligned sub-buffers of one caller-provided block.
 struct Carver {
@@ -75,6 +77,8 @@ bool tile_supported(int h, int w);
 struct CodeWs {
   float2 *E, *G, *xh, *yh, *Th, *lam, *part, *buf;
   double *rpri, *rdual, *opart;
+  double* rres;  // per-image r_pri, r_dual of the last iteration (tolerance mode)
+  int* stop;     // tolerance mode: [0] converged flag, [1] iterations carried out
   float* rho;
   int npri, ndual, ngp;  // partial counts per image; pair groups written to part
 };

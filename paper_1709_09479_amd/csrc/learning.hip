@@ -80,7 +80,9 @@ __global__ void l_complex_to_real(const float2* __restrict__ src, float* __restr
 // Tp[j][p](f) = t_2p,j(f) + i t_2p+1,j(f),  t_k,j(f) = sum_n conj(zhat_k^n(f)) v_j^n(f)
 template <int J>
 __global__ __launch_bounds__(kLW) void l_passA(const float2* __restrict__ Zh, const float2* __restrict__ v,
-                                               float2* __restrict__ Tp, int N, int P, int T, int H, int W) {
+                                               float2* __restrict__ Tp, int N, int P, int T, int H, int W,
+                                               const int* __restrict__ cgf) {
+  if (cgf && cgf[0]) return;
   const int64_t D = int64_t(T) * H * W;
   const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int p = blockIdx.y;
@@ -108,7 +110,8 @@ __global__ __launch_bounds__(kLW) void l_passA(const float2* __restrict__ Zh, co
 // In place on D * (t_2p + i t_2p+1) (spatial): keep the support, scale by
 // 1/(2 mu_k D), zero elsewhere.
 __global__ void l_crop_scale(float2* __restrict__ Tp, const float* __restrict__ mu, int K, int P, int T, int H,
-                             int W, int ft, int fh, int fw) {
+                             int W, int ft, int fh, int fw, const int* __restrict__ cgf) {
+  if (cgf && cgf[0]) return;
   const int64_t D = int64_t(T) * H * W;
   const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int p = blockIdx.y, j = blockIdx.z;
@@ -131,7 +134,9 @@ constexpr int lt_threads(int d) { return d >= 16384 ? 1024 : d <= 1024 ? 64 : d 
 // that fit LDS.  One workgroup per (pair, channel).
 template <int H, int W>
 __global__ __launch_bounds__(lt_threads(H * W)) void l_crop_tile(float2* __restrict__ Tp, const float* __restrict__ mu,
-                                                                int K, int P, int fh, int fw) {
+                                                                int K, int P, int fh, int fw,
+                                                                const int* __restrict__ cgf) {
+  if (cgf && cgf[0]) return;
   constexpr int D = H * W, NT = lt_threads(D), WP = W + 1;
   __shared__ float2 tile[H * WP];
   __shared__ float2 tw[256];
@@ -163,7 +168,8 @@ template <int J>
 __global__ __launch_bounds__(kLW) void l_passB(const float2* __restrict__ Zh, const float2* __restrict__ Up,
                                                const float2* __restrict__ v, float2* __restrict__ q,
                                                const float2* __restrict__ xh, double* __restrict__ dots, int N,
-                                               int P, int T, int H, int W) {
+                                               int P, int T, int H, int W, const int* __restrict__ cgf) {
+  if (cgf && cgf[0]) return;
   __shared__ double red[kLW / 64];
   const int64_t D = int64_t(T) * H * W;
   const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -253,7 +259,8 @@ __device__ __forceinline__ bool canon2(int i, int H, int W, int& f, int& fm) {
 template <int J>
 __global__ __launch_bounds__(256) void l_passA_rows(const float2* __restrict__ Zh, const float2* __restrict__ v,
                                                     float2* __restrict__ S1, int N, int P, int H, int W, int M2,
-                                                    int g) {
+                                                    int g, const int* __restrict__ cgf) {
+  if (cgf && cgf[0]) return;
   __shared__ float2 tw[256];
   __shared__ float2 ts[512];  // [slot][f2]; slots R..2R-1 hold the mirrored rows
   load_twiddles(tw);
@@ -332,7 +339,8 @@ __global__ __launch_bounds__(256) void l_passA_rows(const float2* __restrict__ Z
 // filters of the pair, and R3 is not written.
 __global__ __launch_bounds__(256) void l_prune_mid(const float2* __restrict__ S1, float2* __restrict__ R3,
                                                    const float* __restrict__ mu, float* __restrict__ d, int K, int J,
-                                                   int P, int H, int W, int M1, int M2, int cr, int g) {
+                                                   int P, int H, int W, int M1, int M2, int cr, int g, const int* __restrict__ cgf) {
+  if (cgf && cgf[0]) return;
   __shared__ float2 tw[256];
   __shared__ float2 s[256 * kPruneMax];
   __shared__ float2 u[kPruneMax * kPruneMax];
@@ -383,7 +391,8 @@ __global__ __launch_bounds__(256) void l_prune_mid(const float2* __restrict__ S1
 // e^{-2 pi i f1 m1 / H}.  A workgroup stages r = R3[j][p] in LDS and covers
 // `cpb` canonical indices.
 __global__ __launch_bounds__(256) void l_prune_cols(const float2* __restrict__ R3, float4* __restrict__ Uc, int P,
-                                                    int H, int W, int M1, int cpb) {
+                                                    int H, int W, int M1, int cpb, const int* __restrict__ cgf) {
+  if (cgf && cgf[0]) return;
   __shared__ float2 tw[256];
   __shared__ float2 r[kPruneMax * 256];
   const int p = blockIdx.y, j = blockIdx.z, nc = (H / 2 + 1) * W;
@@ -430,7 +439,8 @@ template <int J>
 __global__ __launch_bounds__(64 * kBW) void l_passB_c(const float2* __restrict__ Zh, const float4* __restrict__ Uc,
                                                       const float2* __restrict__ v, float2* __restrict__ q,
                                                       const float2* __restrict__ xh, double* __restrict__ dots, int N,
-                                                      int P, int H, int W, int nbc) {
+                                                      int P, int H, int W, int nbc, const int* __restrict__ cgf) {
+  if (cgf && cgf[0]) return;
   constexpr int NB = passb_nb<J>(), NI = NB * J;  // items per lane: (image, channel)
   __shared__ float2 part[kBW][NI][64];
   __shared__ double wsum[NI];
@@ -528,11 +538,14 @@ template <int J>
 __global__ __launch_bounds__(kLW) void l_cg_step(float2* __restrict__ g, float2* __restrict__ r,
                                                  const float2* __restrict__ p, const float2* __restrict__ q,
                                                  const double* __restrict__ rr, const double* __restrict__ pap,
-                                                 int npart, double* __restrict__ rrpart, int N, int64_t D) {
+                                                 int npart, double* __restrict__ rrpart, int N, int64_t D,
+                                                 const int* __restrict__ cgf, int* __restrict__ count) {
+  if (cgf && cgf[0]) return;
   __shared__ double red[kLW / 64];
   __shared__ double bc;
   const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int n = blockIdx.y;
+  if (count && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) count[0] += 1;
   double alpha[J];
 #pragma unroll
   for (int j = 0; j < J; ++j) {
@@ -566,18 +579,25 @@ __global__ __launch_bounds__(kLW) void l_cg_step(float2* __restrict__ g, float2*
 template <int J>
 __global__ __launch_bounds__(kLW) void l_cg_dir(float2* __restrict__ p, const float2* __restrict__ r,
                                                 const double* __restrict__ rr, const double* __restrict__ rrpart,
-                                                int npart, double* __restrict__ rr_next, int copy_r, int64_t D) {
+                                                int npart, double* __restrict__ rr_next, int copy_r, int64_t D,
+                                                int* __restrict__ cgf, const double* __restrict__ bb, double tol2) {
+  if (cgf && cgf[0]) return;
   __shared__ double red[kLW / 64];
   __shared__ double bc;
   const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int n = blockIdx.y;
   double bet[J];
+  bool conv = true;
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const double rn = sum_partials(rrpart + int64_t(j) * npart, npart, red, &bc);
     bet[j] = (!copy_r && rr[j] > 0.0) ? rn / rr[j] : 0.0;
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) rr_next[j] = rn;
+    conv = conv && cgf && rn <= tol2 * bb[j];
   }
+  // tolerance mode: |r|^2 <= tol^2 |x|^2 in every channel ends this CG solve;
+  // the later launches of the solve return at once
+  if (conv && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) cgf[0] = 1;
   if (f < D) {
 #pragma unroll
     for (int j = 0; j < J; ++j) {
@@ -591,6 +611,30 @@ __global__ __launch_bounds__(kLW) void l_cg_dir(float2* __restrict__ p, const fl
         p[o] = make_float2(fmaf(b, pp.x, rv.x), fmaf(b, pp.y, rv.y));
       }
     }
+  }
+}
+
+// bb[j] = sum over images and frequencies of |xhat_j|^2 (one workgroup per
+// channel, fixed order): the reference of the CG stopping rule.
+__global__ __launch_bounds__(kLW) void l_norm2(const float2* __restrict__ xh, double* __restrict__ bb, int N, int J,
+                                               int64_t D) {
+  __shared__ double red[kLW / 64];
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int n = 0; n < N; ++n)
+    for (int64_t f = threadIdx.x; f < D; f += kLW) {
+      const float2 x = xh[(int64_t(n) * J + j) * D + f];
+      s += (double)x.x * x.x + (double)x.y * x.y;
+    }
+  const double t = block_sum(s, red);
+  if (threadIdx.x == 0) bb[j] = t;
+}
+
+// start of a multiplier step in tolerance mode: clear the flag and the count
+__global__ void l_cg_reset(int* __restrict__ cgf, int* __restrict__ count) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    cgf[0] = 0;
+    if (count) count[0] = 0;
   }
 }
 
@@ -670,6 +714,8 @@ struct LearnWs {
   float2 *Zh, *xh, *gh, *rh, *ph, *qh, *Tp, *S1, *R3;
   float4* Uc;   // pruned path: U at the canonical frequencies, pair unpacked
   double *dots, *rr;  // dots: pass-B partials then residual partials; rr: [4][J]
+  double* bb;         // tolerance mode: |xhat_j|^2 per channel
+  int* cgf;           // tolerance mode: CG stop flag of the current multiplier step
   int nB;  // pruned path: pass-B partials per channel (one per workgroup)
   int npartB, npartS;  // partial counts per channel: pass B, vector-update kernel
 };
@@ -691,6 +737,8 @@ static size_t carve_learn(const Plan& pl, void* base, LearnWs* w) {
   w->Uc = c.take<float4>(J * P * int64_t(pl.g[1] / 2 + 1) * pl.g[2]);
   w->dots = c.take<double>(J * (int64_t(w->npartB) + std::max(w->npartB, w->npartS)));
   w->rr = c.take<double>(4 * J);
+  w->bb = c.take<double>(J);
+  w->cgf = c.take<int>(1);
   w->nB = (int)canon_blocks(pl) * passb_chunks(pl);
   return c.off;
 }
@@ -700,14 +748,14 @@ size_t run_learn_ws(const Plan& pl) {
   return carve_learn(pl, nullptr, &w);
 }
 
-static bool crop_tile_launch(const Plan& pl, float2* Tp, const float* mu, hipStream_t st) {
+static bool crop_tile_launch(const Plan& pl, float2* Tp, const float* mu, hipStream_t st, const int* cgf) {
   if (!(pl.g[0] == 1 && tile_supported(pl.g[1], pl.g[2]))) return false;
   const dim3 grid(pl.p, pl.j);
   const int h = pl.g[1], w = pl.g[2];
 #define CT(HH, WW)                                                                                             \
   if (h == HH && w == WW) {                                                                                    \
     hipLaunchKernelGGL((l_crop_tile<HH, WW>), grid, dim3(lt_threads(HH * WW)), 0, st, Tp, mu, pl.k, pl.p,      \
-                       pl.fs[1], pl.fs[2]);                                                                    \
+                       pl.fs[1], pl.fs[2], cgf);                                                               \
     return true;                                                                                               \
   }
   CT(16, 16) CT(16, 32) CT(16, 64) CT(16, 128) CT(16, 256)
@@ -722,19 +770,20 @@ static bool crop_tile_launch(const Plan& pl, float2* Tp, const float* mu, hipStr
 // ------------------------------------------------ pruned operator (host)
 // U for A v: pass A with the row stage, the column and back-row stages into
 // R3, the last stage into Uc.
-static hipError_t pruned_zt_proj(const Plan& pl, LearnWs& w, const float2* v, const float* mu, hipStream_t st) {
+static hipError_t pruned_zt_proj(const Plan& pl, LearnWs& w, const float2* v, const float* mu, hipStream_t st,
+                                 const int* cgf) {
   const int H = pl.g[1], W = pl.g[2], R = 256 / W, M1 = pl.fs[1], M2 = pl.fs[2];
   {
     TraceScope trace(kTraceLearnA, st);
     LJ(l_passA_rows, pl.j, dim3((H / 2 + R) / R, pl.p), dim3(256), st, w.Zh, v, w.S1, pl.n, pl.p, H, W, M2,
-       lanes_for(2 * R * M2, W));
+       lanes_for(2 * R * M2, W), cgf);
   }
   const int cr = LEARN_MID_CR;
   hipLaunchKernelGGL(l_prune_mid, dim3(pl.p, pl.j, (M1 + cr - 1) / cr), dim3(256), 0, st, w.S1, w.R3, mu, nullptr,
-                     pl.k, pl.j, pl.p, H, W, M1, M2, cr, lanes_for(cr * M2, H));
+                     pl.k, pl.j, pl.p, H, W, M1, M2, cr, lanes_for(cr * M2, H), cgf);
   const int nc = (H / 2 + 1) * W, cpb = LEARN_COLS_CPB;
   hipLaunchKernelGGL(l_prune_cols, dim3((nc + cpb - 1) / cpb, pl.p, pl.j), dim3(256), 0, st, w.R3, w.Uc, pl.p, H, W,
-                     M1, cpb);
+                     M1, cpb, cgf);
   return hipGetLastError();
 }
 
@@ -744,50 +793,53 @@ static hipError_t pruned_drecover(const Plan& pl, LearnWs& w, const float* mu, f
   {
     TraceScope trace(kTraceLearnA, st);
     LJ(l_passA_rows, pl.j, dim3((H / 2 + R) / R, pl.p), dim3(256), st, w.Zh, w.gh, w.S1, pl.n, pl.p, H, W, M2,
-       lanes_for(2 * R * M2, W));
+       lanes_for(2 * R * M2, W), nullptr);
   }
   const int cr = LEARN_MID_CR;
   hipLaunchKernelGGL(l_prune_mid, dim3(pl.p, pl.j, (M1 + cr - 1) / cr), dim3(256), 0, st, w.S1, w.R3, mu, d, pl.k,
-                     pl.j, pl.p, H, W, M1, M2, cr, lanes_for(cr * M2, H));
+                     pl.j, pl.p, H, W, M1, M2, cr, lanes_for(cr * M2, H), nullptr);
   return hipGetLastError();
 }
 
 // q = v + Z U (pass B); with xh: q = -x - (v + Z U).  Partials to `part`
 // ([J][nB]).
 static void pruned_passB(const Plan& pl, LearnWs& w, const float2* v, float2* q, const float2* xh, double* part,
-                         hipStream_t st) {
+                         hipStream_t st, const int* cgf) {
   const int chunks = passb_chunks(pl), nbc = (pl.n + chunks - 1) / chunks;
   TraceScope trace(kTraceLearnB, st);
   LJ(l_passB_c, pl.j, dim3(canon_blocks(pl), chunks), dim3(64 * kBW), st, w.Zh, w.Uc, v, q, xh, part, pl.n, pl.p,
-     pl.g[1], pl.g[2], nbc);
+     pl.g[1], pl.g[2], nbc, cgf);
 }
 
 // Up <- DFT(S^T S IDFT(pass A of v) / (2 mu)).
-static hipError_t apply_zt_proj(const Plan& pl, LearnWs& w, const float2* v, const float* mu, hipStream_t st) {
+// (With cgf set the kernels skip their work; the axis FFTs of the general
+// path still run on the stale buffer, whose result is then not used.)
+static hipError_t apply_zt_proj(const Plan& pl, LearnWs& w, const float2* v, const float* mu, hipStream_t st,
+                                const int* cgf) {
   const int64_t D = pl.dsz;
   const int T = pl.g[0], H = pl.g[1], W = pl.g[2];
   {
     TraceScope trace(kTraceLearnA, st);
-    LJ(l_passA, pl.j, dim3(lblk(D), pl.p), dim3(kLW), st, w.Zh, v, w.Tp, pl.n, pl.p, T, H, W);
+    LJ(l_passA, pl.j, dim3(lblk(D), pl.p), dim3(kLW), st, w.Zh, v, w.Tp, pl.n, pl.p, T, H, W, cgf);
   }
-  if (crop_tile_launch(pl, w.Tp, mu, st)) return hipGetLastError();
+  if (crop_tile_launch(pl, w.Tp, mu, st, cgf)) return hipGetLastError();
   hipError_t e = fft_grids(w.Tp, int64_t(pl.j) * pl.p, pl.g, +1, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(l_crop_scale, dim3(lblk(D), pl.p, pl.j), dim3(kLW), 0, st, w.Tp, mu, pl.k, pl.p, T, H, W,
-                     pl.fs[0], pl.fs[1], pl.fs[2]);
+                     pl.fs[0], pl.fs[1], pl.fs[2], cgf);
   return fft_grids(w.Tp, int64_t(pl.j) * pl.p, pl.g, -1, st);
 }
 
 // q = v + Z Up (pass B); with xh: q = -x - (v + Z Up).  Dot partials to dots.
 static void apply_passB(const Plan& pl, LearnWs& w, const float2* v, float2* q, const float2* xh, double* dots,
-                        hipStream_t st) {
+                        hipStream_t st, const int* cgf) {
   const int T = pl.g[0], H = pl.g[1], W = pl.g[2];
   TraceScope trace(kTraceLearnB, st);
-  LJ(l_passB, pl.j, dim3(lblk(pl.dsz), pl.n), dim3(kLW), st, w.Zh, w.Tp, v, q, xh, dots, pl.n, pl.p, T, H, W);
+  LJ(l_passB, pl.j, dim3(lblk(pl.dsz), pl.n), dim3(kLW), st, w.Zh, w.Tp, v, q, xh, dots, pl.n, pl.p, T, H, W, cgf);
 }
 
 int run_learn(const Plan& pl, const float* b, const float* z, float* d, float* mu, float* gamma, int inner_iters,
-              int cg_iters, unsigned flags, void* ws, hipStream_t st) {
+              int cg_iters, unsigned flags, void* ws, hipStream_t st, float cg_tol, int* cg_counts) {
   LearnWs w;
   carve_learn(pl, ws, &w);
   const int64_t D = pl.dsz, N = pl.n, J = pl.j;
@@ -809,41 +861,46 @@ int run_learn(const Plan& pl, const float* b, const float* z, float* d, float* m
   double* rr_a = w.rr;
   double* rr_b = w.rr + J;
   const bool pruned = pruned2d(pl);
+  // tolerance mode: each multiplier step's CG stops once |r| <= cg_tol |x|
+  // in every channel (relative residual of A gamma = -x); the remaining
+  // launches of that solve check the flag and return at once
+  const bool tol_mode = cg_tol > 0.0f;
+  int* cgf = tol_mode ? w.cgf : nullptr;
+  const double tol2 = (double)cg_tol * (double)cg_tol;
+  if (tol_mode) hipLaunchKernelGGL(l_norm2, dim3((unsigned)J), dim3(kLW), 0, st, w.xh, w.bb, (int)N, (int)J, D);
+  const int npB = pruned ? w.nB : w.npartB;
   for (int it = 0; it < inner_iters; ++it) {
+    int* cnt = cg_counts ? cg_counts + it : nullptr;
+    if (tol_mode) hipLaunchKernelGGL(l_cg_reset, dim3(1), dim3(64), 0, st, cgf, cnt);
+    else if (cnt) hipLaunchKernelGGL(l_cg_reset, dim3(1), dim3(64), 0, st, w.cgf, cnt);
+    // r = -x - A gamma ; p = r ; rr = |r|^2
     if (pruned) {
-      // r = -x - A gamma ; p = r ; rr = |r|^2
-      if ((e = pruned_zt_proj(pl, w, w.gh, mu, st)) != hipSuccess) return CSC_EHIP;
-      pruned_passB(pl, w, w.gh, w.rh, w.xh, rrp, st);
-      LJ(l_cg_dir, pl.j, vgrid, dim3(kLW), st, w.ph, w.rh, rr_a, rrp, w.nB, rr_a, 1, D);
-      for (int q = 0; q < cg_iters; ++q) {
-        if ((e = pruned_zt_proj(pl, w, w.ph, mu, st)) != hipSuccess) return CSC_EHIP;
-        pruned_passB(pl, w, w.ph, w.qh, nullptr, pap, st);
-        LJ(l_cg_step, pl.j, vgrid, dim3(kLW), st, w.gh, w.rh, w.ph, w.qh, rr_a, pap, w.nB, rrp, pl.n, D);
-        LJ(l_cg_dir, pl.j, vgrid, dim3(kLW), st, w.ph, w.rh, rr_a, rrp, w.npartS, rr_b, 0, D);
-        double* t = rr_a;
-        rr_a = rr_b;
-        rr_b = t;
-      }
+      if ((e = pruned_zt_proj(pl, w, w.gh, mu, st, cgf)) != hipSuccess) return CSC_EHIP;
+      pruned_passB(pl, w, w.gh, w.rh, w.xh, rrp, st, cgf);
     } else {
-      // r = -x - A gamma ; p = r ; rr = |r|^2
-      if ((e = apply_zt_proj(pl, w, w.gh, mu, st)) != hipSuccess) return CSC_EHIP;
-      apply_passB(pl, w, w.gh, w.rh, w.xh, rrp, st);
-      LJ(l_cg_dir, pl.j, vgrid, dim3(kLW), st, w.ph, w.rh, rr_a, rrp, w.npartB, rr_a, 1, D);
-      for (int q = 0; q < cg_iters; ++q) {
-        if ((e = apply_zt_proj(pl, w, w.ph, mu, st)) != hipSuccess) return CSC_EHIP;
-        apply_passB(pl, w, w.ph, w.qh, nullptr, pap, st);
-        LJ(l_cg_step, pl.j, vgrid, dim3(kLW), st, w.gh, w.rh, w.ph, w.qh, rr_a, pap, w.npartB, rrp, pl.n, D);
-        LJ(l_cg_dir, pl.j, vgrid, dim3(kLW), st, w.ph, w.rh, rr_a, rrp, w.npartS, rr_b, 0, D);
-        double* t = rr_a;
-        rr_a = rr_b;
-        rr_b = t;
+      if ((e = apply_zt_proj(pl, w, w.gh, mu, st, cgf)) != hipSuccess) return CSC_EHIP;
+      apply_passB(pl, w, w.gh, w.rh, w.xh, rrp, st, cgf);
+    }
+    LJ(l_cg_dir, pl.j, vgrid, dim3(kLW), st, w.ph, w.rh, rr_a, rrp, npB, rr_a, 1, D, cgf, w.bb, tol2);
+    for (int q = 0; q < cg_iters; ++q) {
+      if (pruned) {
+        if ((e = pruned_zt_proj(pl, w, w.ph, mu, st, cgf)) != hipSuccess) return CSC_EHIP;
+        pruned_passB(pl, w, w.ph, w.qh, nullptr, pap, st, cgf);
+      } else {
+        if ((e = apply_zt_proj(pl, w, w.ph, mu, st, cgf)) != hipSuccess) return CSC_EHIP;
+        apply_passB(pl, w, w.ph, w.qh, nullptr, pap, st, cgf);
       }
+      LJ(l_cg_step, pl.j, vgrid, dim3(kLW), st, w.gh, w.rh, w.ph, w.qh, rr_a, pap, npB, rrp, pl.n, D, cgf, cnt);
+      LJ(l_cg_dir, pl.j, vgrid, dim3(kLW), st, w.ph, w.rh, rr_a, rrp, w.npartS, rr_b, 0, D, cgf, w.bb, tol2);
+      double* t = rr_a;
+      rr_a = rr_b;
+      rr_b = t;
     }
     // d_k = -S Z_k^T gamma / (2 mu_k) ; mu_k <- mu_k ||d_k||
     if (pruned) {
       if ((e = pruned_drecover(pl, w, mu, d, st)) != hipSuccess) return CSC_EHIP;
     } else {
-      LJ(l_passA, pl.j, dim3(lblk(D), pl.p), dim3(kLW), st, w.Zh, w.gh, w.Tp, pl.n, pl.p, T, H, W);
+      LJ(l_passA, pl.j, dim3(lblk(D), pl.p), dim3(kLW), st, w.Zh, w.gh, w.Tp, pl.n, pl.p, T, H, W, nullptr);
       if ((e = fft_grids(w.Tp, J * pl.p, pl.g, +1, st)) != hipSuccess) return CSC_EHIP;
       hipLaunchKernelGGL(l_drecover, dim3(lblk(pl.msz), pl.k, pl.j), dim3(kLW), 0, st, w.Tp, mu, d, pl.k, pl.j,
                          pl.p, T, H, W, pl.fs[0], pl.fs[1], pl.fs[2]);

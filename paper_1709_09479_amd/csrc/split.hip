@@ -22,7 +22,9 @@ constexpr int kSplitNT = 256;   // threads per workgroup
 template <int W, int J>
 __global__ __launch_bounds__(kSplitNT) void k_split_rows_inv(const float2* __restrict__ E,
                                                              const float2* __restrict__ lam,
-                                                             float2* __restrict__ buf, int P, int H) {
+                                                             float2* __restrict__ buf, int P, int H,
+                                                             const int* __restrict__ stop) {
+  if (stop && stop[0]) return;
   constexpr int T = kSplitT, NT = kSplitNT, RB = T / W, WP = tile_stride(W);
   constexpr int A0 = plan_r(W, 0), AL = plan_r(W, 1);
   using P0 = TilePass<W, T, NT, 1, A0, 1, true, true, WP>;
@@ -77,7 +79,9 @@ template <int H, int MODE>
 __global__ __launch_bounds__(kSplitNT) void k_split_cols(float2* __restrict__ buf, float* __restrict__ z,
                                                          float* __restrict__ theta, const int64_t* __restrict__ zoff,
                                                          const float* __restrict__ rho_cur, float beta,
-                                                         double* __restrict__ rpart, int K, int P, int W) {
+                                                         double* __restrict__ rpart, int K, int P, int W,
+                                                         const int* __restrict__ stop) {
+  if (stop && stop[0]) return;
   constexpr int T = kSplitT, NT = kSplitNT, CB = T / H, WP = tile_stride(CB);
   constexpr int B0 = plan_r(H, 0), BL = plan_r(H, 1);
   using C0 = TilePass<H, T, NT, 1, B0, 1, false, false, WP>;
@@ -174,7 +178,8 @@ template <int W, int J>
 __global__ __launch_bounds__(kSplitNT) void k_split_rows_fwd(const float2* __restrict__ E,
                                                              const float2* __restrict__ buf,
                                                              float2* __restrict__ part, int P, int H, int ppg,
-                                                             int ng) {
+                                                             int ng, const int* __restrict__ stop) {
+  if (stop && stop[0]) return;
   constexpr int T = kSplitT, NT = kSplitNT, RB = T / W, WP = tile_stride(W);
   constexpr int A0 = plan_r(W, 0), AL = plan_r(W, 1);
   using Q0 = TilePass<W, T, NT, -1, AL, 1, true, true, WP>;
@@ -245,39 +250,40 @@ int split_row_blocks(const Plan& pl) { return pl.g[1] / (kSplitT / pl.g[2]); }
 template <int J>
 static hipError_t split_iter_j(const Plan& pl, const float2* E, const float2* lam, float2* buf, float* z,
                                float* theta, const float* rho, float beta, float2* part, double* rpart, int mode,
-                               hipStream_t st) {
+                               hipStream_t st, const int* stop) {
   const int H = pl.g[1], W = pl.g[2];
   const dim3 blk(kSplitNT);
   if (mode == 0) {
     const dim3 g1(split_row_blocks(pl) * pl.p * pl.n);
-    if (W == 256) hipLaunchKernelGGL((k_split_rows_inv<256, J>), g1, blk, 0, st, E, lam, buf, pl.p, H);
-    else hipLaunchKernelGGL((k_split_rows_inv<128, J>), g1, blk, 0, st, E, lam, buf, pl.p, H);
+    if (W == 256) hipLaunchKernelGGL((k_split_rows_inv<256, J>), g1, blk, 0, st, E, lam, buf, pl.p, H, stop);
+    else hipLaunchKernelGGL((k_split_rows_inv<128, J>), g1, blk, 0, st, E, lam, buf, pl.p, H, stop);
   }
   const dim3 g2(split_col_blocks(pl), pl.p, pl.n);
   if (mode == 0) {
     if (H == 256)
-      hipLaunchKernelGGL((k_split_cols<256, 0>), g2, blk, 0, st, buf, z, theta, pl.zoff, rho, beta, rpart, pl.k, pl.p, W);
+      hipLaunchKernelGGL((k_split_cols<256, 0>), g2, blk, 0, st, buf, z, theta, pl.zoff, rho, beta, rpart, pl.k, pl.p, W, stop);
     else
-      hipLaunchKernelGGL((k_split_cols<128, 0>), g2, blk, 0, st, buf, z, theta, pl.zoff, rho, beta, rpart, pl.k, pl.p, W);
+      hipLaunchKernelGGL((k_split_cols<128, 0>), g2, blk, 0, st, buf, z, theta, pl.zoff, rho, beta, rpart, pl.k, pl.p, W, stop);
   } else {
     if (H == 256)
-      hipLaunchKernelGGL((k_split_cols<256, 1>), g2, blk, 0, st, buf, z, nullptr, pl.zoff, rho, 0.f, rpart, pl.k, pl.p, W);
+      hipLaunchKernelGGL((k_split_cols<256, 1>), g2, blk, 0, st, buf, z, nullptr, pl.zoff, rho, 0.f, rpart, pl.k, pl.p, W, stop);
     else
-      hipLaunchKernelGGL((k_split_cols<128, 1>), g2, blk, 0, st, buf, z, nullptr, pl.zoff, rho, 0.f, rpart, pl.k, pl.p, W);
+      hipLaunchKernelGGL((k_split_cols<128, 1>), g2, blk, 0, st, buf, z, nullptr, pl.zoff, rho, 0.f, rpart, pl.k, pl.p, W, stop);
   }
   const dim3 g3(split_row_blocks(pl) * pl.ng * pl.n);
-  if (W == 256) hipLaunchKernelGGL((k_split_rows_fwd<256, J>), g3, blk, 0, st, E, buf, part, pl.p, H, pl.ppg, pl.ng);
-  else hipLaunchKernelGGL((k_split_rows_fwd<128, J>), g3, blk, 0, st, E, buf, part, pl.p, H, pl.ppg, pl.ng);
+  if (W == 256) hipLaunchKernelGGL((k_split_rows_fwd<256, J>), g3, blk, 0, st, E, buf, part, pl.p, H, pl.ppg, pl.ng, stop);
+  else hipLaunchKernelGGL((k_split_rows_fwd<128, J>), g3, blk, 0, st, E, buf, part, pl.p, H, pl.ppg, pl.ng, stop);
   return hipGetLastError();
 }
 
 // mode 0: one ADMM map iteration; mode 1: forward transform and reduction of
 // the given maps (z), l1 partials in rpart.
 hipError_t split_maps(const Plan& pl, const float2* E, const float2* lam, float2* buf, float* z, float* theta,
-                      const float* rho, float beta, float2* part, double* rpart, int mode, hipStream_t st) {
-  if (pl.j == 1) return split_iter_j<1>(pl, E, lam, buf, z, theta, rho, beta, part, rpart, mode, st);
-  if (pl.j == 2) return split_iter_j<2>(pl, E, lam, buf, z, theta, rho, beta, part, rpart, mode, st);
-  return split_iter_j<3>(pl, E, lam, buf, z, theta, rho, beta, part, rpart, mode, st);
+                      const float* rho, float beta, float2* part, double* rpart, int mode, hipStream_t st,
+                      const int* stop) {
+  if (pl.j == 1) return split_iter_j<1>(pl, E, lam, buf, z, theta, rho, beta, part, rpart, mode, st, stop);
+  if (pl.j == 2) return split_iter_j<2>(pl, E, lam, buf, z, theta, rho, beta, part, rpart, mode, st, stop);
+  return split_iter_j<3>(pl, E, lam, buf, z, theta, rho, beta, part, rpart, mode, st, stop);
 }
 
 }  // namespace dcsc

@@ -135,3 +135,31 @@ def test_trace_argument_errors():
     assert lib.csc_trace_read(0, None, ctypes.byref(cnt)) == -1
     with pytest.raises(ValueError):
         dc.trace_enable(True, every=0)
+
+
+def test_tolerance_entry_point_argument_errors():
+    """csc_code_tol / csc_learn_tol validate their stopping-rule arguments on
+    the host before anything is enqueued (no GPU needed)."""
+    lib = dc.load()
+    s = shape()
+    wc = lib.csc_workspace_bytes(ctypes.byref(s), dc.OP_CODE, 0)
+    code = lambda **kw: lib.csc_code_tol(
+        ctypes.byref(s), FAKE, FAKE, 1.0, FAKE, kw.get("iters", 5), kw.get("tol", 1e-3), kw.get("flags", 0),
+        FAKE, None, None, None, 0x100000, kw.get("wsb", wc), None)
+    assert code(tol=0.0) == dc.EINVAL
+    assert code(tol=-1.0) == dc.EINVAL
+    assert code(tol=float("nan")) == dc.EINVAL
+    assert code(tol=float("inf")) == dc.EINVAL
+    assert code(iters=-1) == dc.EINVAL
+    assert code(flags=dc.USE_GRAPH) == dc.EINVAL
+    assert code(wsb=wc - 1) == dc.EWORKSPACE
+    wl = lib.csc_workspace_bytes(ctypes.byref(s), dc.OP_LEARN, 0)
+    learn = lambda **kw: lib.csc_learn_tol(
+        ctypes.byref(s), FAKE, FAKE, FAKE, FAKE, FAKE, kw.get("inner", 2), kw.get("cg", 5), kw.get("tol", 1e-3),
+        kw.get("flags", 0), None, 0x100000, kw.get("wsb", wl), None)
+    assert learn(tol=-1e-3) == dc.EINVAL
+    assert learn(tol=float("nan")) == dc.EINVAL
+    assert learn(inner=0) == dc.EINVAL
+    assert learn(cg=-1) == dc.EINVAL
+    assert learn(flags=dc.USE_GRAPH) == dc.EINVAL
+    assert learn(wsb=wl - 1) == dc.EWORKSPACE

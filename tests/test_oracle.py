@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
+import synth
 
 RNG = np.random.default_rng(12345)
 
@@ -540,3 +541,88 @@ def test_gradient_fd_on_unrolled_instance():
         assert abs(fd - gd[idx]) <= 1e-6 * scale, (idx, fd, gd[idx])
     fd_b = (loss(d, cfg.beta + h) - loss(d, cfg.beta - h)) / (2 * h)
     assert abs(fd_b - gb) <= 1e-6 * scale
+
+
+# ------------------------------------------- convergence-driven stopping rules
+
+def test_code_tolerance_stops_at_first_iteration_meeting_the_rule():
+    """The tolerance mode stops after the first iteration at which every
+    image's RMS primal and dual residuals are at most tol (read off the
+    residual history of a fixed-count run), with the same iterates as that
+    run truncated there; a huge tol stops after one iteration and a zero-like
+    tol never fires."""
+    rng = np.random.default_rng(71)
+    b = rng.standard_normal((2, 1, 16, 16)) * 3
+    d = rand_filters(3, 1, (3, 3), rng)
+    K, J, npix = 3, 1, 256
+    full = oracle.code(b, d, 0.5, 2.0, 40)
+    rms = np.maximum(full["resid"][:, :, 0] / np.sqrt(K * npix), full["resid"][:, :, 1] / np.sqrt(J * npix))
+    worst = rms.max(axis=1)                       # [iters]: the largest RMS residual over images and kinds
+    k = 12
+    tol = float(np.sqrt(worst[k] * worst[:k].min())) if worst[:k].min() > worst[k] else None
+    assert tol is not None and worst[k] <= tol < worst[:k].min()
+    first = int(np.argmax(worst <= tol))
+    got = oracle.code(b, d, 0.5, 2.0, 40, tol=tol)
+    assert got["iters"] == first + 1
+    trunc = oracle.code(b, d, 0.5, 2.0, first + 1)
+    np.testing.assert_array_equal(got["z"], trunc["z"])
+    np.testing.assert_array_equal(got["resid"], full["resid"][:first + 1])
+    assert oracle.code(b, d, 0.5, 2.0, 40, tol=1e9)["iters"] == 1
+    assert oracle.code(b, d, 0.5, 2.0, 7, tol=1e-300)["iters"] == 7
+
+
+def test_cg_tolerance_meets_the_rule_minimally_on_the_dense_operator():
+    """With cg_tol the CG solve of eq:Learning_gamma stops at the first step
+    whose residual, measured on the dense operator I + sum_k W_k W_k^T /
+    (2 mu_k), is at most cg_tol ||x||: the step before does not meet it."""
+    N, K, grid, fs = 2, 2, (6, 6), (3, 3)
+    rng = np.random.default_rng(72)
+    z = rng.standard_normal((N, K) + grid) * (rng.random((N, K) + grid) < 0.5)
+    b = rng.standard_normal((N, 1) + grid)
+    mu = np.array([0.9, 1.1])
+    _, W = learning_dense(b[:, 0], z, fs, mu)
+    M = int(np.prod(fs))
+    A = np.eye(W.shape[0]) + (W / np.repeat(2 * mu, M)) @ W.T
+    x = b[:, 0].reshape(-1)
+    tol = 1e-4
+    info = {}
+    _, _, g = oracle.learn(b, z, fs, mu, None, inner_iters=1, cg_iters=200, cg_tol=tol, info=info)
+    steps = info["cg_counts"][0]
+    assert 0 < steps < 200
+    res = np.linalg.norm(-x - A @ g[:, 0].reshape(-1))
+    assert res <= tol * np.linalg.norm(x) * (1 + 1e-9)
+    _, _, g1 = oracle.learn(b, z, fs, mu, None, inner_iters=1, cg_iters=steps - 1)
+    assert np.linalg.norm(-x - A @ g1[:, 0].reshape(-1)) > tol * np.linalg.norm(x)
+    _, _, g2 = oracle.learn(b, z, fs, mu, None, inner_iters=1, cg_iters=steps)
+    np.testing.assert_array_equal(g2, g)
+
+
+def test_cg_tolerance_warm_start_needs_fewer_steps():
+    """Warm-started solves (gamma carried across multiplier updates, Sec.
+    3.2.2) reach the tolerance in fewer CG steps than the first, cold one."""
+    cfg = synth.CONFIGS["small"]
+    b, d = synth.make_inputs(cfg, n=2)
+    z = oracle.code(b, d, cfg.beta, cfg.rho, 10)["z"]
+    info = {}
+    oracle.learn(b, z, cfg.fsupp, np.ones(cfg.k), None, inner_iters=6, cg_iters=50, cg_tol=1e-3, info=info)
+    c = info["cg_counts"]
+    assert c[0] > max(c[2:]), c
+
+
+def test_alternation_tau_stops_on_the_objective_change():
+    """learn_dictionary with tau ends after the first outer step whose
+    objective (after learning) changed by at most tau relative to the
+    previous step's; no earlier step met that."""
+    cfg = synth.CONFIGS["small"]
+    b, d0 = synth.make_inputs(cfg, n=2)
+    tau = 0.05
+    out = oracle.learn_dictionary(b, d0, cfg.beta, cfg.rho, 5, 12, 3, 5, tau=tau)
+    f = np.array(out["objectives"][1::2])              # after each learning half step
+    assert len(f) == out["steps"]
+    rel = np.abs(np.diff(f)) / np.abs(f[:-1])
+    if out["steps"] < 12:
+        assert rel[-1] <= tau and np.all(rel[:-1] > tau)
+    else:
+        assert np.all(rel > tau)
+    full = oracle.learn_dictionary(b, d0, cfg.beta, cfg.rho, 5, out["steps"], 3, 5)
+    np.testing.assert_array_equal(full["d"], out["d"])
