@@ -717,18 +717,26 @@ __global__ __launch_bounds__(kEW) void k_obj_spec(const float2* __restrict__ par
   if (threadIdx.x == 0) opart[int64_t(n) * gridDim.x + blockIdx.x] = t;
 }
 
-__global__ void k_obj_final(const double* __restrict__ opart, int nopart, const double* __restrict__ l1,
-                            int nl1, double* __restrict__ out, int N, int64_t D, float beta) {
+// out[n] = 0.5 sum(opart[n]) / D + beta sum(l1[n]): one workgroup per image,
+// partials summed in a fixed order.
+__global__ __launch_bounds__(kEW) void k_obj_final(const double* __restrict__ opart, int nopart,
+                                                   const double* __restrict__ l1, int nl1, double* __restrict__ out,
+                                                   int N, int64_t D, float beta) {
+  __shared__ double red[kEW / 64];
+  const int n = blockIdx.x;
+  double r = 0.0, a = 0.0;
+  for (int i = threadIdx.x; i < nopart; i += kEW) r += opart[int64_t(n) * nopart + i];
+  for (int i = threadIdx.x; i < nl1; i += kEW) a += l1[int64_t(n) * nl1 + i];
+  r = block_sum(r, red);
+  a = block_sum(a, red);
+  if (threadIdx.x == 0) out[n] = 0.5 * r / (double)D + (double)beta * a;
+}
+
+// out[N] = sum over images of out[n], in image order
+__global__ void k_obj_total(double* __restrict__ out, int N) {
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
   double tot = 0.0;
-  for (int n = 0; n < N; ++n) {
-    double r = 0.0, a = 0.0;
-    for (int i = 0; i < nopart; ++i) r += opart[int64_t(n) * nopart + i];
-    for (int i = 0; i < nl1; ++i) a += l1[int64_t(n) * nl1 + i];
-    const double v = 0.5 * r / (double)D + (double)beta * a;
-    out[n] = v;
-    tot += v;
-  }
+  for (int n = 0; n < N; ++n) tot += out[n];
   out[N] = tot;
 }
 
@@ -936,8 +944,9 @@ void launch_sym_reduce(const Plan& pl, const float2* part, int ng, float2* dst, 
 void launch_objective_tail(const Plan& pl, CodeWs& w, float beta, double* out, hipStream_t st) {
   LAUNCH_J(k_obj_spec, pl.j, dim3(nblk(pl.dsz), pl.n), dim3(kEW), st, w.part, w.xh, w.opart, w.ngp, pl.g[0], pl.g[1],
            pl.g[2]);
-  hipLaunchKernelGGL(k_obj_final, dim3(1), dim3(64), 0, st, w.opart, w.ndual, w.rpri, w.npri, out, pl.n, pl.dsz,
-                     beta);
+  hipLaunchKernelGGL(k_obj_final, dim3((unsigned)pl.n), dim3(kEW), 0, st, w.opart, w.ndual, w.rpri, w.npri, out, pl.n,
+                     pl.dsz, beta);
+  hipLaunchKernelGGL(k_obj_total, dim3(1), dim3(64), 0, st, out, pl.n);
 }
 
 int run_objective(const Plan& pl, const float* b, const float* d, const float* z, float beta, double* out, void* ws,
@@ -949,7 +958,9 @@ int run_objective(const Plan& pl, const float* b, const float* d, const float* z
   if (setup_spectra(pl, b, d, w, st) != hipSuccess) return CSC_EHIP;
   if (forward_maps(pl, z, w, w.rpri, st) != hipSuccess) return CSC_EHIP;
   LAUNCH_J(k_obj_spec, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.part, w.xh, w.opart, w.ngp, T, H, W);
-  hipLaunchKernelGGL(k_obj_final, dim3(1), dim3(64), 0, st, w.opart, w.ndual, w.rpri, w.npri, out, (int)N, D, beta);
+  hipLaunchKernelGGL(k_obj_final, dim3((unsigned)N), dim3(kEW), 0, st, w.opart, w.ndual, w.rpri, w.npri, out, (int)N,
+                     D, beta);
+  hipLaunchKernelGGL(k_obj_total, dim3(1), dim3(64), 0, st, out, (int)N);
   return hipGetLastError() == hipSuccess ? CSC_OK : CSC_EHIP;
 }
 

@@ -251,11 +251,16 @@ __global__ void d_crop_taps(const float2* __restrict__ Dsp, float* __restrict__ 
 }
 
 // out[0] = sum of n partials (fixed order), single thread.
-__global__ void d_sum(const double* __restrict__ part, int64_t n, double* __restrict__ out) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+// out = sum of n partials by one workgroup of 1024 threads in a fixed order
+// (thread t sums every 1024th partial from t, then the block reduction).
+constexpr int kSumT = 1024;
+
+__global__ __launch_bounds__(kSumT) void d_sum(const double* __restrict__ part, int64_t n, double* __restrict__ out) {
+  __shared__ double red[kSumT / 64];
   double s = 0.0;
-  for (int64_t i = 0; i < n; ++i) s += part[i];
-  out[0] = s;
+  for (int64_t i = threadIdx.x; i < n; i += kSumT) s += part[i];
+  const double t = block_sum(s, red);
+  if (threadIdx.x == 0) out[0] = t;
 }
 
 // ----------------------------------------------------------------- host
@@ -387,7 +392,7 @@ int run_backward(const Plan& pl, const float* b, const float* d, float beta, con
     }
   }
   if (finish_taps(pl, w, dd, false, st) != hipSuccess) return CSC_EHIP;
-  hipLaunchKernelGGL(d_sum, dim3(1), dim3(64), 0, st, w.bpart, w.nbpart, dbeta);
+  hipLaunchKernelGGL(d_sum, dim3(1), dim3(kSumT), 0, st, w.bpart, w.nbpart, dbeta);
   return hipGetLastError() == hipSuccess ? CSC_OK : CSC_EHIP;
 }
 
@@ -413,7 +418,7 @@ int run_loss_grad(const Plan& pl, const float* b, const float* d, const float* z
   hipLaunchKernelGGL(d_dbar, dim3(dblk(D), pl.p), dim3(kDW), 0, st, w.Wb, (const float2*)nullptr, w.cw.E, w.lam,
                      (const float2*)nullptr, w.Dbar, pl.n, pl.p, pl.g[0], pl.g[1], pl.g[2]);
   if (finish_taps(pl, w, dd, false, st) != hipSuccess) return CSC_EHIP;
-  hipLaunchKernelGGL(d_sum, dim3(1), dim3(64), 0, st, w.cw.rpri, int64_t(pl.n) * w.cw.npri, dbeta);
+  hipLaunchKernelGGL(d_sum, dim3(1), dim3(kSumT), 0, st, w.cw.rpri, int64_t(pl.n) * w.cw.npri, dbeta);
   return hipGetLastError() == hipSuccess ? CSC_OK : CSC_EHIP;
 }
 
