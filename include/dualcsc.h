@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define CSC_ABI_VERSION 1
+#define CSC_ABI_VERSION 2
 
 /* Return codes. */
 #define CSC_OK 0
@@ -194,19 +194,22 @@ int csc_objective(const csc_shape* shape, const float* b, const float* d,
 /*
  * Differentiable coding (grayscale, J = 1; J > 1 gives CSC_EUNSUPPORTED).
  *
- * csc_code_unrolled runs `iters` literal iterations of eq:Inference_solution
- * from z = theta = 0 at the fixed per-image steps rho [N] (device) and
- * writes z^T.  If `ckpt` is non-NULL it receives the state (z, theta) at
- * iterations 0, every, 2 every, ... : ceil(iters / every) records of
- * [2][N][K][grid] floats (device, caller-owned).
+ * csc_code_unrolled runs `iters` iterations of eq:Inference_solution from
+ * z = theta = 0 at the fixed per-image steps rho [N] (device) and writes z^T
+ * (the iteration of csc_code, so z^T equals csc_code's result bit for bit).
+ * If `ckpt` is non-NULL it receives the solver state at iterations 0, every,
+ * 2 every, ... : ceil(iters / every) consecutive records of
+ * csc_unrolled_record_floats(shape) floats each (device, caller-owned;
+ * opaque apart from its first [2][N][K][grid] floats, z then theta).
  *
  * csc_code_backward is the reverse pass of that solve: given the same
  * inputs, the checkpoints and zbar = dL/dz^T [N][K][grid], it writes
  * dd = dL/dd [K][1][fsupp] and *dbeta = dL/dbeta (device float64) through
  * every iteration (the filters enter each iteration through D and
  * (D D^T + I/rho)^-1).  It replays `every` iterations at a time from their
- * checkpoint.  Kinks: the clip passes gradient iff |u| < beta strictly and
- * contributes sign(u) to dL/dbeta iff |u| > beta.
+ * record, reproducing the forward's states exactly, so the result does not
+ * depend on `every`.  Kinks: the clip passes gradient iff |u| < beta
+ * strictly and contributes sign(u) to dL/dbeta iff |u| > beta.
  *
  * csc_loss_grad evaluates the objective of eq:CSC, loss [N + 1] (as
  * csc_objective), and its gradients: zbar = D^T (D z - x) + beta sign(z)
@@ -218,6 +221,10 @@ int csc_objective(const csc_shape* shape, const float* b, const float* d,
  *         CSC_EUNSUPPORTED, CSC_EWORKSPACE, CSC_EHIP.
  */
 size_t csc_unrolled_workspace_bytes(const csc_shape* shape, int every);
+
+/* Floats in one checkpoint record of csc_code_unrolled for `shape`
+ * (N (2K + 6) grid); 0 for an invalid or J > 1 shape. */
+int64_t csc_unrolled_record_floats(const csc_shape* shape);
 
 int csc_code_unrolled(const csc_shape* shape, const float* b, const float* d,
                       float beta, const float* rho, int iters, int every,

@@ -26,7 +26,7 @@ __all__ = [
 _PKG = os.path.dirname(os.path.abspath(__file__))
 _LIB_NAME = "libdualcsc.so"
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 OK, EINVAL, EWORKSPACE, EUNSUPPORTED, EHIP = 0, -1, -2, -3, -4
 OP_CODE, OP_LEARN, OP_OBJECTIVE = 1, 2, 3
 ADAPTIVE_RHO, Z_ZERO, THETA_ZERO, GAMMA_ZERO, USE_GRAPH = 0x1, 0x2, 0x4, 0x8, 0x10
@@ -125,6 +125,8 @@ def load() -> ctypes.CDLL:
     lib.csc_batch_autotune.argtypes = [bp, vp, vp, f32, f32, i32, vp, vp, sz, vp, ctypes.POINTER(ctypes.c_int32), i32]
     lib.csc_unrolled_workspace_bytes.restype = sz
     lib.csc_unrolled_workspace_bytes.argtypes = [sp, i32]
+    lib.csc_unrolled_record_floats.restype = ctypes.c_int64
+    lib.csc_unrolled_record_floats.argtypes = [sp]
     lib.csc_code_unrolled.restype = i32
     lib.csc_code_unrolled.argtypes = [sp, vp, vp, f32, vp, i32, i32, vp, vp, vp, sz, vp]
     lib.csc_code_backward.restype = i32
@@ -653,7 +655,8 @@ def _make_unrolled():
             rho_t = _rho_tensor(rho, N, b.device)
             nck = (int(iters) + int(every) - 1) // int(every)
             z = torch.empty((N, K) + tuple(b.shape[2:]), dtype=torch.float32, device=b.device)
-            ckpt = torch.empty(max(1, nck) * 2 * z.numel(), dtype=torch.float32, device=b.device)
+            rec = lib.csc_unrolled_record_floats(ctypes.byref(shape))
+            ckpt = torch.empty(max(1, nck) * rec, dtype=torch.float32, device=b.device)
             ws, nbytes = _diff_ws(shape, every, b.device)
             _check(lib.csc_code_unrolled(ctypes.byref(shape), _ptr(b), _ptr(d), float(beta), _ptr(rho_t),
                                          int(iters), int(every), _ptr(z), _ptr(ckpt), ws, nbytes, _stream()))

@@ -11,9 +11,6 @@
 
 namespace dcsc {
 
-int run_code(const Plan& pl, const float* b, const float* d, float beta, float* rho, int iters, unsigned flags,
-             float* z, float* theta, double* resid, void* ws, hipStream_t st, float tol = 0.0f,
-             int* iters_done = nullptr);
 size_t run_code_ws(const Plan& pl);
 int run_objective(const Plan& pl, const float* b, const float* d, const float* z, float beta, double* out, void* ws,
                   hipStream_t st);
@@ -340,6 +337,12 @@ int csc_learn_tol(const csc_shape* shape, const float* b, const float* z, float*
   if ((rc = check_ws(ws, ws_bytes, run_learn_ws(pl))) != CSC_OK) return rc;
   return run_learn(pl, b, z, d, mu, gamma, inner_iters, max_cg, flags, ws, static_cast<hipStream_t>(stream), cg_tol,
                    cg_counts);
+}
+
+int64_t csc_unrolled_record_floats(const csc_shape* shape) {
+  Plan pl;
+  if (make_plan(shape, &pl) != CSC_OK || pl.j != 1) return 0;
+  return code_record_floats(pl);
 }
 
 size_t csc_unrolled_workspace_bytes(const csc_shape* shape, int every) {

@@ -21,9 +21,6 @@
 
 namespace dcsc {
 
-int run_code(const Plan& pl, const float* b, const float* d, float beta, float* rho, int iters, unsigned flags,
-             float* z, float* theta, double* resid, void* ws, hipStream_t st, float tol = 0.0f,
-             int* iters_done = nullptr);
 size_t run_code_ws(const Plan& pl);
 
 constexpr int kChunk = 32;

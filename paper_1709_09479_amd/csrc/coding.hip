@@ -868,12 +868,14 @@ static hipError_t iterate_maps(const Plan& pl, CodeWs& w, float* z, float* theta
 }
 
 int run_code(const Plan& pl, const float* b, const float* d, float beta, float* rho, int iters, unsigned flags,
-             float* z, float* theta, double* resid, void* ws, hipStream_t st, float tol, int* iters_done) {
+             float* z, float* theta, double* resid, void* ws, hipStream_t st, float tol, int* iters_done, float* ckpt,
+             int every) {
+  const bool adaptive = (flags & CSC_ADAPTIVE_RHO) != 0;
+  if (ckpt && (tol > 0.0f || adaptive || every < 1 || pl.zoff)) return CSC_EINVAL;
   CodeWs w;
   carve_code(pl, ws, &w);
   const int64_t D = pl.dsz, N = pl.n, J = pl.j;
   const int T = pl.g[0], H = pl.g[1], W = pl.g[2];
-  const bool adaptive = (flags & CSC_ADAPTIVE_RHO) != 0;
   const bool z_zero = (flags & CSC_Z_ZERO) != 0;
   const bool th_zero = theta == nullptr || (flags & CSC_THETA_ZERO) != 0;
   const int64_t ns = N * J * D;
@@ -905,17 +907,35 @@ int run_code(const Plan& pl, const float* b, const float* d, float beta, float* 
   const bool need_rho = adaptive || resid != nullptr || tol_mode;
   const double thr_pri = (double)tol * sqrt((double)pl.k * (double)D);
   const double thr_dual = (double)tol * sqrt((double)J * (double)D);
+  // a record holds z and theta, then the spectral state the next iteration
+  // starts from (yhat, Thhat and lam), so that replay_code resumes the loop
+  // exactly where it was
+  const int64_t nz = N * pl.k * D, rec_floats = code_record_floats(pl);
+  auto save_spec = [&](float* rec) {
+    float* s = rec + 2 * nz;
+    hipLaunchKernelGGL(k_copy_f, dim3(nblk(2 * ns)), dim3(kEW), 0, st, s, (const float*)w.yh, 2 * ns);
+    hipLaunchKernelGGL(k_copy_f, dim3(nblk(2 * ns)), dim3(kEW), 0, st, s + 2 * ns, (const float*)w.Th, 2 * ns);
+    hipLaunchKernelGGL(k_copy_f, dim3(nblk(2 * ns)), dim3(kEW), 0, st, s + 4 * ns, (const float*)w.lam, 2 * ns);
+  };
+  if (ckpt && iters > 0) {
+    hipLaunchKernelGGL(k_fill_f2, dim3(nblk(nz)), dim3(kEW), 0, st, (float2*)ckpt, nz);
+    save_spec(ckpt);
+  }
   for (int it = 0; it < iters; ++it) {
     const bool last = it == iters - 1;
     // theta is written by the last iteration, or by every one when the loop may stop early
-    if ((e = iterate_maps(pl, w, z, (last || tol_mode) ? theta : nullptr, beta, st, stop)) != hipSuccess)
-      return CSC_EHIP;
+    float* th_out = (last || tol_mode) ? theta : nullptr;
+    float* rec = (ckpt && !last && (it + 1) % every == 0) ? ckpt + int64_t((it + 1) / every) * rec_floats : nullptr;
+    if (rec) th_out = rec + nz;
+    if ((e = iterate_maps(pl, w, z, th_out, beta, st, stop)) != hipSuccess) return CSC_EHIP;
+    if (rec) hipLaunchKernelGGL(k_copy_f, dim3(nblk(nz)), dim3(kEW), 0, st, rec, z, nz);
     const int solve_next = (!last && !adaptive) ? 1 : 0;
     {
       TraceScope trace(kTraceCodeSpec, st);
       LAUNCH_J(k_spec, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.part, w.G, w.xh, w.yh, w.Th, w.lam, w.rho,
                w.rdual, w.ngp, T, H, W, solve_next, stop);
     }
+    if (rec) save_spec(rec);
     if (need_rho)
       hipLaunchKernelGGL(k_rho, dim3((unsigned)N), dim3(64), 0, st, w.rpri, w.npri, w.rdual, w.ndual, w.rho, resid,
                          it, (int)N, D, adaptive ? 1 : 0, stop, tol_mode ? w.rres : nullptr);
@@ -929,6 +949,32 @@ int run_code(const Plan& pl, const float* b, const float* d, float beta, float* 
     else hipLaunchKernelGGL(k_fill_i, dim3(1), dim3(64), 0, st, iters_done, iters);
   }
   return hipGetLastError() == hipSuccess ? CSC_OK : CSC_EHIP;
+}
+
+int64_t code_record_floats(const Plan& pl) {
+  return int64_t(pl.n) * pl.dsz * (2 * int64_t(pl.k) + 6 * int64_t(pl.j));
+}
+
+hipError_t replay_code(const Plan& pl, CodeWs& w, const float* rho, float beta, const float* rec, int len, float* seg,
+                       hipStream_t st) {
+  const int64_t D = pl.dsz, N = pl.n, nz = N * pl.k * D, ns = N * pl.j * D;
+  const int T = pl.g[0], H = pl.g[1], W = pl.g[2];
+  const float* s = rec + 2 * nz;
+  hipLaunchKernelGGL(k_copy_f, dim3(nblk(N)), dim3(kEW), 0, st, w.rho, rho, N);
+  hipLaunchKernelGGL(k_copy_f, dim3(nblk(2 * nz)), dim3(kEW), 0, st, seg, rec, 2 * nz);
+  hipLaunchKernelGGL(k_copy_f, dim3(nblk(2 * ns)), dim3(kEW), 0, st, (float*)w.yh, s, 2 * ns);
+  hipLaunchKernelGGL(k_copy_f, dim3(nblk(2 * ns)), dim3(kEW), 0, st, (float*)w.Th, s + 2 * ns, 2 * ns);
+  hipLaunchKernelGGL(k_copy_f, dim3(nblk(2 * ns)), dim3(kEW), 0, st, (float*)w.lam, s + 4 * ns, 2 * ns);
+  for (int i = 1; i < len; ++i) {
+    float* zi = seg + int64_t(i) * 2 * nz;
+    hipLaunchKernelGGL(k_copy_f, dim3(nblk(nz)), dim3(kEW), 0, st, zi, zi - 2 * nz, nz);
+    hipError_t e = iterate_maps(pl, w, zi, zi + nz, beta, st, nullptr);
+    if (e != hipSuccess) return e;
+    if (i < len - 1)
+      LAUNCH_J(k_spec, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.part, w.G, w.xh, w.yh, w.Th, w.lam, w.rho, w.rdual,
+               w.ngp, T, H, W, 1, nullptr);
+  }
+  return hipGetLastError();
 }
 
 size_t run_code_ws(const Plan& pl) { return code_ws_bytes(pl); }

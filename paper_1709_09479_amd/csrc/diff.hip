@@ -3,12 +3,13 @@
 // sparsity weight, and the gradient of the objective of eq:CSC.  Grayscale
 // (J = 1).
 //
-// The unrolled solve runs the literal updates of eq:Inference_solution with
-// theta kept (w = theta + z/rho, s = D w - x/rho, lam = P s with
+// The unrolled solve is the coding iteration (coding.hip), which records its
+// state every `every` iterations.  The reverse pass replays each segment from
+// its record with that same iteration, then walks the segment's iterations in
+// reverse through the literal updates of eq:Inference_solution with theta
+// kept (w = theta + z/rho, s = D w - x/rho, lam = P s with
 // P = (D D^T + I/rho)^-1, v = D^T lam, u = v - z/rho, theta' = clip(u, +-beta),
-// z' = z + rho (theta' - v)) and stores (z, theta) every `every` iterations.
-// The backward pass replays each segment from its checkpoint and walks its
-// iterations in reverse:
+// z' = z + rho (theta' - v)), whose intermediates it recomputes at each state:
 //   t = thbar' + rho zbar';  ubar = t [|u| < beta];  betabar += t sign(u) [|u| > beta]
 //   vbar = ubar - rho zbar';  zbar = zbar' - ubar/rho
 //   sbar = P D vbar;  wbar = D^T sbar;  thetabar = wbar;  zbar += wbar/rho
@@ -87,26 +88,6 @@ __global__ void d_reduce_solve(const float2* __restrict__ buf, const float2* __r
   }
   const float den = G[f].x + ir;
   out[int64_t(n) * D + f] = make_float2(s.x / den, s.y / den);
-}
-
-// Forward update from V = D * (v_2p + i v_2p+1): theta' = clip(v - z/rho), z' = z + rho (theta' - v).
-__global__ void d_update(const float2* __restrict__ Vb, const float* __restrict__ z, const float* __restrict__ th,
-                         float* __restrict__ zo, float* __restrict__ tho, const float* __restrict__ rho, float beta,
-                         int K, int P, int64_t D) {
-  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int p = blockIdx.y, n = blockIdx.z;
-  if (f >= D) return;
-  const float r = rho[n], ir = 1.0f / r, invD = 1.0f / (float)D;
-  const float2 c = Vb[(int64_t(n) * P + p) * D + f];
-  const int64_t a = (int64_t(n) * K + 2 * p) * D + f;
-  for (int s = 0; s < 2 && 2 * p + s < K; ++s) {
-    const float v = (s ? c.y : c.x) * invD;
-    const float zz = z[a + s * D];
-    const float t1 = fminf(fmaxf(v - zz * ir, -beta), beta);
-    tho[a + s * D] = t1;
-    zo[a + s * D] = zz + r * (t1 - v);
-  }
-  (void)th;
 }
 
 // Adjoint of the clip and z updates.  In: V (forward D^T lam, unscaled),
@@ -268,7 +249,7 @@ __global__ __launch_bounds__(kSumT) void d_sum(const double* __restrict__ part, 
 struct DiffWs {
   CodeWs cw;
   float2 *Wb, *Vb, *lam, *sbar, *Dbar;
-  float *zs, *ths, *zbar, *thbar, *seg;
+  float *zbar, *thbar, *seg;
   double* bpart;
   int64_t nbpart;
 };
@@ -283,8 +264,6 @@ static size_t carve_diff(const Plan& pl, int every, void* base, DiffWs* w) {
   w->lam = c.take<float2>(N * D);
   w->sbar = c.take<float2>(N * D);
   w->Dbar = c.take<float2>(P * D);
-  w->zs = c.take<float>(N * K * D);
-  w->ths = c.take<float>(N * K * D);
   w->zbar = c.take<float>(N * K * D);
   w->thbar = c.take<float>(N * K * D);
   w->seg = c.take<float>(int64_t(every > 0 ? every : 1) * 2 * N * K * D);
@@ -298,10 +277,10 @@ size_t run_diff_ws(const Plan& pl, int every) {
   return carve_diff(pl, every, nullptr, &w);
 }
 
-// One literal forward iteration: (z, th) -> (zo, tho); leaves what in Wb,
-// lam, and D * (D^T lam) pairs in Vb.
-static hipError_t lit_forward(const Plan& pl, DiffWs& w, const float* z, const float* th, float* zo, float* tho,
-                              const float* rho, float beta, hipStream_t st, bool update) {
+// Intermediates of one literal iteration at the state (z, th): the spectra
+// of w in Wb, lam, and D * (D^T lam) pairs in Vb.
+static hipError_t lit_intermediates(const Plan& pl, DiffWs& w, const float* z, const float* th, const float* rho,
+                              hipStream_t st) {
   const int64_t D = pl.dsz;
   const dim3 g3(dblk(D), pl.p, pl.n);
   hipLaunchKernelGGL(d_pack_w, g3, dim3(kDW), 0, st, z, th, w.Wb, rho, pl.k, pl.p, D);
@@ -312,7 +291,6 @@ static hipError_t lit_forward(const Plan& pl, DiffWs& w, const float* z, const f
   launch_make_v(pl, w.cw.E, w.lam, w.Vb, st);
   e = fft_grids(w.Vb, int64_t(pl.n) * pl.p, pl.g, +1, st);
   if (e != hipSuccess) return e;
-  if (update) hipLaunchKernelGGL(d_update, g3, dim3(kDW), 0, st, w.Vb, z, th, zo, tho, rho, beta, pl.k, pl.p, D);
   return hipGetLastError();
 }
 
@@ -322,7 +300,7 @@ static hipError_t adjoint_iter(const Plan& pl, DiffWs& w, const float* z, const 
                                float beta, hipStream_t st) {
   const int64_t D = pl.dsz;
   const dim3 g3(dblk(D), pl.p, pl.n);
-  hipError_t e = lit_forward(pl, w, z, th, nullptr, nullptr, rho, beta, st, false);
+  hipError_t e = lit_intermediates(pl, w, z, th, rho, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(d_adj_clip, g3, dim3(kDW), 0, st, w.Vb, z, w.zbar, w.thbar, rho, beta, w.bpart, pl.k, pl.p, D);
   if ((e = fft_grids(w.Vb, int64_t(pl.n) * pl.p, pl.g, -1, st)) != hipSuccess) return e;
@@ -344,23 +322,16 @@ static hipError_t finish_taps(const Plan& pl, DiffWs& w, float* dd, bool accumul
   return hipGetLastError();
 }
 
+// The forward runs the coding path's iteration (the updates of
+// eq:Inference_solution in implicit-theta form) and records the checkpoints
+// as it passes them; the reverse pass replays each segment with the same
+// iteration from its record (so the states, and with them the gradient, do
+// not depend on the checkpoint interval) and differentiates the literal
+// iteration above at each state.
 int run_unrolled(const Plan& pl, const float* b, const float* d, float beta, const float* rho, int iters, int every,
                  float* z, float* ckpt, void* ws, hipStream_t st) {
-  DiffWs w;
-  carve_diff(pl, every, ws, &w);
-  const int64_t nz = int64_t(pl.n) * pl.k * pl.dsz;
-  if (setup_spectra(pl, b, d, w.cw, st) != hipSuccess) return CSC_EHIP;
-  hipLaunchKernelGGL(d_zero, dim3(dblk(nz)), dim3(kDW), 0, st, z, nz);
-  hipLaunchKernelGGL(d_zero, dim3(dblk(nz)), dim3(kDW), 0, st, w.ths, nz);
-  for (int it = 0; it < iters; ++it) {
-    if (ckpt && it % every == 0) {
-      float* c = ckpt + int64_t(it / every) * 2 * nz;
-      hipLaunchKernelGGL(d_copy, dim3(dblk(nz)), dim3(kDW), 0, st, c, z, nz);
-      hipLaunchKernelGGL(d_copy, dim3(dblk(nz)), dim3(kDW), 0, st, c + nz, w.ths, nz);
-    }
-    if (lit_forward(pl, w, z, w.ths, z, w.ths, rho, beta, st, true) != hipSuccess) return CSC_EHIP;
-  }
-  return hipGetLastError() == hipSuccess ? CSC_OK : CSC_EHIP;
+  return run_code(pl, b, d, beta, const_cast<float*>(rho), iters, CSC_Z_ZERO | CSC_THETA_ZERO, z, nullptr, nullptr,
+                  ws, st, 0.0f, nullptr, ckpt, every);
 }
 
 int run_backward(const Plan& pl, const float* b, const float* d, float beta, const float* rho, int iters, int every,
@@ -377,15 +348,8 @@ int run_backward(const Plan& pl, const float* b, const float* d, float beta, con
   const int nseg = (iters + every - 1) / every;
   for (int sgi = nseg - 1; sgi >= 0; --sgi) {
     const int c0 = sgi * every, len = (iters - c0 < every) ? iters - c0 : every;
-    const float* ck = ckpt + int64_t(sgi) * 2 * nz;
-    float* s0 = w.seg;
-    hipLaunchKernelGGL(d_copy, dim3(dblk(nz)), dim3(kDW), 0, st, s0, ck, nz);
-    hipLaunchKernelGGL(d_copy, dim3(dblk(nz)), dim3(kDW), 0, st, s0 + nz, ck + nz, nz);
-    for (int i = 1; i < len; ++i) {
-      const float* zi = w.seg + int64_t(i - 1) * 2 * nz;
-      float* zo = w.seg + int64_t(i) * 2 * nz;
-      if (lit_forward(pl, w, zi, zi + nz, zo, zo + nz, rho, beta, st, true) != hipSuccess) return CSC_EHIP;
-    }
+    const float* ck = ckpt + int64_t(sgi) * code_record_floats(pl);
+    if (replay_code(pl, w.cw, rho, beta, ck, len, w.seg, st) != hipSuccess) return CSC_EHIP;
     for (int i = len - 1; i >= 0; --i) {
       const float* zi = w.seg + int64_t(i) * 2 * nz;
       if (adjoint_iter(pl, w, zi, zi + nz, rho, beta, st) != hipSuccess) return CSC_EHIP;

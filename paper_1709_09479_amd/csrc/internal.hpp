@@ -85,6 +85,23 @@ struct CodeWs {
 size_t carve_code(const Plan& pl, void* base, CodeWs* w);
 // Filter pair spectra E, Gram blocks G and image spectra xhat.
 hipError_t setup_spectra(const Plan& pl, const float* b, const float* d, CodeWs& w, hipStream_t st);
+// ADMM coding of eq:Inference_solution (csc_code / csc_code_tol).  tol > 0
+// selects the stopping rule; iters_done receives the count.  With `ckpt`
+// (dense maps, fixed steps and count only) the state after 0, every,
+// 2 every, ... (< iters) iterations is written to consecutive records of
+// code_record_floats(pl) floats: z [N][K][grid], theta [N][K][grid], then
+// yhat, Thhat and lam ([N][J][grid] complex each) as the next iteration
+// reads them.
+int run_code(const Plan& pl, const float* b, const float* d, float beta, float* rho, int iters, unsigned flags,
+             float* z, float* theta, double* resid, void* ws, hipStream_t st, float tol = 0.0f,
+             int* iters_done = nullptr, float* ckpt = nullptr, int every = 0);
+int64_t code_record_floats(const Plan& pl);
+// Resumes run_code's fixed-step loop from a record: seg[i] ([2][N][K][grid],
+// z then theta) receives the state after i more iterations, i < len, equal
+// bit for bit to the states the uninterrupted loop passes through.  E, G and
+// xh of `w` must hold the spectra of the same images and filters.
+hipError_t replay_code(const Plan& pl, CodeWs& w, const float* rho, float beta, const float* rec, int len, float* seg,
+                       hipStream_t st);
 // part <- per-group spectral contributions sum_p DFT(maps pair) conj(E_p);
 // l1 <- partial sums of |maps| ([N][npri]).
 hipError_t forward_maps(const Plan& pl, const float* maps, CodeWs& w, double* l1, hipStream_t st);

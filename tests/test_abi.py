@@ -163,3 +163,15 @@ def test_tolerance_entry_point_argument_errors():
     assert learn(cg=-1) == dc.EINVAL
     assert learn(flags=dc.USE_GRAPH) == dc.EINVAL
     assert learn(wsb=wl - 1) == dc.EWORKSPACE
+
+
+def test_unrolled_record_size():
+    """A checkpoint record holds z and theta ([N][K][grid] each) and the
+    solver's spectral state (three [N][1][grid] complex arrays); J > 1 has no
+    differentiable form."""
+    lib = dc.load()
+    for n, k, grid in ((2, 4, (64, 64)), (3, 7, (32, 128)), (1, 100, (256, 256))):
+        s = shape(n=n, k=k, grid=grid)
+        assert lib.csc_unrolled_record_floats(ctypes.byref(s)) == n * grid[0] * grid[1] * (2 * k + 6)
+    assert lib.csc_unrolled_record_floats(ctypes.byref(shape(j=3))) == 0
+    assert lib.csc_unrolled_record_floats(ctypes.byref(shape(grid=(60, 64)))) == 0

@@ -33,6 +33,50 @@ def test_unrolled_forward_matches_oracle(lib):
     assert np.abs(N(z) - ref).max() <= 1e-4
 
 
+def test_unrolled_forward_is_the_coding_iteration(lib):
+    """The unrolled forward runs csc_code's iteration: equal z bit for bit,
+    with checkpoints recorded or not, on the split-path grid too."""
+    for grid, n in (((64, 64), 2), ((256, 256), 1)):
+        rng = np.random.default_rng(11)
+        b = np.stack([synth.contrast_normalize(synth.one_over_f(rng, grid))[None] * 30 for _ in range(n)])
+        d = synth.unit_filters(6, 1, (11, 11), 3)
+        z_code = N(lib.code(T(b), T(d), 1.0, 10.0, 9)[0])
+        for every in (1, 4, 9):
+            z = N(lib.unrolled_code(T(b), T(d), 1.0, 10.0, 9, every))
+            assert np.array_equal(z, z_code), (grid, every)
+
+
+def test_unrolled_records_hold_the_states(lib):
+    """Records 0, 1, 2 of iters = 9, every = 4 hold (z, theta) after 0, 4
+    and 8 iterations (csc_code's, bit for bit), at the record stride the
+    library reports, and nothing is written past the last record."""
+    import ctypes
+    import torch
+    cfg = synth.CONFIGS["small"]
+    b, d = synth.make_inputs(cfg, n=2)
+    bt, dt = T(b), T(d)
+    shape = lib._shape_of(bt, dt)
+    L = lib.load()
+    rec = L.csc_unrolled_record_floats(ctypes.byref(shape))
+    nz = cfg.k * 2 * b.shape[2] * b.shape[3]
+    assert rec == 2 * nz + 6 * 2 * b.shape[2] * b.shape[3]
+    rho = torch.full((2,), cfg.rho, dtype=torch.float32, device="cuda")
+    z = torch.empty((2, cfg.k) + b.shape[2:], dtype=torch.float32, device="cuda")
+    ckpt = torch.full((3 * rec + 1024,), 7.0, dtype=torch.float32, device="cuda")
+    ws, nbytes = lib._diff_ws(shape, 4, bt.device)
+    rc = L.csc_code_unrolled(ctypes.byref(shape), lib._ptr(bt), lib._ptr(dt), cfg.beta, lib._ptr(rho), 9, 4,
+                             lib._ptr(z), lib._ptr(ckpt), ws, nbytes, lib._stream())
+    assert rc == 0
+    torch.cuda.synchronize()
+    c = ckpt.cpu().numpy()
+    assert np.all(c[3 * rec:] == 7.0)
+    assert np.all(c[:2 * nz] == 0.0)
+    for r, it in ((1, 4), (2, 8)):
+        zr, thr = lib.code(bt, dt, cfg.beta, cfg.rho, it, want_theta=True)[:2]
+        assert np.array_equal(c[r * rec:r * rec + nz], zr.cpu().numpy().ravel()), r
+        assert np.array_equal(c[r * rec + nz:r * rec + 2 * nz], thr.cpu().numpy().ravel()), r
+
+
 def test_loss_grad_matches_oracle(lib):
     import torch
     b, d = synth.make_inputs(synth.CONFIGS["small"], n=2)
