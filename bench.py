@@ -43,12 +43,15 @@ def alg_bytes_per_iter(n, j, k, d):
     return 8 * n * k * d + 4 * j * k * d + 12 * n * j * d
 
 
-def alg_bytes_pass_a(n, j, k, h, w, m2):
+def alg_bytes_pass_a(n, j, k, h, w, m1, m2):
     """Bytes one learning pass A must move: the N x ceil(K/2) code pair spectra
     (4 N K D), the CG vector at the canonical half of the frequencies
-    (8 N J (H/2+1) W) and the row-stage output (8 J ceil(K/2) H M2)."""
+    (8 N J (H/2+1) W) and its output, one M1 x M2 column-stage partial per
+    row group of 256 / W canonical rows (8 J ceil(K/2) G M1 M2)."""
     p = (k + 1) // 2
-    return 8 * n * p * h * w + 8 * n * j * (h // 2 + 1) * w + 8 * j * p * h * m2
+    r = 256 // w
+    g = (h // 2 + r) // r
+    return 8 * n * p * h * w + 8 * n * j * (h // 2 + 1) * w + 8 * j * p * g * m1 * m2
 
 
 def alg_bytes_pass_b(n, j, k, h, w):
@@ -219,6 +222,81 @@ def bench_backward(dc, synth, np, torch, reps=2, only_plain=False):
     }
 
 
+def bench_sweep_point(dc, synth, np, torch, cfg, steps=5, conv_steps=30):
+    """One point of a scaling sweep: the time of one outer step of the
+    alternation at fixed counts (coding, learning, objective; median, p10,
+    p90 over `steps` steps after one warm-up step), and the time to
+    convergence of the convergence-driven alternation (tau = 1e-3 on the
+    relative change of the objective, ADMM stopped at an RMS residual of 1e-3
+    of the images' RMS within 100 iterations, CG at a relative residual of
+    1e-3 within 50 steps, at most `conv_steps` outer steps)."""
+    b, d0 = synth.make_inputs(cfg)
+    dev = torch.device("cuda:0")
+    bt = torch.from_numpy(b).to(dev)
+    N, J, K = b.shape[0], cfg.j, cfg.k
+    D = int(np.prod(cfg.grid))
+    adaptive = cfg.rho is None
+    rho0 = cfg.rho0 if adaptive else cfg.rho
+    st = {"d": torch.from_numpy(d0).to(dev), "z": None, "theta": None, "gamma": None,
+          "mu": torch.ones(K, dtype=torch.float32, device=dev),
+          "rho": torch.full((N,), rho0, dtype=torch.float32, device=dev)}
+
+    def step():
+        st["z"], st["theta"], _, st["rho"] = dc.code(bt, st["d"], cfg.beta, st["rho"], cfg.t_in, z=st["z"],
+                                                     theta=st["theta"], adaptive=adaptive, want_theta=True)
+        st["d"], st["mu"], st["gamma"] = dc.learn(bt, st["z"], cfg.fsupp, st["mu"], st["gamma"], cfg.learn_inner,
+                                                  cfg.learn_cg, out=st["d"])
+        st["obj"] = dc.objective(bt, st["d"], st["z"], cfg.beta)
+
+    step()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record()
+    for i in range(steps):
+        step()
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+    density = float(torch.count_nonzero(st["z"]).item()) / st["z"].numel()
+    del st
+
+    tol = 1e-3 * float(np.sqrt(np.mean(b.astype(np.float64) ** 2)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = dc.learn_dictionary(bt, torch.from_numpy(d0).to(dev), cfg.beta, rho0, 100, conv_steps,
+                              cfg.learn_inner, 50, adaptive=adaptive, tau=1e-3, tol=tol, cg_tol=1e-3)
+    torch.cuda.synchronize()
+    conv_s = time.perf_counter() - t0
+    code_its = [int(n) for n in out["coding_iters"]]
+    cg = [int(c) for counts in out["cg_counts"] for c in counts]
+    return {
+        "point": cfg.name, "n": N, "j": J, "k": K, "grid": list(cfg.grid), "fsupp": list(cfg.fsupp),
+        "beta": cfg.beta, "rho": "adaptive from %g" % rho0 if adaptive else rho0, "t_in": cfg.t_in,
+        "learn": [cfg.learn_inner, cfg.learn_cg],
+        "outer_step_ms": {"median": float(np.median(ms)), "p10": float(np.percentile(ms, 10)),
+                          "p90": float(np.percentile(ms, 90))},
+        "cp_it_per_s": N * K * D * cfg.t_in / (float(np.median(ms)) / 1e3),
+        "code_density": density,
+        "convergence": {"seconds": conv_s, "outer_steps": int(out["steps"]), "admm_iters": code_its,
+                        "cg_steps_total": int(sum(cg)), "objective": float(out["objectives"][-1].item())},
+    }
+
+
+def run_sweeps(names):
+    import numpy as np
+    import torch
+
+    import paper_1709_09479_amd as dc
+    import synth
+
+    dc.load()
+    for name in names:
+        for cfg in synth.SWEEPS[name]:
+            r = bench_sweep_point(dc, synth, np, torch, cfg)
+            r["sweep"] = name
+            print(json.dumps(r), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -232,6 +310,9 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB")
     ap.add_argument("--profile-leg", choices=["batched", "unrolled-plain"], default=None,
                     help="run only the timed calls of one leg (for counter collection)")
+    ap.add_argument("--sweep", default=None, metavar="NAMES",
+                    help="comma-separated scaling sweeps (gray_K, gray_N, rgb_K, rgb_N, video_K, or all): "
+                         "one JSON line per point instead of the benchmark line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on one GPU only (the build targets a single MI355X); "
@@ -240,6 +321,15 @@ def main():
 
     if args.calibrate_copy > 0:
         calibrate_copy(args.calibrate_copy)
+        return
+    if args.sweep:
+        import synth
+        names = list(synth.SWEEPS) if args.sweep == "all" else args.sweep.split(",")
+        unknown = [n for n in names if n not in synth.SWEEPS]
+        if unknown:
+            print("unknown sweep(s): %s" % ", ".join(unknown), file=sys.stderr)
+            sys.exit(2)
+        run_sweeps(names)
         return
 
     import numpy as np
@@ -328,7 +418,7 @@ def main():
                 "alg_bytes_per_launch": alg_bytes}
 
     roof_a = hbm_roofline("l_passA_rows<1> (learning pass A: sum over images of conj(zhat) p, row stage of "
-                          "the support projection)", alg_bytes_pass_a(N, J, K, H, W, cfg.fsupp[1]), la_ms,
+                          "the support projection)", alg_bytes_pass_a(N, J, K, H, W, cfg.fsupp[0], cfg.fsupp[1]), la_ms,
                           la_cnt, counter_traffic("l_passA_rows<1>"))
     roof_b = hbm_roofline("l_passB_c<1> (learning pass B: p + sum over filters of zhat U)",
                           alg_bytes_pass_b(N, J, K, H, W), lb_ms, lb_cnt, counter_traffic("l_passB_c<1>"))

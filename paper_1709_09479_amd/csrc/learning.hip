@@ -35,12 +35,6 @@ constexpr int kLW = 256;
 #ifndef LEARN_BW
 #define LEARN_BW 16  // pass B: wavefronts per workgroup
 #endif
-#ifndef LEARN_MID_CR
-#define LEARN_MID_CR 2  // column stage: rows m1 per workgroup
-#endif
-#ifndef LEARN_COLS_CPB
-#define LEARN_COLS_CPB 512  // last stage: canonical frequencies per workgroup
-#endif
 
 static unsigned lblk(int64_t n, int b = kLW) { return (unsigned)((n + b - 1) / b); }
 
@@ -167,16 +161,17 @@ __global__ __launch_bounds__(lt_threads(H * W)) void l_crop_tile(float2* __restr
 template <int J>
 __global__ __launch_bounds__(kLW) void l_passB(const float2* __restrict__ Zh, const float2* __restrict__ Up,
                                                const float2* __restrict__ v, float2* __restrict__ q,
-                                               const float2* __restrict__ xh, double* __restrict__ dots, int N,
-                                               int P, int T, int H, int W, const int* __restrict__ cgf) {
+                                               const float2* __restrict__ xh, double* __restrict__ dots,
+                                               double* __restrict__ vdots, int N, int P, int T, int H, int W,
+                                               const int* __restrict__ cgf) {
   if (cgf && cgf[0]) return;
   __shared__ double red[kLW / 64];
   const int64_t D = int64_t(T) * H * W;
   const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int n = blockIdx.y;
-  double s[J];
+  double s[J], s2[J];
 #pragma unroll
-  for (int j = 0; j < J; ++j) s[j] = 0.0;
+  for (int j = 0; j < J; ++j) s[j] = s2[j] = 0.0;
   if (f < D) {
     const int64_t fn = lneg(f, T, H, W);
     float2 acc[J];
@@ -205,6 +200,7 @@ __global__ __launch_bounds__(kLW) void l_passB(const float2* __restrict__ Zh, co
         s[j] = (double)qq.x * qq.x + (double)qq.y * qq.y;
       } else {
         s[j] = (double)vv.x * qq.x + (double)vv.y * qq.y;
+        s2[j] = (double)vv.x * vv.x + (double)vv.y * vv.y;
       }
       q[o] = qq;
     }
@@ -213,6 +209,10 @@ __global__ __launch_bounds__(kLW) void l_passB(const float2* __restrict__ Zh, co
   for (int j = 0; j < J; ++j) {
     const double t = block_sum(s[j], red);
     if (threadIdx.x == 0) dots[(int64_t(j) * N + n) * gridDim.x + blockIdx.x] = t;
+    if (vdots) {
+      const double t2 = block_sum(s2[j], red);
+      if (threadIdx.x == 0) vdots[(int64_t(j) * N + n) * gridDim.x + blockIdx.x] = t2;
+    }
   }
 }
 
@@ -250,19 +250,23 @@ __device__ __forceinline__ bool canon2(int i, int H, int W, int& f, int& fm) {
   return true;
 }
 
-// Pass A and the row stage.  A workgroup of 256 threads owns R = 256/W
-// canonical rows f1 (and their mirrors H - f1) of one pair p; every thread
-// forms t_k,j = sum_n conj(zhat_k^n) v_j^n at (f1, f2) and, by conjugation,
-// at -(f1, f2), pair-packed as t_2p + i t_2p+1.  The block parks the 2R rows
-// in LDS and evaluates the 2R x M2 row sums with g lanes per output.  S1 is
-// [J][P][H][M2].
+// Pass A, the row stage and this row group's share of the column stage.  A
+// workgroup of 256 threads owns R = 256/W canonical rows f1 (and their
+// mirrors H - f1) of one pair p; every thread forms
+// t_k,j = sum_n conj(zhat_k^n) v_j^n at (f1, f2) and, by conjugation, at
+// -(f1, f2), pair-packed as t_2p + i t_2p+1.  The block parks the 2R rows in
+// LDS, evaluates the 2R x M2 row sums s[row][m2] with g lanes per output, and
+// writes its part of the column DFT,
+//   Upart[j][p][bx][m1][m2] = sum over its rows of s[row][m2] e^{+2 pi i row m1 / H},
+// each of the rows 0 .. H-1 counted by exactly one workgroup.
 template <int J>
 __global__ __launch_bounds__(256) void l_passA_rows(const float2* __restrict__ Zh, const float2* __restrict__ v,
-                                                    float2* __restrict__ S1, int N, int P, int H, int W, int M2,
-                                                    int g, const int* __restrict__ cgf) {
+                                                    float2* __restrict__ Upart, int N, int P, int H, int W, int M1,
+                                                    int M2, int g, const int* __restrict__ cgf) {
   if (cgf && cgf[0]) return;
   __shared__ float2 tw[256];
   __shared__ float2 ts[512];  // [slot][f2]; slots R..2R-1 hold the mirrored rows
+  __shared__ float2 rsum[2 * 16 * kPruneMax];  // [slot][m2] row sums (zero where a row is not this block's)
   load_twiddles(tw);
   const int lw = __builtin_ctz(W), R = 256 >> lw, D = H * W;
   const int rs = threadIdx.x >> lw, f2 = threadIdx.x & (W - 1);
@@ -323,99 +327,107 @@ __global__ __launch_bounds__(256) void l_passA_rows(const float2* __restrict__ Z
         acc.y += __shfl_down(acc.y, off, lanes);
       }
       const int r1 = blockIdx.x * R + (slot < R ? slot : slot - R);
-      const bool keep = ob < O && l == 0 && r1 <= H / 2 && !(slot >= R && (r1 == 0 || r1 == H / 2));
-      if (keep) {
-        const int row = slot < R ? r1 : H - r1;
-        S1[((int64_t(j) * P + p) * H + row) * M2 + m2] = acc;
+      const bool keep = r1 <= H / 2 && !(slot >= R && (r1 == 0 || r1 == H / 2));
+      if (ob < O && l == 0) rsum[slot * M2 + m2] = keep ? acc : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    // this block's rows of the column DFT (2R terms per output)
+    const int MM = M1 * M2;
+    float2* up = Upart + ((int64_t(j) * P + p) * gridDim.x + blockIdx.x) * MM;
+    for (int o = threadIdx.x; o < MM; o += 256) {
+      const int m1 = o / M2, m2 = o % M2;
+      float2 acc = make_float2(0.f, 0.f);
+      for (int slot = 0; slot < 2 * R; ++slot) {
+        const int r1 = blockIdx.x * R + (slot < R ? slot : slot - R);
+        const int row = (slot < R ? r1 : H - r1) & (H - 1);
+        acc = cadd(acc, cmul(rsum[slot * M2 + m2], twl(tw, (row * m1) & (H - 1), H, +1)));
       }
+      up[o] = acc;
     }
     __syncthreads();
   }
 }
 
-// Column and back-row stages for `cr` rows m1 of one (pair, channel):
-// R3[j][p][m1][f2].  With d given, the column stage alone recovers the
-// filters instead (eq:Learning_Solution): d_k,j[m] = -u_k,j[m] for the two
-// filters of the pair, and R3 is not written.
-__global__ __launch_bounds__(256) void l_prune_mid(const float2* __restrict__ S1, float2* __restrict__ R3,
-                                                   const float* __restrict__ mu, float* __restrict__ d, int K, int J,
-                                                   int P, int H, int W, int M1, int M2, int cr, int g, const int* __restrict__ cgf) {
+// Sum of the column-stage partials of pass A for one (pair, channel) in a
+// fixed order, scaled by 1/(D 2 mu) per filter of the pair (u of the support
+// projection).  Threads o < M1 M2 hold u[o].
+__device__ __forceinline__ float2 sum_upart(const float2* __restrict__ up, int G, int MM, int o, float sa, float sb) {
+  float2 a[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) a[t] = make_float2(0.f, 0.f);
+  int gi = 0;
+  for (; gi + 4 <= G; gi += 4) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) a[t] = cadd(a[t], up[int64_t(gi + t) * MM + o]);
+  }
+  for (; gi < G; ++gi) a[0] = cadd(a[0], up[int64_t(gi) * MM + o]);
+  const float2 t = cadd(cadd(a[0], a[1]), cadd(a[2], a[3]));
+  return make_float2(t.x * sa, t.y * sb);
+}
+
+// Back-row and last stages for a slice of kUcCols columns.  A workgroup of
+// (slice, pair, channel) sums u (sum_upart), forms the back rows
+// r[m1][c] = sum_m2 u[m1][m2] e^{-2 pi i c m2 / W} for the slice's columns
+// and their mirrors W - c, and writes Uc[j][p][i] = (U_2p, U_2p+1) at the
+// canonical frequencies i = (f1, f2) of the slice (f2 in the slice), pair
+// unpacked, with U(f) = sum_m1 r[m1][f2] e^{-2 pi i f1 m1 / H}.
+constexpr int kUcCols = 8;
+__global__ __launch_bounds__(256) void l_prune_uc(const float2* __restrict__ Upart, float4* __restrict__ Uc,
+                                                  const float* __restrict__ mu, int K, int P, int H, int W, int M1,
+                                                  int M2, int G, const int* __restrict__ cgf) {
   if (cgf && cgf[0]) return;
   __shared__ float2 tw[256];
-  __shared__ float2 s[256 * kPruneMax];
   __shared__ float2 u[kPruneMax * kPruneMax];
-  const int p = blockIdx.x, j = blockIdx.y, m0 = blockIdx.z * cr;
-  const int rows = min(cr, M1 - m0);
+  __shared__ float2 rb[kPruneMax * 2 * kUcCols];  // [m1][slot]: slice columns, then their mirrors
+  const int p = blockIdx.y, j = blockIdx.z, c0 = blockIdx.x * kUcCols, MM = M1 * M2;
   load_twiddles(tw);
-  const float2* s_g = S1 + (int64_t(j) * P + p) * H * M2;
-  for (int i = threadIdx.x; i < H * M2; i += blockDim.x) s[i] = s_g[i];
-  __syncthreads();
   const float invD = 1.0f / (float)(H * W);
   const float sa = invD / (2.0f * mu[2 * p]);
   const float sb = (2 * p + 1 < K) ? invD / (2.0f * mu[2 * p + 1]) : 0.f;
-  // columns: u[m1][m2] = (1/D) sum_f1 s[f1][m2] e^{+2 pi i f1 m1 / H}, scaled
-  const int O = rows * M2, l = threadIdx.x & (g - 1);
-  for (int ob = threadIdx.x / g; ob - threadIdx.x / g < O; ob += 256 / g) {
-    const int o = ob < O ? ob : O - 1;
-    const int m1 = m0 + o / M2, m2 = o % M2;
-    float2 acc = make_float2(0.f, 0.f);
-    for (int f1 = l; f1 < H; f1 += g) acc = cadd(acc, cmul(s[f1 * M2 + m2], twl(tw, (f1 * m1) & (H - 1), H, +1)));
-    for (int off = g >> 1; off > 0; off >>= 1) {
-      acc.x += __shfl_down(acc.x, off, g);
-      acc.y += __shfl_down(acc.y, off, g);
-    }
-    if (ob < O && l == 0) {
-      if (d) {
-        const int64_t msz = int64_t(M1) * M2, m = int64_t(m1) * M2 + m2;
-        d[(int64_t(2 * p) * J + j) * msz + m] = -acc.x * sa;
-        if (2 * p + 1 < K) d[(int64_t(2 * p + 1) * J + j) * msz + m] = -acc.y * sb;
-      } else {
-        u[o] = make_float2(acc.x * sa, acc.y * sb);
-      }
-    }
-  }
-  if (d) return;
+  const float2* up = Upart + (int64_t(j) * P + p) * G * MM;
+  for (int o = threadIdx.x; o < MM; o += 256) u[o] = sum_upart(up, G, MM, o, sa, sb);
   __syncthreads();
-  // back rows: r[m1][f2] = sum_m2 u[m1][m2] e^{-2 pi i f2 m2 / W}
-  float2* r_g = R3 + ((int64_t(j) * P + p) * M1 + m0) * W;
-  for (int q = threadIdx.x; q < rows * W; q += blockDim.x) {
-    const int r = q / W, f2 = q % W;
+  constexpr int C2 = 2 * kUcCols;
+  for (int q = threadIdx.x; q < M1 * C2; q += 256) {
+    const int m1 = q / C2, sl = q % C2;
+    const int c = sl < kUcCols ? c0 + sl : (W - c0 - (sl - kUcCols)) & (W - 1);
     float2 a = make_float2(0.f, 0.f);
-    for (int m2 = 0; m2 < M2; ++m2) a = cadd(a, cmul(u[r * M2 + m2], twl(tw, (f2 * m2) & (W - 1), W, -1)));
-    r_g[q] = a;
+    for (int m2 = 0; m2 < M2; ++m2) a = cadd(a, cmul(u[m1 * M2 + m2], twl(tw, (c * m2) & (W - 1), W, -1)));
+    rb[q] = a;
   }
-}
-
-// Last stage at the canonical frequencies: Uc[j][p][i] = (U_2p, U_2p+1) at
-// the canonical frequency i (pair unpacked), U(f) = sum_m1 r[m1][f2]
-// e^{-2 pi i f1 m1 / H}.  A workgroup stages r = R3[j][p] in LDS and covers
-// `cpb` canonical indices.
-__global__ __launch_bounds__(256) void l_prune_cols(const float2* __restrict__ R3, float4* __restrict__ Uc, int P,
-                                                    int H, int W, int M1, int cpb, const int* __restrict__ cgf) {
-  if (cgf && cgf[0]) return;
-  __shared__ float2 tw[256];
-  __shared__ float2 r[kPruneMax * 256];
-  const int p = blockIdx.y, j = blockIdx.z, nc = (H / 2 + 1) * W;
-  load_twiddles(tw);
-  const float2* r_g = R3 + (int64_t(j) * P + p) * M1 * W;
-  for (int i = threadIdx.x; i < M1 * W; i += 256) r[i] = r_g[i];
   __syncthreads();
-  const int lw = __builtin_ctz(W);
+  const int lw = __builtin_ctz(W), nc = (H / 2 + 1) * W;
   float4* out = Uc + (int64_t(j) * P + p) * nc;
-  const int i1 = min(nc, (int)(blockIdx.x + 1) * cpb);
-  for (int i = blockIdx.x * cpb + threadIdx.x; i < i1; i += 256) {
-    int f, fm;
-    if (!canon2(i, H, W, f, fm)) continue;
-    const int f1 = f >> lw, f2 = f & (W - 1), f2m = (W - f2) & (W - 1);
+  for (int q = threadIdx.x; q < (H / 2 + 1) * kUcCols; q += 256) {
+    const int f1 = q / kUcCols, sl = q % kUcCols, f2 = c0 + sl;
+    if ((f1 == 0 || f1 == H / 2) && f2 > W / 2) continue;  // not canonical (canon2)
     float2 a = make_float2(0.f, 0.f), am = make_float2(0.f, 0.f);
     for (int m1 = 0; m1 < M1; ++m1) {
       const float2 w = twl(tw, (f1 * m1) & (H - 1), H, -1);  // at -f: conj(w)
-      a = cadd(a, cmul(r[m1 * W + f2], w));
-      am = cadd(am, cmulc(r[m1 * W + f2m], w));
+      a = cadd(a, cmul(rb[m1 * C2 + sl], w));
+      am = cadd(am, cmulc(rb[m1 * C2 + kUcCols + sl], w));
     }
     float2 ua, ub;
     unpack_pair(a, am, ua, ub);
-    out[i] = make_float4(ua.x, ua.y, ub.x, ub.y);
+    out[(f1 << lw) | f2] = make_float4(ua.x, ua.y, ub.x, ub.y);
+  }
+}
+
+// Filter recovery (eq:Learning_Solution) from pass A of gamma:
+// d_k,j[m] = -u_k,j[m] for the two filters of pair p (one workgroup per
+// (pair, channel)).
+__global__ __launch_bounds__(256) void l_drec_u(const float2* __restrict__ Upart, const float* __restrict__ mu,
+                                                float* __restrict__ d, int K, int J, int P, int H, int W, int M1,
+                                                int M2, int G) {
+  const int p = blockIdx.x, j = blockIdx.y, MM = M1 * M2;
+  const float invD = 1.0f / (float)(H * W);
+  const float sa = invD / (2.0f * mu[2 * p]);
+  const float sb = (2 * p + 1 < K) ? invD / (2.0f * mu[2 * p + 1]) : 0.f;
+  const float2* up = Upart + (int64_t(j) * P + p) * G * MM;
+  for (int o = threadIdx.x; o < MM; o += 256) {
+    const float2 a = sum_upart(up, G, MM, o, sa, sb);
+    d[(int64_t(2 * p) * J + j) * MM + o] = -a.x;
+    if (2 * p + 1 < K) d[(int64_t(2 * p + 1) * J + j) * MM + o] = -a.y;
   }
 }
 
@@ -438,12 +450,13 @@ constexpr int passb_nb() {
 template <int J>
 __global__ __launch_bounds__(64 * kBW) void l_passB_c(const float2* __restrict__ Zh, const float4* __restrict__ Uc,
                                                       const float2* __restrict__ v, float2* __restrict__ q,
-                                                      const float2* __restrict__ xh, double* __restrict__ dots, int N,
-                                                      int P, int H, int W, int nbc, const int* __restrict__ cgf) {
+                                                      const float2* __restrict__ xh, double* __restrict__ dots,
+                                                      double* __restrict__ vdots, int N, int P, int H, int W, int nbc,
+                                                      const int* __restrict__ cgf) {
   if (cgf && cgf[0]) return;
   constexpr int NB = passb_nb<J>(), NI = NB * J;  // items per lane: (image, channel)
   __shared__ float2 part[kBW][NI][64];
-  __shared__ double wsum[NI];
+  __shared__ double wsum[NI], vsum[NI];
   const int D = H * W, nc = (H / 2 + 1) * W;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int n0 = blockIdx.y * nbc, nb = min(nbc, N - n0);
@@ -492,7 +505,7 @@ __global__ __launch_bounds__(64 * kBW) void l_passB_c(const float2* __restrict__
     float2 a = make_float2(0.f, 0.f);
 #pragma unroll
     for (int w = 0; w < kBW; ++w) a = cadd(a, part[w][it][lane]);
-    double sv = 0.0;
+    double sv = 0.0, s2 = 0.0;
     if (own && u < nb) {
       const int64_t base = (int64_t(n0 + u) * J + j) * D;
       for (int side = 0; side < (self ? 1 : 2); ++side) {
@@ -505,20 +518,32 @@ __global__ __launch_bounds__(64 * kBW) void l_passB_c(const float2* __restrict__
           sv += (double)qq.x * qq.x + (double)qq.y * qq.y;
         } else {
           sv += (double)vv.x * qq.x + (double)vv.y * qq.y;
+          s2 += (double)vv.x * vv.x + (double)vv.y * vv.y;
         }
         q[base + ff] = qq;
       }
     }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) sv += __shfl_down(sv, off, 64);
-    if (lane == 0) wsum[it] = sv;
+    for (int off = 32; off > 0; off >>= 1) {
+      sv += __shfl_down(sv, off, 64);
+      s2 += __shfl_down(s2, off, 64);
+    }
+    if (lane == 0) {
+      wsum[it] = sv;
+      vsum[it] = s2;
+    }
   }
   __syncthreads();
   if (threadIdx.x < J) {
     const int j = threadIdx.x;
-    double t = 0.0;
-    for (int u = 0; u < nb; ++u) t += wsum[u * J + j];
-    dots[int64_t(j) * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x] = t;
+    double t = 0.0, t2 = 0.0;
+    for (int u = 0; u < nb; ++u) {
+      t += wsum[u * J + j];
+      t2 += vsum[u * J + j];
+    }
+    const int64_t o = int64_t(j) * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x;
+    dots[o] = t;
+    if (vdots) vdots[o] = t2;
   }
 }
 
@@ -532,84 +557,70 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ p, int
   return *bcast;
 }
 
-// gamma += alpha p ; r -= alpha q ; partials of |r|^2.  alpha = rr / pAp.
-// `rr` is the running |r|^2 per channel (float64), `pap` the partials.
+// One conjugate-gradient step in the arrangement of Chronopoulos and Gear
+// (1989), which needs a single reduction phase per step: after the operator
+// has produced w = A r, with gamma = |r|^2 and delta = Re<r, w> (partials of
+// pass B, fixed-order sums here),
+//   beta = gamma / gamma'  (0 on the first step),
+//   alpha = gamma / (delta - beta gamma / alpha'),
+//   p = r + beta p,  s = w + beta s  (= A p),  x += alpha p,  r -= alpha s,
+// where gamma', alpha' are the previous step's (sc_in, [2][J]); block (0,0)
+// stores this step's into sc_out.  The iterates are those of the textbook
+// recurrence in exact arithmetic.  Tolerance mode: gamma <= tol^2 |x|^2 in
+// every channel ends the solve before the update.
 template <int J>
-__global__ __launch_bounds__(kLW) void l_cg_step(float2* __restrict__ g, float2* __restrict__ r,
-                                                 const float2* __restrict__ p, const float2* __restrict__ q,
-                                                 const double* __restrict__ rr, const double* __restrict__ pap,
-                                                 int npart, double* __restrict__ rrpart, int N, int64_t D,
-                                                 const int* __restrict__ cgf, int* __restrict__ count) {
+__global__ __launch_bounds__(kLW) void l_cg_cg(float2* __restrict__ x, float2* __restrict__ r,
+                                               float2* __restrict__ p, float2* __restrict__ s,
+                                               const float2* __restrict__ w, const double* __restrict__ dpart,
+                                               const double* __restrict__ gpart, int npart,
+                                               const double* __restrict__ sc_in, double* __restrict__ sc_out,
+                                               int first, int64_t D, int* __restrict__ cgf,
+                                               const double* __restrict__ bb, double tol2, int* __restrict__ count) {
   if (cgf && cgf[0]) return;
   __shared__ double red[kLW / 64];
   __shared__ double bc;
   const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int n = blockIdx.y;
-  if (count && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) count[0] += 1;
-  double alpha[J];
+  const bool lead = blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0;
+  double al[J], be[J];
+  bool conv = cgf != nullptr;
 #pragma unroll
   for (int j = 0; j < J; ++j) {
-    const double pa = sum_partials(pap + int64_t(j) * npart, npart, red, &bc);
-    alpha[j] = pa > 0.0 ? rr[j] / pa : 0.0;
-  }
-  double s[J];
-#pragma unroll
-  for (int j = 0; j < J; ++j) {
-    s[j] = 0.0;
-    if (f < D) {
-      const int64_t o = (int64_t(n) * J + j) * D + f;
-      const float a = (float)alpha[j];
-      const float2 pp = p[o], qq = q[o];
-      float2 gg = g[o], rv = r[o];
-      gg = make_float2(fmaf(a, pp.x, gg.x), fmaf(a, pp.y, gg.y));
-      rv = make_float2(fmaf(-a, qq.x, rv.x), fmaf(-a, qq.y, rv.y));
-      g[o] = gg;
-      r[o] = rv;
-      s[j] = (double)rv.x * rv.x + (double)rv.y * rv.y;
+    const double gam = sum_partials(gpart + int64_t(j) * npart, npart, red, &bc);
+    const double del = sum_partials(dpart + int64_t(j) * npart, npart, red, &bc);
+    const double gp = first ? 0.0 : sc_in[j], ap = first ? 0.0 : sc_in[J + j];
+    const double b = gp > 0.0 ? gam / gp : 0.0;
+    const double den = ap > 0.0 ? del - b * gam / ap : del;
+    al[j] = den > 0.0 ? gam / den : 0.0;
+    be[j] = b;
+    if (lead) {
+      sc_out[j] = gam;
+      sc_out[J + j] = al[j];
     }
+    conv = conv && gam <= tol2 * bb[j];
   }
-#pragma unroll
-  for (int j = 0; j < J; ++j) {
-    const double t = block_sum(s[j], red);
-    if (threadIdx.x == 0) rrpart[(int64_t(j) * N + n) * gridDim.x + blockIdx.x] = t;
+  if (conv) {
+    if (lead) cgf[0] = 1;
+    return;
   }
-}
-
-// p = r + (rr_new / rr) p; block (0,0) records rr_new into rr_next.
-template <int J>
-__global__ __launch_bounds__(kLW) void l_cg_dir(float2* __restrict__ p, const float2* __restrict__ r,
-                                                const double* __restrict__ rr, const double* __restrict__ rrpart,
-                                                int npart, double* __restrict__ rr_next, int copy_r, int64_t D,
-                                                int* __restrict__ cgf, const double* __restrict__ bb, double tol2) {
-  if (cgf && cgf[0]) return;
-  __shared__ double red[kLW / 64];
-  __shared__ double bc;
-  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int n = blockIdx.y;
-  double bet[J];
-  bool conv = true;
-#pragma unroll
-  for (int j = 0; j < J; ++j) {
-    const double rn = sum_partials(rrpart + int64_t(j) * npart, npart, red, &bc);
-    bet[j] = (!copy_r && rr[j] > 0.0) ? rn / rr[j] : 0.0;
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) rr_next[j] = rn;
-    conv = conv && cgf && rn <= tol2 * bb[j];
-  }
-  // tolerance mode: |r|^2 <= tol^2 |x|^2 in every channel ends this CG solve;
-  // the later launches of the solve return at once
-  if (conv && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) cgf[0] = 1;
+  if (count && lead) count[0] += 1;
   if (f < D) {
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const int64_t o = (int64_t(n) * J + j) * D + f;
-      const float2 rv = r[o];
-      if (copy_r) {
-        p[o] = rv;
-      } else {
-        const float2 pp = p[o];
-        const float b = (float)bet[j];
-        p[o] = make_float2(fmaf(b, pp.x, rv.x), fmaf(b, pp.y, rv.y));
+      const float a = (float)al[j], b = (float)be[j];
+      const float2 rv = r[o], wv = w[o];
+      float2 pp = rv, ss = wv;
+      if (!first) {
+        const float2 po = p[o], so = s[o];
+        pp = make_float2(fmaf(b, po.x, rv.x), fmaf(b, po.y, rv.y));
+        ss = make_float2(fmaf(b, so.x, wv.x), fmaf(b, so.y, wv.y));
       }
+      const float2 xv = x[o];
+      p[o] = pp;
+      s[o] = ss;
+      x[o] = make_float2(fmaf(a, pp.x, xv.x), fmaf(a, pp.y, xv.y));
+      r[o] = make_float2(fmaf(-a, ss.x, rv.x), fmaf(-a, ss.y, rv.y));
     }
   }
 }
@@ -706,14 +717,20 @@ static int lanes_for(int outs, int len) { return std::max(1, std::min(std::min(6
 static int passb_nb_host(int J) { return J == 1 ? LEARN_B_NB1 : (J == 2 ? 4 : 2); }
 static int passb_chunks(const Plan& pl) { return (pl.n + passb_nb_host(pl.j) - 1) / passb_nb_host(pl.j); }
 
+// pass-A row groups of the pruned path (R = 256 / W canonical rows each)
+static int passa_groups(const Plan& pl) {
+  const int H = pl.g[1], R = 256 / pl.g[2];
+  return (H / 2 + R) / R;
+}
+
 static int dot_parts(const Plan& pl) {
   return pruned2d(pl) ? (int)canon_blocks(pl) * passb_chunks(pl) : pl.n * (int)lblk(pl.dsz);
 }
 
 struct LearnWs {
-  float2 *Zh, *xh, *gh, *rh, *ph, *qh, *Tp, *S1, *R3;
+  float2 *Zh, *xh, *gh, *rh, *ph, *qh, *sh, *Tp, *Upart;
   float4* Uc;   // pruned path: U at the canonical frequencies, pair unpacked
-  double *dots, *rr;  // dots: pass-B partials then residual partials; rr: [4][J]
+  double *dots, *rr;  // dots: pass-B partials of Re<r, A r>, then of |r|^2; rr: two [2][J] CG scalar sets
   double* bb;         // tolerance mode: |xhat_j|^2 per channel
   int* cgf;           // tolerance mode: CG stop flag of the current multiplier step
   int nB;  // pruned path: pass-B partials per channel (one per workgroup)
@@ -731,9 +748,9 @@ static size_t carve_learn(const Plan& pl, void* base, LearnWs* w) {
   w->rh = c.take<float2>(N * J * D);
   w->ph = c.take<float2>(N * J * D);
   w->qh = c.take<float2>(N * J * D);
+  w->sh = c.take<float2>(N * J * D);
   w->Tp = c.take<float2>(J * P * D);
-  w->S1 = c.take<float2>(J * P * int64_t(pl.g[1]) * pl.fs[2]);
-  w->R3 = c.take<float2>(J * P * int64_t(pl.fs[1]) * pl.g[2]);
+  w->Upart = c.take<float2>(J * P * int64_t(passa_groups(pl)) * pl.fs[1] * pl.fs[2]);
   w->Uc = c.take<float4>(J * P * int64_t(pl.g[1] / 2 + 1) * pl.g[2]);
   w->dots = c.take<double>(J * (int64_t(w->npartB) + std::max(w->npartB, w->npartS)));
   w->rr = c.take<double>(4 * J);
@@ -768,47 +785,42 @@ static bool crop_tile_launch(const Plan& pl, float2* Tp, const float* mu, hipStr
 }
 
 // ------------------------------------------------ pruned operator (host)
-// U for A v: pass A with the row stage, the column and back-row stages into
-// R3, the last stage into Uc.
+// U for A v: pass A with the row stage and the column-stage partials, then
+// the back-row and last stages into Uc.
 static hipError_t pruned_zt_proj(const Plan& pl, LearnWs& w, const float2* v, const float* mu, hipStream_t st,
                                  const int* cgf) {
-  const int H = pl.g[1], W = pl.g[2], R = 256 / W, M1 = pl.fs[1], M2 = pl.fs[2];
+  const int H = pl.g[1], W = pl.g[2], R = 256 / W, M1 = pl.fs[1], M2 = pl.fs[2], G = passa_groups(pl);
   {
     TraceScope trace(kTraceLearnA, st);
-    LJ(l_passA_rows, pl.j, dim3((H / 2 + R) / R, pl.p), dim3(256), st, w.Zh, v, w.S1, pl.n, pl.p, H, W, M2,
+    LJ(l_passA_rows, pl.j, dim3(G, pl.p), dim3(256), st, w.Zh, v, w.Upart, pl.n, pl.p, H, W, M1, M2,
        lanes_for(2 * R * M2, W), cgf);
   }
-  const int cr = LEARN_MID_CR;
-  hipLaunchKernelGGL(l_prune_mid, dim3(pl.p, pl.j, (M1 + cr - 1) / cr), dim3(256), 0, st, w.S1, w.R3, mu, nullptr,
-                     pl.k, pl.j, pl.p, H, W, M1, M2, cr, lanes_for(cr * M2, H), cgf);
-  const int nc = (H / 2 + 1) * W, cpb = LEARN_COLS_CPB;
-  hipLaunchKernelGGL(l_prune_cols, dim3((nc + cpb - 1) / cpb, pl.p, pl.j), dim3(256), 0, st, w.R3, w.Uc, pl.p, H, W,
-                     M1, cpb, cgf);
+  hipLaunchKernelGGL(l_prune_uc, dim3(W / kUcCols, pl.p, pl.j), dim3(256), 0, st, w.Upart, w.Uc, mu, pl.k, pl.p, H,
+                     W, M1, M2, G, cgf);
   return hipGetLastError();
 }
 
 // d_k = -S Z_k^T gamma / (2 mu_k) through pass A and the column stage.
 static hipError_t pruned_drecover(const Plan& pl, LearnWs& w, const float* mu, float* d, hipStream_t st) {
-  const int H = pl.g[1], W = pl.g[2], R = 256 / W, M1 = pl.fs[1], M2 = pl.fs[2];
+  const int H = pl.g[1], W = pl.g[2], R = 256 / W, M1 = pl.fs[1], M2 = pl.fs[2], G = passa_groups(pl);
   {
     TraceScope trace(kTraceLearnA, st);
-    LJ(l_passA_rows, pl.j, dim3((H / 2 + R) / R, pl.p), dim3(256), st, w.Zh, w.gh, w.S1, pl.n, pl.p, H, W, M2,
+    LJ(l_passA_rows, pl.j, dim3(G, pl.p), dim3(256), st, w.Zh, w.gh, w.Upart, pl.n, pl.p, H, W, M1, M2,
        lanes_for(2 * R * M2, W), nullptr);
   }
-  const int cr = LEARN_MID_CR;
-  hipLaunchKernelGGL(l_prune_mid, dim3(pl.p, pl.j, (M1 + cr - 1) / cr), dim3(256), 0, st, w.S1, w.R3, mu, d, pl.k,
-                     pl.j, pl.p, H, W, M1, M2, cr, lanes_for(cr * M2, H), nullptr);
+  hipLaunchKernelGGL(l_drec_u, dim3(pl.p, pl.j), dim3(256), 0, st, w.Upart, mu, d, pl.k, pl.j, pl.p, H, W, M1, M2,
+                     G);
   return hipGetLastError();
 }
 
-// q = v + Z U (pass B); with xh: q = -x - (v + Z U).  Partials to `part`
-// ([J][nB]).
+// q = v + Z U (pass B); with xh: q = -x - (v + Z U).  Partials ([J][nB]) of
+// Re<v, q> (|q|^2 with xh) to `part`, of |v|^2 to `vpart` if given.
 static void pruned_passB(const Plan& pl, LearnWs& w, const float2* v, float2* q, const float2* xh, double* part,
-                         hipStream_t st, const int* cgf) {
+                         double* vpart, hipStream_t st, const int* cgf) {
   const int chunks = passb_chunks(pl), nbc = (pl.n + chunks - 1) / chunks;
   TraceScope trace(kTraceLearnB, st);
-  LJ(l_passB_c, pl.j, dim3(canon_blocks(pl), chunks), dim3(64 * kBW), st, w.Zh, w.Uc, v, q, xh, part, pl.n, pl.p,
-     pl.g[1], pl.g[2], nbc, cgf);
+  LJ(l_passB_c, pl.j, dim3(canon_blocks(pl), chunks), dim3(64 * kBW), st, w.Zh, w.Uc, v, q, xh, part, vpart, pl.n,
+     pl.p, pl.g[1], pl.g[2], nbc, cgf);
 }
 
 // Up <- DFT(S^T S IDFT(pass A of v) / (2 mu)).
@@ -830,12 +842,14 @@ static hipError_t apply_zt_proj(const Plan& pl, LearnWs& w, const float2* v, con
   return fft_grids(w.Tp, int64_t(pl.j) * pl.p, pl.g, -1, st);
 }
 
-// q = v + Z Up (pass B); with xh: q = -x - (v + Z Up).  Dot partials to dots.
+// q = v + Z Up (pass B); with xh: q = -x - (v + Z Up).  Dot partials to
+// dots (and of |v|^2 to vdots if given), as pruned_passB.
 static void apply_passB(const Plan& pl, LearnWs& w, const float2* v, float2* q, const float2* xh, double* dots,
-                        hipStream_t st, const int* cgf) {
+                        double* vdots, hipStream_t st, const int* cgf) {
   const int T = pl.g[0], H = pl.g[1], W = pl.g[2];
   TraceScope trace(kTraceLearnB, st);
-  LJ(l_passB, pl.j, dim3(lblk(pl.dsz), pl.n), dim3(kLW), st, w.Zh, w.Tp, v, q, xh, dots, pl.n, pl.p, T, H, W, cgf);
+  LJ(l_passB, pl.j, dim3(lblk(pl.dsz), pl.n), dim3(kLW), st, w.Zh, w.Tp, v, q, xh, dots, vdots, pl.n, pl.p, T, H,
+     W, cgf);
 }
 
 int run_learn(const Plan& pl, const float* b, const float* z, float* d, float* mu, float* gamma, int inner_iters,
@@ -858,8 +872,6 @@ int run_learn(const Plan& pl, const float* b, const float* z, float* d, float* m
   const dim3 vgrid(lblk(D), pl.n);
   double* pap = w.dots;
   double* rrp = w.dots + J * w.npartB;
-  double* rr_a = w.rr;
-  double* rr_b = w.rr + J;
   const bool pruned = pruned2d(pl);
   // tolerance mode: each multiplier step's CG stops once |r| <= cg_tol |x|
   // in every channel (relative residual of A gamma = -x); the remaining
@@ -869,32 +881,34 @@ int run_learn(const Plan& pl, const float* b, const float* z, float* d, float* m
   const double tol2 = (double)cg_tol * (double)cg_tol;
   if (tol_mode) hipLaunchKernelGGL(l_norm2, dim3((unsigned)J), dim3(kLW), 0, st, w.xh, w.bb, (int)N, (int)J, D);
   const int npB = pruned ? w.nB : w.npartB;
+  // the operator A v = v + sum_k 1/(2 mu_k) Z_k S^T S Z_k^T v into q (with xh:
+  // q = -x - A v), dot partials as pruned_passB
+  auto apply_A = [&](const float2* v, float2* q, const float2* xh, double* part, double* vpart) -> hipError_t {
+    hipError_t err;
+    if (pruned) {
+      if ((err = pruned_zt_proj(pl, w, v, mu, st, cgf)) != hipSuccess) return err;
+      pruned_passB(pl, w, v, q, xh, part, vpart, st, cgf);
+    } else {
+      if ((err = apply_zt_proj(pl, w, v, mu, st, cgf)) != hipSuccess) return err;
+      apply_passB(pl, w, v, q, xh, part, vpart, st, cgf);
+    }
+    return hipGetLastError();
+  };
   for (int it = 0; it < inner_iters; ++it) {
     int* cnt = cg_counts ? cg_counts + it : nullptr;
     if (tol_mode) hipLaunchKernelGGL(l_cg_reset, dim3(1), dim3(64), 0, st, cgf, cnt);
     else if (cnt) hipLaunchKernelGGL(l_cg_reset, dim3(1), dim3(64), 0, st, w.cgf, cnt);
-    // r = -x - A gamma ; p = r ; rr = |r|^2
-    if (pruned) {
-      if ((e = pruned_zt_proj(pl, w, w.gh, mu, st, cgf)) != hipSuccess) return CSC_EHIP;
-      pruned_passB(pl, w, w.gh, w.rh, w.xh, rrp, st, cgf);
-    } else {
-      if ((e = apply_zt_proj(pl, w, w.gh, mu, st, cgf)) != hipSuccess) return CSC_EHIP;
-      apply_passB(pl, w, w.gh, w.rh, w.xh, rrp, st, cgf);
-    }
-    LJ(l_cg_dir, pl.j, vgrid, dim3(kLW), st, w.ph, w.rh, rr_a, rrp, npB, rr_a, 1, D, cgf, w.bb, tol2);
+    // r = -x - A gamma, then per step w = A r and the update (l_cg_cg)
+    if ((e = apply_A(w.gh, w.rh, w.xh, rrp, nullptr)) != hipSuccess) return CSC_EHIP;
+    double* sc_in = w.rr;
+    double* sc_out = w.rr + 2 * J;
     for (int q = 0; q < cg_iters; ++q) {
-      if (pruned) {
-        if ((e = pruned_zt_proj(pl, w, w.ph, mu, st, cgf)) != hipSuccess) return CSC_EHIP;
-        pruned_passB(pl, w, w.ph, w.qh, nullptr, pap, st, cgf);
-      } else {
-        if ((e = apply_zt_proj(pl, w, w.ph, mu, st, cgf)) != hipSuccess) return CSC_EHIP;
-        apply_passB(pl, w, w.ph, w.qh, nullptr, pap, st, cgf);
-      }
-      LJ(l_cg_step, pl.j, vgrid, dim3(kLW), st, w.gh, w.rh, w.ph, w.qh, rr_a, pap, npB, rrp, pl.n, D, cgf, cnt);
-      LJ(l_cg_dir, pl.j, vgrid, dim3(kLW), st, w.ph, w.rh, rr_a, rrp, w.npartS, rr_b, 0, D, cgf, w.bb, tol2);
-      double* t = rr_a;
-      rr_a = rr_b;
-      rr_b = t;
+      if ((e = apply_A(w.rh, w.qh, nullptr, pap, rrp)) != hipSuccess) return CSC_EHIP;
+      LJ(l_cg_cg, pl.j, vgrid, dim3(kLW), st, w.gh, w.rh, w.ph, w.sh, w.qh, pap, rrp, npB, sc_in, sc_out,
+         q == 0 ? 1 : 0, D, cgf, w.bb, tol2, cnt);
+      double* t = sc_in;
+      sc_in = sc_out;
+      sc_out = t;
     }
     // d_k = -S Z_k^T gamma / (2 mu_k) ; mu_k <- mu_k ||d_k||
     if (pruned) {

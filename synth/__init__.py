@@ -228,6 +228,27 @@ CONFIGS = {
 }
 
 
+def _vary(base: str, tag: str, **kw) -> CSCConfig:
+    return dataclasses.replace(CONFIGS[base], name="%s_%s" % (base, tag), **kw)
+
+
+# Scaling sweeps over the number of filters K and of images N (the shapes of
+# the paper's scalability study, Sec. 5.3, and of its TCSC study on colour
+# images and video, Sec. 5.4), on this generator: gray 100 x 100 images
+# (128^2 grid) around the alternation workload; RGB 128^2 images at ten
+# images or K = 64; the RGB video volume.  K = 49 and K = 100 are the paper's
+# own dictionary sizes.  Each point keeps its base workload's seeds, steps
+# and iteration counts (images are the first N of the base set where N is
+# not larger).
+SWEEPS = {
+    "gray_K": [_vary("learn", "K%d" % k, k=k) for k in (16, 25, 36, 49, 64, 81, 100)],
+    "gray_N": [_vary("learn", "N%d" % n, n=n) for n in (1, 2, 5, 10, 20, 50, 100)],
+    "rgb_K": [_vary("tensor", "K%d" % k, n=10, k=k) for k in (8, 16, 32, 64, 100)],
+    "rgb_N": [_vary("tensor", "N%d" % n, n=n) for n in (1, 5, 10, 20, 50, 100)],
+    "video_K": [_vary("video", "K%d" % k, k=k) for k in (8, 16, 32, 64)],
+}
+
+
 def make_inputs(cfg: CSCConfig, n: Optional[int] = None):
     """(b, d0) for a uniform-grid config: b [N][J][*grid] f32, d0 [K][J][*fsupp] f32.
     ``n`` limits the number of images (the first n of the full set)."""

@@ -176,7 +176,7 @@ def learn_tol(d_ref):
 
 
 @pytest.mark.parametrize("grid,j,k", [((64, 64), 1, 8), ((64, 64), 1, 7), ((32, 64), 3, 6),
-                                      ((256, 256), 1, 4)])
+                                      ((128, 128), 3, 5), ((256, 256), 1, 4)])
 def test_learn(lib, grid, j, k):
     b, d0 = rand_case(31 + k, 3, j, k, grid, (11, 11))
     z = oracle.code(b, d0, 1.0, 5.0, 10)["z"].astype(np.float32)
@@ -184,6 +184,21 @@ def test_learn(lib, grid, j, k):
     mu0 = np.linspace(0.8, 1.5, k)
     d_ref, mu_ref, g_ref = oracle.learn(b, z, (11, 11), mu0.astype(np.float32), None, 3, 6)
     d, mu, gamma = lib.learn(T(b), T(z), (11, 11), T(mu0), None, 3, 6)
+    assert np.abs(N(d) - d_ref).max() <= learn_tol(d_ref)
+    np.testing.assert_allclose(N(mu), mu_ref, rtol=1e-4)
+    assert np.abs(N(gamma) - g_ref).max() <= 1e-4 * max(1.0, np.abs(g_ref).max())
+
+
+def test_learn_3d(lib):
+    """Learning on a 3-D grid with J = 3 (the colour video form): the general
+    path (axis FFTs, support crop of a 3-D tile)."""
+    fs = (3, 5, 5)
+    b, d0 = rand_case(51, 2, 3, 4, (8, 16, 16), fs)
+    z = oracle.code(b, d0, 1.0, 5.0, 10)["z"].astype(np.float32)
+    assert density(z) > 0.005
+    mu0 = np.linspace(0.8, 1.5, 4)
+    d_ref, mu_ref, g_ref = oracle.learn(b, z, fs, mu0.astype(np.float32), None, 3, 6)
+    d, mu, gamma = lib.learn(T(b), T(z), fs, T(mu0), None, 3, 6)
     assert np.abs(N(d) - d_ref).max() <= learn_tol(d_ref)
     np.testing.assert_allclose(N(mu), mu_ref, rtol=1e-4)
     assert np.abs(N(gamma) - g_ref).max() <= 1e-4 * max(1.0, np.abs(g_ref).max())

@@ -127,3 +127,50 @@ def test_alternation_tau_stops_with_the_oracle(lib):
     out = lib.learn_dictionary(T(b), T(d0), cfg.beta, cfg.rho, 5, 12, 3, 5, tau=tau)
     assert out["steps"] == ref["steps"] < 12
     assert np.abs(N(out["d"]) - ref["d"]).max() <= 1e-3
+
+
+def _rand_case(seed, n, j, k, grid, fsupp, amp=10.0):
+    rng = np.random.default_rng(seed)
+    b = np.zeros((n, j) + grid, np.float32)
+    for i in range(n):
+        for c in range(j):
+            b[i, c] = synth.contrast_normalize(synth.one_over_f(rng, grid)) * amp
+    return b, synth.unit_filters(k, j, fsupp, seed + 1)
+
+
+@pytest.mark.parametrize("grid,fsupp", [((64, 64), (11, 11)), ((8, 16, 16), (3, 5, 5))])
+def test_code_until_colour_and_3d(lib, grid, fsupp):
+    """The ADMM stopping rule with J = 3 on a 2-D grid and on a 3-D grid (the
+    colour image and video forms): the GPU stops at the oracle's iteration
+    (tolerance placed between two residual values that differ by more than
+    10%), with the oracle's codes."""
+    b, d = _rand_case(61, 2, 3, 5, grid, fsupp)
+    K, npix, J = 5, int(np.prod(grid)), 3
+    full = oracle.code(b, d, 0.5, 10.0, 30)
+    worst = np.maximum(full["resid"][:, :, 0] / np.sqrt(K * npix),
+                       full["resid"][:, :, 1] / np.sqrt(J * npix)).max(axis=1)
+    k = int(np.argmax(worst[1:] < 0.9 * worst[:-1])) + 1
+    assert worst[k] < 0.9 * worst[k - 1] and np.all(worst[:k] > worst[k])
+    tol = float(np.sqrt(worst[k] * worst[k - 1]))
+    ref = oracle.code(b, d, 0.5, 10.0, 30, tol=tol)
+    assert ref["iters"] == k + 1
+    z, _, _, _, done = lib.code_until(T(b), T(d), 0.5, 10.0, 30, tol)
+    assert done == ref["iters"]
+    assert np.abs(N(z) - ref["z"]).max() <= CODE_TOL
+
+
+def test_learn_until_3d_colour(lib):
+    """CG stopping rule on the 3-D, J = 3 form: a tolerance that never fires
+    runs csc_learn's iteration (equal filters, bit for bit), and a firing one
+    stops its cold solve within 3 steps of the oracle's count."""
+    fs = (3, 5, 5)
+    b, d0 = _rand_case(71, 2, 3, 4, (8, 16, 16), fs)
+    z = oracle.code(b, d0, 0.5, 10.0, 10)["z"].astype(np.float32)
+    d_fix, _, _ = lib.learn(T(b), T(z), fs, None, None, 2, 6)
+    d_tol, _, _, counts = lib.learn_until(T(b), T(z), fs, None, None, 2, 6, 1e-30)
+    assert counts == [6, 6]
+    assert np.array_equal(N(d_tol), N(d_fix))
+    info = {}
+    oracle.learn(b, z, fs, np.ones(4), None, 1, 80, cg_tol=2e-2, info=info)
+    _, _, _, got = lib.learn_until(T(b), T(z), fs, None, None, 1, 80, 2e-2)
+    assert abs(got[0] - info["cg_counts"][0]) <= 3, (got, info)
