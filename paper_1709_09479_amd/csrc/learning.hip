@@ -371,13 +371,17 @@ __device__ __forceinline__ float2 sum_upart(const float2* __restrict__ up, int G
 // and their mirrors W - c, and writes Uc[j][p][i] = (U_2p, U_2p+1) at the
 // canonical frequencies i = (f1, f2) of the slice (f2 in the slice), pair
 // unpacked, with U(f) = sum_m1 r[m1][f2] e^{-2 pi i f1 m1 / H}.
-constexpr int kUcCols = 8;
+#ifndef LEARN_UC_COLS
+#define LEARN_UC_COLS 8  // columns per workgroup of the back-row and last stages
+#endif
+constexpr int kUcCols = LEARN_UC_COLS;
 __global__ __launch_bounds__(256) void l_prune_uc(const float2* __restrict__ Upart, float4* __restrict__ Uc,
                                                   const float* __restrict__ mu, int K, int P, int H, int W, int M1,
                                                   int M2, int G, const int* __restrict__ cgf) {
   if (cgf && cgf[0]) return;
   __shared__ float2 tw[256];
   __shared__ float2 u[kPruneMax * kPruneMax];
+  __shared__ float2 half[kPruneMax * kPruneMax];
   __shared__ float2 rb[kPruneMax * 2 * kUcCols];  // [m1][slot]: slice columns, then their mirrors
   const int p = blockIdx.y, j = blockIdx.z, c0 = blockIdx.x * kUcCols, MM = M1 * M2;
   load_twiddles(tw);
@@ -385,7 +389,31 @@ __global__ __launch_bounds__(256) void l_prune_uc(const float2* __restrict__ Upa
   const float sa = invD / (2.0f * mu[2 * p]);
   const float sb = (2 * p + 1 < K) ? invD / (2.0f * mu[2 * p + 1]) : 0.f;
   const float2* up = Upart + (int64_t(j) * P + p) * G * MM;
-  for (int o = threadIdx.x; o < MM; o += 256) u[o] = sum_upart(up, G, MM, o, sa, sb);
+  // u = sum of the G partials: with M1 M2 <= 128 the two halves of the
+  // workgroup take the even and the odd partials, added in that order
+  if (MM <= 128) {
+    const int o = threadIdx.x & 127, hf = threadIdx.x >> 7;
+    float2 a[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) a[t] = make_float2(0.f, 0.f);
+    if (o < MM) {
+      int gi = hf;
+      for (; gi + 6 < G; gi += 8) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) a[t] = cadd(a[t], up[int64_t(gi + 2 * t) * MM + o]);
+      }
+      for (; gi < G; gi += 2) a[0] = cadd(a[0], up[int64_t(gi) * MM + o]);
+    }
+    const float2 t = cadd(cadd(a[0], a[1]), cadd(a[2], a[3]));
+    if (hf && o < MM) half[o] = t;
+    __syncthreads();
+    if (!hf && o < MM) {
+      const float2 v = cadd(t, half[o]);
+      u[o] = make_float2(v.x * sa, v.y * sb);
+    }
+  } else {
+    for (int o = threadIdx.x; o < MM; o += 256) u[o] = sum_upart(up, G, MM, o, sa, sb);
+  }
   __syncthreads();
   constexpr int C2 = 2 * kUcCols;
   for (int q = threadIdx.x; q < M1 * C2; q += 256) {
@@ -396,16 +424,27 @@ __global__ __launch_bounds__(256) void l_prune_uc(const float2* __restrict__ Upa
     rb[q] = a;
   }
   __syncthreads();
+  // last stage: a thread keeps one column's back rows (and its mirror's) in
+  // registers and walks the rows f1 = t, t + 32, ...
   const int lw = __builtin_ctz(W), nc = (H / 2 + 1) * W;
   float4* out = Uc + (int64_t(j) * P + p) * nc;
-  for (int q = threadIdx.x; q < (H / 2 + 1) * kUcCols; q += 256) {
-    const int f1 = q / kUcCols, sl = q % kUcCols, f2 = c0 + sl;
+  const int sl = threadIdx.x % kUcCols, f2 = c0 + sl;
+  float2 ra[kPruneMax], rm[kPruneMax];
+#pragma unroll
+  for (int m1 = 0; m1 < kPruneMax; ++m1) {
+    ra[m1] = m1 < M1 ? rb[m1 * C2 + sl] : make_float2(0.f, 0.f);
+    rm[m1] = m1 < M1 ? rb[m1 * C2 + kUcCols + sl] : make_float2(0.f, 0.f);
+  }
+  for (int f1 = threadIdx.x / kUcCols; f1 <= H / 2; f1 += 256 / kUcCols) {
     if ((f1 == 0 || f1 == H / 2) && f2 > W / 2) continue;  // not canonical (canon2)
     float2 a = make_float2(0.f, 0.f), am = make_float2(0.f, 0.f);
-    for (int m1 = 0; m1 < M1; ++m1) {
-      const float2 w = twl(tw, (f1 * m1) & (H - 1), H, -1);  // at -f: conj(w)
-      a = cadd(a, cmul(rb[m1 * C2 + sl], w));
-      am = cadd(am, cmulc(rb[m1 * C2 + kUcCols + sl], w));
+#pragma unroll
+    for (int m1 = 0; m1 < kPruneMax; ++m1) {
+      if (m1 < M1) {
+        const float2 w = twl(tw, (f1 * m1) & (H - 1), H, -1);  // at -f: conj(w)
+        a = cadd(a, cmul(ra[m1], w));
+        am = cadd(am, cmulc(rm[m1], w));
+      }
     }
     float2 ua, ub;
     unpack_pair(a, am, ua, ub);
