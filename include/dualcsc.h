@@ -208,8 +208,10 @@ int csc_objective(const csc_shape* shape, const float* b, const float* d,
  * every iteration (the filters enter each iteration through D and
  * (D D^T + I/rho)^-1).  It replays `every` iterations at a time from their
  * record, reproducing the forward's states exactly, so the result does not
- * depend on `every`.  Kinks: the clip passes gradient iff |u| < beta
- * strictly and contributes sign(u) to dL/dbeta iff |u| > beta.
+ * depend on `every`.  Kinks: the branch of the clip at each code is the
+ * forward's own (gradient passes where its soft threshold returned zero,
+ * i.e. |u| <= beta in its float arithmetic, and sign(u) enters dL/dbeta
+ * elsewhere); the measure-zero ties |u| = beta count as passed.
  *
  * csc_loss_grad evaluates the objective of eq:CSC, loss [N + 1] (as
  * csc_objective), and its gradients: zbar = D^T (D z - x) + beta sign(z)

@@ -955,8 +955,8 @@ int64_t code_record_floats(const Plan& pl) {
   return int64_t(pl.n) * pl.dsz * (2 * int64_t(pl.k) + 6 * int64_t(pl.j));
 }
 
-hipError_t replay_code(const Plan& pl, CodeWs& w, const float* rho, float beta, const float* rec, int len, float* seg,
-                       hipStream_t st) {
+hipError_t replay_code(const Plan& pl, CodeWs& w, const float* rho, float beta, const float* rec, int nstates,
+                       float* seg, hipStream_t st) {
   const int64_t D = pl.dsz, N = pl.n, nz = N * pl.k * D, ns = N * pl.j * D;
   const int T = pl.g[0], H = pl.g[1], W = pl.g[2];
   const float* s = rec + 2 * nz;
@@ -965,12 +965,12 @@ hipError_t replay_code(const Plan& pl, CodeWs& w, const float* rho, float beta, 
   hipLaunchKernelGGL(k_copy_f, dim3(nblk(2 * ns)), dim3(kEW), 0, st, (float*)w.yh, s, 2 * ns);
   hipLaunchKernelGGL(k_copy_f, dim3(nblk(2 * ns)), dim3(kEW), 0, st, (float*)w.Th, s + 2 * ns, 2 * ns);
   hipLaunchKernelGGL(k_copy_f, dim3(nblk(2 * ns)), dim3(kEW), 0, st, (float*)w.lam, s + 4 * ns, 2 * ns);
-  for (int i = 1; i < len; ++i) {
+  for (int i = 1; i < nstates; ++i) {
     float* zi = seg + int64_t(i) * 2 * nz;
     hipLaunchKernelGGL(k_copy_f, dim3(nblk(nz)), dim3(kEW), 0, st, zi, zi - 2 * nz, nz);
     hipError_t e = iterate_maps(pl, w, zi, zi + nz, beta, st, nullptr);
     if (e != hipSuccess) return e;
-    if (i < len - 1)
+    if (i < nstates - 1)
       LAUNCH_J(k_spec, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.part, w.G, w.xh, w.yh, w.Th, w.lam, w.rho, w.rdual,
                w.ngp, T, H, W, 1, nullptr);
   }

@@ -9,7 +9,10 @@
 // reverse through the literal updates of eq:Inference_solution with theta
 // kept (w = theta + z/rho, s = D w - x/rho, lam = P s with
 // P = (D D^T + I/rho)^-1, v = D^T lam, u = v - z/rho, theta' = clip(u, +-beta),
-// z' = z + rho (theta' - v)), whose intermediates it recomputes at each state:
+// z' = z + rho (theta' - v)).  At each state it recomputes the spectra of w
+// and lam; the branch of the clip at each code is read from the codes after
+// the iteration (exactly zero where u passed through, of the sign opposite
+// to u elsewhere), so v itself is never formed:
 //   t = thbar' + rho zbar';  ubar = t [|u| < beta];  betabar += t sign(u) [|u| > beta]
 //   vbar = ubar - rho zbar';  zbar = zbar' - ubar/rho
 //   sbar = P D vbar;  wbar = D^T sbar;  thetabar = wbar;  zbar += wbar/rho
@@ -90,35 +93,35 @@ __global__ void d_reduce_solve(const float2* __restrict__ buf, const float2* __r
   out[int64_t(n) * D + f] = make_float2(s.x / den, s.y / den);
 }
 
-// Adjoint of the clip and z updates.  In: V (forward D^T lam, unscaled),
-// z_i, zbar', thbar'.  Out: V <- vbar pair (spatial), zbar <- zbar' - ubar/rho,
-// bpart[(n P + p) nblk + blk] += sum t sign(u) [|u| > beta].
-__global__ __launch_bounds__(kDW) void d_adj_clip(float2* __restrict__ Vb, const float* __restrict__ z,
+// Adjoint of the clip and z updates.  The clip's branch at each code is the
+// forward's own: its step z' = soft(z - rho v, rho beta) is exactly 0 where
+// the clip passed u = v - z/rho through, and elsewhere sign(u) = -sign(z'),
+// so the state after the iteration (znext) decides both.  In: znext,
+// zbar', thbar'.  Out: Vb <- vbar pair (spatial), zbar <- zbar' - ubar/rho,
+// bpart[(n P + p) nblk + blk] += sum t sign(u) over the clipped codes.
+__global__ __launch_bounds__(kDW) void d_adj_clip(float2* __restrict__ Vb, const float* __restrict__ znext,
                                                   float* __restrict__ zbar, const float* __restrict__ thbar,
-                                                  const float* __restrict__ rho, float beta,
-                                                  double* __restrict__ bpart, int K, int P, int64_t D) {
+                                                  const float* __restrict__ rho, double* __restrict__ bpart, int K,
+                                                  int P, int64_t D) {
   __shared__ double red[kDW / 64];
   const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int p = blockIdx.y, n = blockIdx.z;
   double bs = 0.0;
   if (f < D) {
-    const float r = rho[n], ir = 1.0f / r, invD = 1.0f / (float)D;
-    float2* vp = Vb + (int64_t(n) * P + p) * D + f;
-    const float2 c = *vp;
+    const float r = rho[n], ir = 1.0f / r;
     const int64_t a = (int64_t(n) * K + 2 * p) * D + f;
     float vbar[2] = {0.f, 0.f};
     for (int s = 0; s < 2 && 2 * p + s < K; ++s) {
-      const float v = (s ? c.y : c.x) * invD;
-      const float u = v - z[a + s * D] * ir;
+      const float zn = znext[a + s * D];
       const float zb = zbar[a + s * D];
       const float t = thbar[a + s * D] + r * zb;
-      const float au = fabsf(u);
-      const float ub = au < beta ? t : 0.f;
-      if (au > beta) bs += (double)(u > 0.f ? t : -t);
+      const bool pass = zn == 0.f;
+      const float ub = pass ? t : 0.f;
+      if (!pass) bs += (double)(zn < 0.f ? t : -t);
       vbar[s] = ub - r * zb;
       zbar[a + s * D] = zb - ub * ir;
     }
-    *vp = make_float2(vbar[0], vbar[1]);
+    Vb[(int64_t(n) * P + p) * D + f] = make_float2(vbar[0], vbar[1]);
   }
   const double tot = block_sum(bs, red);
   if (threadIdx.x == 0) bpart[(int64_t(n) * P + p) * gridDim.x + blockIdx.x] += tot;
@@ -266,7 +269,7 @@ static size_t carve_diff(const Plan& pl, int every, void* base, DiffWs* w) {
   w->Dbar = c.take<float2>(P * D);
   w->zbar = c.take<float>(N * K * D);
   w->thbar = c.take<float>(N * K * D);
-  w->seg = c.take<float>(int64_t(every > 0 ? every : 1) * 2 * N * K * D);
+  w->seg = c.take<float>(int64_t(every > 0 ? every + 1 : 2) * 2 * N * K * D);
   w->nbpart = N * P * int64_t(dblk(D));
   w->bpart = c.take<double>(w->nbpart + 1);
   return c.off;
@@ -277,10 +280,10 @@ size_t run_diff_ws(const Plan& pl, int every) {
   return carve_diff(pl, every, nullptr, &w);
 }
 
-// Intermediates of one literal iteration at the state (z, th): the spectra
-// of w in Wb, lam, and D * (D^T lam) pairs in Vb.
+// Spectra the adjoint needs from one literal iteration at the state (z, th):
+// those of the pairs of w = th + z/rho in Wb, and lam.
 static hipError_t lit_intermediates(const Plan& pl, DiffWs& w, const float* z, const float* th, const float* rho,
-                              hipStream_t st) {
+                                    hipStream_t st) {
   const int64_t D = pl.dsz;
   const dim3 g3(dblk(D), pl.p, pl.n);
   hipLaunchKernelGGL(d_pack_w, g3, dim3(kDW), 0, st, z, th, w.Wb, rho, pl.k, pl.p, D);
@@ -288,21 +291,19 @@ static hipError_t lit_intermediates(const Plan& pl, DiffWs& w, const float* z, c
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(d_reduce_solve, dim3(dblk(D), pl.n), dim3(kDW), 0, st, w.Wb, w.cw.E, w.cw.G, w.cw.xh, rho,
                      w.lam, pl.p, pl.g[0], pl.g[1], pl.g[2]);
-  launch_make_v(pl, w.cw.E, w.lam, w.Vb, st);
-  e = fft_grids(w.Vb, int64_t(pl.n) * pl.p, pl.g, +1, st);
-  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 
-// Adjoint of one iteration whose input state is (z, th); (zbar, thbar) hold
-// the adjoint of its output and are replaced by the adjoint of its input.
-static hipError_t adjoint_iter(const Plan& pl, DiffWs& w, const float* z, const float* th, const float* rho,
-                               float beta, hipStream_t st) {
+// Adjoint of one iteration whose input state is (z, th) and whose output
+// codes are znext; (zbar, thbar) hold the adjoint of its output and are
+// replaced by the adjoint of its input.
+static hipError_t adjoint_iter(const Plan& pl, DiffWs& w, const float* z, const float* th, const float* znext,
+                               const float* rho, hipStream_t st) {
   const int64_t D = pl.dsz;
   const dim3 g3(dblk(D), pl.p, pl.n);
   hipError_t e = lit_intermediates(pl, w, z, th, rho, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(d_adj_clip, g3, dim3(kDW), 0, st, w.Vb, z, w.zbar, w.thbar, rho, beta, w.bpart, pl.k, pl.p, D);
+  hipLaunchKernelGGL(d_adj_clip, g3, dim3(kDW), 0, st, w.Vb, znext, w.zbar, w.thbar, rho, w.bpart, pl.k, pl.p, D);
   if ((e = fft_grids(w.Vb, int64_t(pl.n) * pl.p, pl.g, -1, st)) != hipSuccess) return e;
   hipLaunchKernelGGL(d_reduce_solve, dim3(dblk(D), pl.n), dim3(kDW), 0, st, w.Vb, w.cw.E, w.cw.G,
                      (const float2*)nullptr, rho, w.sbar, pl.p, pl.g[0], pl.g[1], pl.g[2]);
@@ -349,10 +350,15 @@ int run_backward(const Plan& pl, const float* b, const float* d, float beta, con
   for (int sgi = nseg - 1; sgi >= 0; --sgi) {
     const int c0 = sgi * every, len = (iters - c0 < every) ? iters - c0 : every;
     const float* ck = ckpt + int64_t(sgi) * code_record_floats(pl);
-    if (replay_code(pl, w.cw, rho, beta, ck, len, w.seg, st) != hipSuccess) return CSC_EHIP;
+    // states c0 .. c0 + len - 1, and for the last segment also the final one
+    // (the codes after each state's iteration decide its clip branches)
+    const bool last_seg = sgi == nseg - 1;
+    if (replay_code(pl, w.cw, rho, beta, ck, len + (last_seg ? 1 : 0), w.seg, st) != hipSuccess) return CSC_EHIP;
     for (int i = len - 1; i >= 0; --i) {
       const float* zi = w.seg + int64_t(i) * 2 * nz;
-      if (adjoint_iter(pl, w, zi, zi + nz, rho, beta, st) != hipSuccess) return CSC_EHIP;
+      const float* znext =
+          (i + 1 < len || last_seg) ? zi + 2 * nz : ckpt + int64_t(sgi + 1) * code_record_floats(pl);
+      if (adjoint_iter(pl, w, zi, zi + nz, znext, rho, st) != hipSuccess) return CSC_EHIP;
     }
   }
   if (finish_taps(pl, w, dd, false, st) != hipSuccess) return CSC_EHIP;

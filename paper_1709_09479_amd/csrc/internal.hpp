@@ -97,10 +97,10 @@ int run_code(const Plan& pl, const float* b, const float* d, float beta, float* 
              int* iters_done = nullptr, float* ckpt = nullptr, int every = 0);
 int64_t code_record_floats(const Plan& pl);
 // Resumes run_code's fixed-step loop from a record: seg[i] ([2][N][K][grid],
-// z then theta) receives the state after i more iterations, i < len, equal
-// bit for bit to the states the uninterrupted loop passes through.  E, G and
-// xh of `w` must hold the spectra of the same images and filters.
-hipError_t replay_code(const Plan& pl, CodeWs& w, const float* rho, float beta, const float* rec, int len, float* seg,
+// z then theta) receives the state after i more iterations, i < nstates,
+// equal bit for bit to the states the uninterrupted loop passes through.  E,
+// G and xh of `w` must hold the spectra of the same images and filters.
+hipError_t replay_code(const Plan& pl, CodeWs& w, const float* rho, float beta, const float* rec, int nstates, float* seg,
                        hipStream_t st);
 // part <- per-group spectral contributions sum_p DFT(maps pair) conj(E_p);
 // l1 <- partial sums of |maps| ([N][npri]).
