@@ -152,7 +152,8 @@ std::vector<int> g_ev_cls;
 int g_ev_used = 0;
 }  // namespace
 
-TraceScope::TraceScope(int cls, hipStream_t st) : cls_(cls), st_(st), slot_(-1) {
+TraceScope::TraceScope(int cls, hipStream_t st, bool own_launch)
+    : cls_(cls), st_(st), slot_(-1), own_(own_launch) {
   std::lock_guard<std::mutex> lk(g_trace_mu);
   if (!g_trace_on || g_ev_used >= kTraceSlots) return;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -160,11 +161,19 @@ TraceScope::TraceScope(int cls, hipStream_t st) : cls_(cls), st_(st), slot_(-1) 
   if (g_cls_seen[cls]++ % g_trace_every != 0) return;
   slot_ = g_ev_used++;
   g_ev_cls[slot_] = cls;
-  hipEventRecord(g_ev_start[slot_], st_);
+  if (!own_) hipEventRecord(g_ev_start[slot_], st_);
 }
 
 TraceScope::~TraceScope() {
-  if (slot_ >= 0) hipEventRecord(g_ev_stop[slot_], st_);
+  if (slot_ >= 0 && !own_) hipEventRecord(g_ev_stop[slot_], st_);
+}
+
+bool TraceScope::events(hipEvent_t* start, hipEvent_t* stop) const {
+  if (slot_ < 0 || !own_) return false;
+  std::lock_guard<std::mutex> lk(g_trace_mu);
+  *start = g_ev_start[slot_];
+  *stop = g_ev_stop[slot_];
+  return true;
 }
 
 }  // namespace dcsc

@@ -754,13 +754,18 @@ static unsigned nblk(int64_t n, int b = kEW) { return (unsigned)((n + b - 1) / b
 template <int J, int MODE>
 static bool fused_launch(const Plan& pl, const float2* E, const float2* lam, float* z, float* theta,
                          const float* rho, float beta, float2* part, double* rpart, hipStream_t st,
-                         const int* stop) {
+                         const int* stop, hipEvent_t e0, hipEvent_t e1) {
   const dim3 grid(pl.ng * pl.n);
   const int h = pl.g[1], w = pl.g[2];
 #define FL(HH, WW)                                                                                         \
   if (h == HH && w == WW) {                                                                                \
-    hipLaunchKernelGGL((k_fused<HH, WW, J, MODE>), grid, dim3(fused_threads(HH * WW, J)), 0, st, E, lam, z, \
-                       theta, pl.zoff, rho, beta, part, rpart, pl.k, pl.p, pl.ppg, pl.ng, stop);         \
+    if (e0)                                                                                                \
+      hipExtLaunchKernelGGL((k_fused<HH, WW, J, MODE>), grid, dim3(fused_threads(HH * WW, J)), 0, st, e0, \
+                            e1, 0, E, lam, z, theta, pl.zoff, rho, beta, part, rpart, pl.k, pl.p, pl.ppg,   \
+                            pl.ng, stop);                                                                  \
+    else                                                                                                   \
+      hipLaunchKernelGGL((k_fused<HH, WW, J, MODE>), grid, dim3(fused_threads(HH * WW, J)), 0, st, E, lam,  \
+                         z, theta, pl.zoff, rho, beta, part, rpart, pl.k, pl.p, pl.ppg, pl.ng, stop);      \
     return true;                                                                                           \
   }
   FL(16, 16) FL(16, 32) FL(16, 64) FL(16, 128) FL(16, 256)
@@ -772,13 +777,14 @@ static bool fused_launch(const Plan& pl, const float2* E, const float2* lam, flo
   return false;
 }
 
+// e0, e1: events to launch with (an own-launch TraceScope's), or null
 template <int MODE>
 static bool fused_dispatch(const Plan& pl, const float2* E, const float2* lam, float* z, float* theta,
                            const float* rho, float beta, float2* part, double* rpart, hipStream_t st,
-                           const int* stop = nullptr) {
-  if (pl.j == 1) return fused_launch<1, MODE>(pl, E, lam, z, theta, rho, beta, part, rpart, st, stop);
-  if (pl.j == 2) return fused_launch<2, MODE>(pl, E, lam, z, theta, rho, beta, part, rpart, st, stop);
-  return fused_launch<3, MODE>(pl, E, lam, z, theta, rho, beta, part, rpart, st, stop);
+                           const int* stop = nullptr, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+  if (pl.j == 1) return fused_launch<1, MODE>(pl, E, lam, z, theta, rho, beta, part, rpart, st, stop, e0, e1);
+  if (pl.j == 2) return fused_launch<2, MODE>(pl, E, lam, z, theta, rho, beta, part, rpart, st, stop, e0, e1);
+  return fused_launch<3, MODE>(pl, E, lam, z, theta, rho, beta, part, rpart, st, stop, e0, e1);
 }
 
 size_t carve_code(const Plan& pl, void* base, CodeWs* w) {
@@ -849,9 +855,13 @@ hipError_t forward_maps(const Plan& pl, const float* maps, CodeWs& w, double* l1
 static hipError_t iterate_maps(const Plan& pl, CodeWs& w, float* z, float* theta, float beta, hipStream_t st,
                                const int* stop) {
   const int64_t D = pl.dsz;
-  TraceScope trace(kTraceCodeMaps, st);
+  // one kernel on the single-tile path (timed at its own start and end),
+  // several otherwise (timed around them)
+  TraceScope trace(kTraceCodeMaps, st, pl.lds);
   if (pl.lds) {
-    if (!fused_dispatch<kModeIter>(pl, w.E, w.lam, z, theta, w.rho, beta, w.part, w.rpri, st, stop))
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    trace.events(&e0, &e1);
+    if (!fused_dispatch<kModeIter>(pl, w.E, w.lam, z, theta, w.rho, beta, w.part, w.rpri, st, stop, e0, e1))
       return hipErrorInvalidValue;
     return hipGetLastError();
   }
@@ -931,8 +941,8 @@ int run_code(const Plan& pl, const float* b, const float* d, float beta, float* 
     if (rec) hipLaunchKernelGGL(k_copy_f, dim3(nblk(nz)), dim3(kEW), 0, st, rec, z, nz);
     const int solve_next = (!last && !adaptive) ? 1 : 0;
     {
-      TraceScope trace(kTraceCodeSpec, st);
-      LAUNCH_J(k_spec, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.part, w.G, w.xh, w.yh, w.Th, w.lam, w.rho,
+      TraceScope trace(kTraceCodeSpec, st, true);
+      LAUNCH_J_TRACED(trace, k_spec, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.part, w.G, w.xh, w.yh, w.Th, w.lam, w.rho,
                w.rdual, w.ngp, T, H, W, solve_next, stop);
     }
     if (rec) save_spec(rec);

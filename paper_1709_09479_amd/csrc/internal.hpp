@@ -1,6 +1,7 @@
 // Host-side plan and launch helpers shared by the library's translation units.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -117,16 +118,40 @@ void launch_objective_tail(const Plan& pl, CodeWs& w, float beta, double* out, h
 // calls replay the executable graph.  Returns a CSC_* code.
 int graph_call(const std::vector<int64_t>& key, hipStream_t st, int (*enqueue)(void*), void* ctx);
 
-// Launch tracing.  While enabled (csc_trace_enable), a TraceScope brackets
-// the launches made in its lifetime with a pair of HIP events recorded on
-// the launching stream; csc_trace_read sums the elapsed times per class.
+// Launch tracing.  While enabled (csc_trace_enable), a sampled TraceScope
+// times the launches made in its lifetime with a pair of HIP events on the
+// launching stream; csc_trace_read sums the elapsed times per class.  A
+// scope that covers several kernels records the events around them.  A
+// scope made with own_launch covers exactly one kernel, which the caller
+// launches with hipExtLaunchKernelGGL and the scope's events (events()):
+// the runtime then stamps them at that kernel's own start and end, so the
+// time excludes the dispatch around it.
 enum TraceClass { kTraceCodeMaps = 0, kTraceCodeSpec = 1, kTraceLearnA = 2, kTraceLearnB = 3, kTraceClasses = 4 };
 struct TraceScope {
-  TraceScope(int cls, hipStream_t st);
+  TraceScope(int cls, hipStream_t st, bool own_launch = false);
   ~TraceScope();
+  // own-launch scopes: the events to launch the kernel with; false when the
+  // scope is not sampled (launch it normally)
+  bool events(hipEvent_t* start, hipEvent_t* stop) const;
   int cls_;
   hipStream_t st_;
   int slot_;
+  bool own_;
 };
+
+// Launch KERNEL<J> (J = 1, 2, 3) under an own-launch TraceScope `tr`.
+#define LAUNCH_J_TRACED(tr, KERNEL, J, grid, block, st, ...)                                          \
+  do {                                                                                                \
+    hipEvent_t e0_, e1_;                                                                              \
+    if ((tr).events(&e0_, &e1_)) {                                                                    \
+      if ((J) == 1) hipExtLaunchKernelGGL(KERNEL<1>, grid, block, 0, st, e0_, e1_, 0, __VA_ARGS__);      \
+      else if ((J) == 2) hipExtLaunchKernelGGL(KERNEL<2>, grid, block, 0, st, e0_, e1_, 0, __VA_ARGS__); \
+      else hipExtLaunchKernelGGL(KERNEL<3>, grid, block, 0, st, e0_, e1_, 0, __VA_ARGS__);             \
+    } else {                                                                                          \
+      if ((J) == 1) hipLaunchKernelGGL(KERNEL<1>, grid, block, 0, st, __VA_ARGS__);                      \
+      else if ((J) == 2) hipLaunchKernelGGL(KERNEL<2>, grid, block, 0, st, __VA_ARGS__);                 \
+      else hipLaunchKernelGGL(KERNEL<3>, grid, block, 0, st, __VA_ARGS__);                               \
+    }                                                                                                 \
+  } while (0)
 
 }  // namespace dcsc

@@ -830,8 +830,8 @@ static hipError_t pruned_zt_proj(const Plan& pl, LearnWs& w, const float2* v, co
                                  const int* cgf) {
   const int H = pl.g[1], W = pl.g[2], R = 256 / W, M1 = pl.fs[1], M2 = pl.fs[2], G = passa_groups(pl);
   {
-    TraceScope trace(kTraceLearnA, st);
-    LJ(l_passA_rows, pl.j, dim3(G, pl.p), dim3(256), st, w.Zh, v, w.Upart, pl.n, pl.p, H, W, M1, M2,
+    TraceScope trace(kTraceLearnA, st, true);
+    LAUNCH_J_TRACED(trace, l_passA_rows, pl.j, dim3(G, pl.p), dim3(256), st, w.Zh, v, w.Upart, pl.n, pl.p, H, W, M1, M2,
        lanes_for(2 * R * M2, W), cgf);
   }
   hipLaunchKernelGGL(l_prune_uc, dim3(W / kUcCols, pl.p, pl.j), dim3(256), 0, st, w.Upart, w.Uc, mu, pl.k, pl.p, H,
@@ -843,8 +843,8 @@ static hipError_t pruned_zt_proj(const Plan& pl, LearnWs& w, const float2* v, co
 static hipError_t pruned_drecover(const Plan& pl, LearnWs& w, const float* mu, float* d, hipStream_t st) {
   const int H = pl.g[1], W = pl.g[2], R = 256 / W, M1 = pl.fs[1], M2 = pl.fs[2], G = passa_groups(pl);
   {
-    TraceScope trace(kTraceLearnA, st);
-    LJ(l_passA_rows, pl.j, dim3(G, pl.p), dim3(256), st, w.Zh, w.gh, w.Upart, pl.n, pl.p, H, W, M1, M2,
+    TraceScope trace(kTraceLearnA, st, true);
+    LAUNCH_J_TRACED(trace, l_passA_rows, pl.j, dim3(G, pl.p), dim3(256), st, w.Zh, w.gh, w.Upart, pl.n, pl.p, H, W, M1, M2,
        lanes_for(2 * R * M2, W), nullptr);
   }
   hipLaunchKernelGGL(l_drec_u, dim3(pl.p, pl.j), dim3(256), 0, st, w.Upart, mu, d, pl.k, pl.j, pl.p, H, W, M1, M2,
@@ -857,8 +857,8 @@ static hipError_t pruned_drecover(const Plan& pl, LearnWs& w, const float* mu, f
 static void pruned_passB(const Plan& pl, LearnWs& w, const float2* v, float2* q, const float2* xh, double* part,
                          double* vpart, hipStream_t st, const int* cgf) {
   const int chunks = passb_chunks(pl), nbc = (pl.n + chunks - 1) / chunks;
-  TraceScope trace(kTraceLearnB, st);
-  LJ(l_passB_c, pl.j, dim3(canon_blocks(pl), chunks), dim3(64 * kBW), st, w.Zh, w.Uc, v, q, xh, part, vpart, pl.n,
+  TraceScope trace(kTraceLearnB, st, true);
+  LAUNCH_J_TRACED(trace, l_passB_c, pl.j, dim3(canon_blocks(pl), chunks), dim3(64 * kBW), st, w.Zh, w.Uc, v, q, xh, part, vpart, pl.n,
      pl.p, pl.g[1], pl.g[2], nbc, cgf);
 }
 
@@ -870,8 +870,8 @@ static hipError_t apply_zt_proj(const Plan& pl, LearnWs& w, const float2* v, con
   const int64_t D = pl.dsz;
   const int T = pl.g[0], H = pl.g[1], W = pl.g[2];
   {
-    TraceScope trace(kTraceLearnA, st);
-    LJ(l_passA, pl.j, dim3(lblk(D), pl.p), dim3(kLW), st, w.Zh, v, w.Tp, pl.n, pl.p, T, H, W, cgf);
+    TraceScope trace(kTraceLearnA, st, true);
+    LAUNCH_J_TRACED(trace, l_passA, pl.j, dim3(lblk(D), pl.p), dim3(kLW), st, w.Zh, v, w.Tp, pl.n, pl.p, T, H, W, cgf);
   }
   if (crop_tile_launch(pl, w.Tp, mu, st, cgf)) return hipGetLastError();
   hipError_t e = fft_grids(w.Tp, int64_t(pl.j) * pl.p, pl.g, +1, st);
@@ -886,8 +886,8 @@ static hipError_t apply_zt_proj(const Plan& pl, LearnWs& w, const float2* v, con
 static void apply_passB(const Plan& pl, LearnWs& w, const float2* v, float2* q, const float2* xh, double* dots,
                         double* vdots, hipStream_t st, const int* cgf) {
   const int T = pl.g[0], H = pl.g[1], W = pl.g[2];
-  TraceScope trace(kTraceLearnB, st);
-  LJ(l_passB, pl.j, dim3(lblk(pl.dsz), pl.n), dim3(kLW), st, w.Zh, w.Tp, v, q, xh, dots, vdots, pl.n, pl.p, T, H,
+  TraceScope trace(kTraceLearnB, st, true);
+  LAUNCH_J_TRACED(trace, l_passB, pl.j, dim3(lblk(pl.dsz), pl.n), dim3(kLW), st, w.Zh, w.Tp, v, q, xh, dots, vdots, pl.n, pl.p, T, H,
      W, cgf);
 }
 
