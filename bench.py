@@ -33,7 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-TRACE_EVERY = 8                # timed steps bracket every 8th launch of a traced kernel
+TRACE_EVERY = 32  # timed steps time every 32nd launch of a traced kernel (from the first)
 FP32_VECTOR_TFLOPS = 157.3     # MI355X fp32 vector (packed); 78.6 unpacked
 
 
