@@ -169,10 +169,6 @@ __global__ void k_copy_f(float* __restrict__ dst, const float* __restrict__ src,
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < count) dst[i] = src[i];
 }
-__global__ void k_fill_f(float* __restrict__ dst, int64_t count, float v) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < count) dst[i] = v;
-}
 
 // dst[n][j](f) = (Y(f) + conj(Y(-f)))/2 with Y = sum_g part[n][g][j].  The
 // thread of the lower index of each pair (f, -f) writes both values (the
