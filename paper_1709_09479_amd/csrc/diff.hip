@@ -249,6 +249,197 @@ __global__ __launch_bounds__(kSumT) void d_sum(const double* __restrict__ part, 
 
 // ----------------------------------------------------------------- host
 
+// ------------------------------------------------------ fused axis passes
+// The 2-D grids beyond one LDS tile (and 3-D volumes) are transformed one
+// axis at a time, each pass reading and writing every element.  These passes
+// fold the elementwise step that precedes or follows a transform of the
+// adjoint into the pass that moves the data anyway: LD(i) produces element i
+// of the first pass's input and ST(i, v) takes element i of the last pass's
+// output (i: linear index into [N P][T][H][W]).  Each operator repeats the
+// arithmetic of its stand-alone kernel exactly.
+constexpr int kOpTile = 4096, kOpThreads = 256;
+
+struct LdPlain {
+  const float2* d;
+  __device__ float2 operator()(int64_t i) { return d[i]; }
+  __device__ void flush(double*) {}
+};
+struct StPlain {
+  float2* d;
+  __device__ void operator()(int64_t i, float2 v) { d[i] = v; }
+  __device__ void flush(double*) {}
+};
+
+// index i -> image n, pair p, grid position f (D a power of two)
+__device__ __forceinline__ void op_index(int64_t i, int lgD, int P, int& n, int& p, int64_t& f) {
+  const int64_t g = i >> lgD;
+  f = i & ((int64_t(1) << lgD) - 1);
+  n = (int)(g / P);
+  p = (int)(g - int64_t(n) * P);
+}
+
+// d_pack_w: the pairs of w = theta + z/rho
+struct LdPackW {
+  const float *z, *th, *rho;
+  int K, P, lgD;
+  __device__ float2 operator()(int64_t i) {
+    int n, p;
+    int64_t f;
+    op_index(i, lgD, P, n, p, f);
+    const int64_t D = int64_t(1) << lgD;
+    const float ir = 1.0f / rho[n];
+    const int64_t a = (int64_t(n) * K + 2 * p) * D + f;
+    float2 v = make_float2(th[a] + z[a] * ir, 0.f);
+    if (2 * p + 1 < K) v.y = th[a + D] + z[a + D] * ir;
+    return v;
+  }
+  __device__ void flush(double*) {}
+};
+
+// d_adj_clip: vbar pairs, zbar update, and the beta partial of the block
+struct LdAdjClip {
+  const float* znext;
+  float* zbar;
+  const float *thbar, *rho;
+  double* bpart;
+  int K, P, lgD;
+  double bs;
+  __device__ float2 operator()(int64_t i) {
+    int n, p;
+    int64_t f;
+    op_index(i, lgD, P, n, p, f);
+    const int64_t D = int64_t(1) << lgD;
+    const float r = rho[n], ir = 1.0f / r;
+    const int64_t a = (int64_t(n) * K + 2 * p) * D + f;
+    float vbar[2] = {0.f, 0.f};
+    for (int s = 0; s < 2 && 2 * p + s < K; ++s) {
+      const float zn = znext[a + s * D];
+      const float zb = zbar[a + s * D];
+      const float t = thbar[a + s * D] + r * zb;
+      const bool pass = zn == 0.f;
+      const float ub = pass ? t : 0.f;
+      if (!pass) bs += (double)(zn < 0.f ? t : -t);
+      vbar[s] = ub - r * zb;
+      zbar[a + s * D] = zb - ub * ir;
+    }
+    return make_float2(vbar[0], vbar[1]);
+  }
+  __device__ void flush(double* red) {
+    const double tot = block_sum(bs, red);
+    if (threadIdx.x == 0) bpart[blockIdx.x] += tot;
+  }
+};
+
+// k_make_v (J = 1): lam E_p
+struct LdMakeV {
+  const float2 *E, *lam;
+  int P, lgD;
+  __device__ float2 operator()(int64_t i) {
+    int n, p;
+    int64_t f;
+    op_index(i, lgD, P, n, p, f);
+    const int64_t D = int64_t(1) << lgD;
+    return cmul(lam[int64_t(n) * D + f], E[int64_t(p) * D + f]);
+  }
+  __device__ void flush(double*) {}
+};
+
+// d_adj_finish: thetabar = wbar, zbar += wbar / rho
+struct StAdjFinish {
+  float *zbar, *thbar;
+  const float* rho;
+  int K, P, lgD;
+  __device__ void operator()(int64_t i, float2 c) {
+    int n, p;
+    int64_t f;
+    op_index(i, lgD, P, n, p, f);
+    const int64_t D = int64_t(1) << lgD;
+    const float ir = 1.0f / rho[n], invD = 1.0f / (float)D;
+    const int64_t a = (int64_t(n) * K + 2 * p) * D + f;
+    for (int s = 0; s < 2 && 2 * p + s < K; ++s) {
+      const float wb = (s ? c.y : c.x) * invD;
+      thbar[a + s * D] = wb;
+      zbar[a + s * D] += wb * ir;
+    }
+  }
+  __device__ void flush(double*) {}
+};
+
+// One axis pass over [outer][L][inner] (as the plain axis pass of fftops.hip).
+template <int L, int DIR, class LD, class ST>
+__global__ __launch_bounds__(kOpThreads) void d_fft_axis_op(LD ld, ST sto, int64_t outer, int64_t inner, int lbi,
+                                                            int lbo) {
+  constexpr int T = kOpTile, NT = kOpThreads, LP = L + 1;
+  __shared__ float2 tile[(T / L) * LP];
+  __shared__ float2 tw[256];
+  __shared__ double red[NT / 64];
+  load_twiddles(tw);
+  const int bi = 1 << lbi;
+  const int64_t tiles_in = inner >> lbi;
+  const int64_t t = blockIdx.x;
+  const int64_t o0 = (t / tiles_in) << lbo;
+  const int64_t i0 = (t % tiles_in) << lbi;
+  for (int e = threadIdx.x; e < T; e += NT) {
+    const int b_in = e & (bi - 1);
+    const int jj = (e >> lbi) & (L - 1);
+    const int b_o = e >> lbi >> __builtin_ctz(L);
+    float2 v = make_float2(0.f, 0.f);
+    if (o0 + b_o < outer) v = ld(((o0 + b_o) * L + jj) * inner + i0 + b_in);
+    tile[((b_o << lbi) + b_in) * LP + jj] = v;
+  }
+  __syncthreads();
+  fft_lines<L, T, NT, DIR, 1, LP>(tile, tw);
+  for (int e = threadIdx.x; e < T; e += NT) {
+    const int b_in = e & (bi - 1);
+    const int jj = (e >> lbi) & (L - 1);
+    const int b_o = e >> lbi >> __builtin_ctz(L);
+    if (o0 + b_o < outer) sto(((o0 + b_o) * L + jj) * inner + i0 + b_in, tile[((b_o << lbi) + b_in) * LP + jj]);
+  }
+  ld.flush(red);
+  sto.flush(red);
+}
+
+static int dlog2(int64_t v) {
+  int l = 0;
+  while ((int64_t(1) << l) < v) ++l;
+  return l;
+}
+
+template <int DIR, class LD, class ST>
+static hipError_t axis_op(LD ld, ST sto, int64_t outer, int L, int64_t inner, hipStream_t st) {
+  const int ll = dlog2(L), lt = dlog2(kOpTile);
+  int lbi = dlog2(inner);
+  if (lbi > lt - ll) lbi = lt - ll;
+  const int lbo = lt - ll - lbi;
+  const int64_t tiles = ((outer + (int64_t(1) << lbo) - 1) >> lbo) * (inner >> lbi);
+  const dim3 grid((unsigned)tiles), block(kOpThreads);
+  switch (L) {
+#define CASE(LL) \
+  case LL: hipLaunchKernelGGL((d_fft_axis_op<LL, DIR, LD, ST>), grid, block, 0, st, ld, sto, outer, inner, lbi, lbo); break;
+    CASE(2) CASE(4) CASE(8) CASE(16) CASE(32) CASE(64) CASE(128) CASE(256)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Transform of `count` grids in place (as fft_grids on the axis path) with
+// LD feeding the first pass and ST taking the last pass's output.
+template <int DIR, class LD, class ST>
+static hipError_t fft_fused(float2* data, int64_t count, const int g[3], LD ld, ST sto, hipStream_t st) {
+  const int T = g[0], H = g[1], W = g[2];
+  hipError_t e = axis_op<DIR>(ld, StPlain{data}, count * T * H, W, 1, st);
+  if (e != hipSuccess) return e;
+  if (T > 1) {
+    if ((e = axis_op<DIR>(LdPlain{data}, StPlain{data}, count * T, H, W, st)) != hipSuccess) return e;
+    return axis_op<DIR>(LdPlain{data}, sto, count, T, int64_t(H) * W, st);
+  }
+  return axis_op<DIR>(LdPlain{data}, sto, count, H, W, st);
+}
+
+// grids that fft_grids transforms axis by axis
+static bool axis_path(const Plan& pl) { return !(pl.g[0] == 1 && tile_supported(pl.g[1], pl.g[2])); }
+
 struct DiffWs {
   CodeWs cw;
   float2 *Wb, *Vb, *lam, *sbar, *Dbar;
@@ -286,8 +477,13 @@ static hipError_t lit_intermediates(const Plan& pl, DiffWs& w, const float* z, c
                                     hipStream_t st) {
   const int64_t D = pl.dsz;
   const dim3 g3(dblk(D), pl.p, pl.n);
-  hipLaunchKernelGGL(d_pack_w, g3, dim3(kDW), 0, st, z, th, w.Wb, rho, pl.k, pl.p, D);
-  hipError_t e = fft_grids(w.Wb, int64_t(pl.n) * pl.p, pl.g, -1, st);
+  hipError_t e;
+  if (axis_path(pl)) {
+    e = fft_fused<-1>(w.Wb, int64_t(pl.n) * pl.p, pl.g, LdPackW{z, th, rho, pl.k, pl.p, dlog2(D)}, StPlain{w.Wb}, st);
+  } else {
+    hipLaunchKernelGGL(d_pack_w, g3, dim3(kDW), 0, st, z, th, w.Wb, rho, pl.k, pl.p, D);
+    e = fft_grids(w.Wb, int64_t(pl.n) * pl.p, pl.g, -1, st);
+  }
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(d_reduce_solve, dim3(dblk(D), pl.n), dim3(kDW), 0, st, w.Wb, w.cw.E, w.cw.G, w.cw.xh, rho,
                      w.lam, pl.p, pl.g[0], pl.g[1], pl.g[2]);
@@ -303,14 +499,26 @@ static hipError_t adjoint_iter(const Plan& pl, DiffWs& w, const float* z, const 
   const dim3 g3(dblk(D), pl.p, pl.n);
   hipError_t e = lit_intermediates(pl, w, z, th, rho, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(d_adj_clip, g3, dim3(kDW), 0, st, w.Vb, znext, w.zbar, w.thbar, rho, w.bpart, pl.k, pl.p, D);
-  if ((e = fft_grids(w.Vb, int64_t(pl.n) * pl.p, pl.g, -1, st)) != hipSuccess) return e;
+  const bool fused = axis_path(pl);
+  const int lgD = dlog2(D);
+  const int64_t np = int64_t(pl.n) * pl.p;
+  if (fused) {
+    e = fft_fused<-1>(w.Vb, np, pl.g, LdAdjClip{znext, w.zbar, w.thbar, rho, w.bpart, pl.k, pl.p, lgD, 0.0},
+                      StPlain{w.Vb}, st);
+  } else {
+    hipLaunchKernelGGL(d_adj_clip, g3, dim3(kDW), 0, st, w.Vb, znext, w.zbar, w.thbar, rho, w.bpart, pl.k, pl.p, D);
+    e = fft_grids(w.Vb, np, pl.g, -1, st);
+  }
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(d_reduce_solve, dim3(dblk(D), pl.n), dim3(kDW), 0, st, w.Vb, w.cw.E, w.cw.G,
                      (const float2*)nullptr, rho, w.sbar, pl.p, pl.g[0], pl.g[1], pl.g[2]);
   hipLaunchKernelGGL(d_dbar, dim3(dblk(D), pl.p), dim3(kDW), 0, st, w.Vb, w.Wb, w.cw.E, w.lam, w.sbar, w.Dbar,
                      pl.n, pl.p, pl.g[0], pl.g[1], pl.g[2]);
+  if (fused)
+    return fft_fused<+1>(w.Wb, np, pl.g, LdMakeV{w.cw.E, w.sbar, pl.p, lgD},
+                         StAdjFinish{w.zbar, w.thbar, rho, pl.k, pl.p, lgD}, st);
   launch_make_v(pl, w.cw.E, w.sbar, w.Wb, st);
-  if ((e = fft_grids(w.Wb, int64_t(pl.n) * pl.p, pl.g, +1, st)) != hipSuccess) return e;
+  if ((e = fft_grids(w.Wb, np, pl.g, +1, st)) != hipSuccess) return e;
   hipLaunchKernelGGL(d_adj_finish, g3, dim3(kDW), 0, st, w.Wb, w.zbar, w.thbar, rho, pl.k, pl.p, D);
   return hipGetLastError();
 }

@@ -134,6 +134,25 @@ def test_checkpoint_interval_does_not_change_gradient(lib):
         assert np.array_equal(got[1], ref[1]) and got[2] == ref[2], every
 
 
+@pytest.mark.parametrize("grid,fs", [((128, 256), (11, 11)), ((4, 16, 16), (3, 5, 5))])
+def test_gradient_axis_path_grids(lib, grid, fs):
+    """Grids transformed axis by axis (beyond one LDS tile, and a 3-D volume),
+    where the adjoint folds its elementwise steps into the transform passes:
+    gradient against the oracle's reverse pass, bit-identical for checkpoint
+    intervals 2 and 5."""
+    rng = np.random.default_rng(8 if len(grid) == 2 else 9)
+    b = (synth.contrast_normalize(synth.one_over_f(rng, grid)) * 30)[None, None]
+    d = synth.unit_filters(4 if len(grid) == 2 else 3, 1, fs, 78 if len(grid) == 2 else 79)
+    ref = unrolled_grad(lib, b, d, 1.0, 10.0, 8, 2)
+    got = unrolled_grad(lib, b, d, 1.0, 10.0, 8, 5)
+    assert np.array_equal(got[1], ref[1]) and got[2] == ref[2]
+    Lr, gdr, gbr = oracle.code_loss_grad(b, d, 1.0, 10.0, 8)
+    scale = max(np.abs(gdr).max(), abs(gbr))
+    assert abs(ref[0] - Lr) <= 1e-5 * abs(Lr)
+    assert np.abs(ref[1] - gdr).max() <= GRAD_RTOL * scale, np.abs(ref[1] - gdr).max() / scale
+    assert abs(ref[2] - gbr) <= GRAD_RTOL * scale
+
+
 def test_zero_iterations(lib):
     import torch
     cfg = synth.CONFIGS["unrolled_fd"]
