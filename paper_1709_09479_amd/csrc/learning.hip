@@ -826,10 +826,12 @@ static bool crop_tile_launch(const Plan& pl, float2* Tp, const float* mu, hipStr
 // ------------------------------------------------ pruned operator (host)
 // U for A v: pass A with the row stage and the column-stage partials, then
 // the back-row and last stages into Uc.
+// With `have_upart` the column-stage partials of v are already in w.Upart
+// (pass A of the same v and code spectra ran last) and pass A is skipped.
 static hipError_t pruned_zt_proj(const Plan& pl, LearnWs& w, const float2* v, const float* mu, hipStream_t st,
-                                 const int* cgf) {
+                                 const int* cgf, bool have_upart = false) {
   const int H = pl.g[1], W = pl.g[2], R = 256 / W, M1 = pl.fs[1], M2 = pl.fs[2], G = passa_groups(pl);
-  {
+  if (!have_upart) {
     TraceScope trace(kTraceLearnA, st, true);
     LAUNCH_J_TRACED(trace, l_passA_rows, pl.j, dim3(G, pl.p), dim3(256), st, w.Zh, v, w.Upart, pl.n, pl.p, H, W, M1, M2,
        lanes_for(2 * R * M2, W), cgf);
@@ -922,10 +924,11 @@ int run_learn(const Plan& pl, const float* b, const float* z, float* d, float* m
   const int npB = pruned ? w.nB : w.npartB;
   // the operator A v = v + sum_k 1/(2 mu_k) Z_k S^T S Z_k^T v into q (with xh:
   // q = -x - A v), dot partials as pruned_passB
-  auto apply_A = [&](const float2* v, float2* q, const float2* xh, double* part, double* vpart) -> hipError_t {
+  auto apply_A = [&](const float2* v, float2* q, const float2* xh, double* part, double* vpart,
+                     bool have_upart = false) -> hipError_t {
     hipError_t err;
     if (pruned) {
-      if ((err = pruned_zt_proj(pl, w, v, mu, st, cgf)) != hipSuccess) return err;
+      if ((err = pruned_zt_proj(pl, w, v, mu, st, cgf, have_upart)) != hipSuccess) return err;
       pruned_passB(pl, w, v, q, xh, part, vpart, st, cgf);
     } else {
       if ((err = apply_zt_proj(pl, w, v, mu, st, cgf)) != hipSuccess) return err;
@@ -937,8 +940,10 @@ int run_learn(const Plan& pl, const float* b, const float* z, float* d, float* m
     int* cnt = cg_counts ? cg_counts + it : nullptr;
     if (tol_mode) hipLaunchKernelGGL(l_cg_reset, dim3(1), dim3(64), 0, st, cgf, cnt);
     else if (cnt) hipLaunchKernelGGL(l_cg_reset, dim3(1), dim3(64), 0, st, w.cgf, cnt);
-    // r = -x - A gamma, then per step w = A r and the update (l_cg_cg)
-    if ((e = apply_A(w.gh, w.rh, w.xh, rrp, nullptr)) != hipSuccess) return CSC_EHIP;
+    // r = -x - A gamma, then per step w = A r and the update (l_cg_cg).
+    // After the first multiplier step, pass A of gamma is the one the
+    // filter recovery just ran (same gamma, same code spectra).
+    if ((e = apply_A(w.gh, w.rh, w.xh, rrp, nullptr, pruned && it > 0)) != hipSuccess) return CSC_EHIP;
     double* sc_in = w.rr;
     double* sc_out = w.rr + 2 * J;
     for (int q = 0; q < cg_iters; ++q) {
