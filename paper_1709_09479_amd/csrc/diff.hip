@@ -259,14 +259,21 @@ __global__ __launch_bounds__(kSumT) void d_sum(const double* __restrict__ part, 
 // arithmetic of its stand-alone kernel exactly.
 constexpr int kOpTile = 4096, kOpThreads = 256;
 
+// Each operator splits into fetch(i) -> Pre (global loads only) and
+// make(i, pre) / put(i, v, pre) (arithmetic and stores), so that a thread
+// issues the loads of all its elements before its first store.
 struct LdPlain {
   const float2* d;
-  __device__ float2 operator()(int64_t i) { return d[i]; }
+  using Pre = float2;
+  __device__ Pre fetch(int64_t i) const { return d[i]; }
+  __device__ float2 make(int64_t, const Pre& v) { return v; }
   __device__ void flush(double*) {}
 };
 struct StPlain {
   float2* d;
-  __device__ void operator()(int64_t i, float2 v) { d[i] = v; }
+  struct Pre {};
+  __device__ Pre fetch(int64_t) const { return Pre{}; }
+  __device__ void put(int64_t i, float2 v, const Pre&) { d[i] = v; }
   __device__ void flush(double*) {}
 };
 
@@ -277,21 +284,37 @@ __device__ __forceinline__ void op_index(int64_t i, int lgD, int P, int& n, int&
   n = (int)(g / P);
   p = (int)(g - int64_t(n) * P);
 }
+// offset of map 2p of image n at f, and whether map 2p + 1 exists
+__device__ __forceinline__ int64_t op_map(int64_t i, int lgD, int K, int P, int& n, bool& hb) {
+  int p;
+  int64_t f;
+  op_index(i, lgD, P, n, p, f);
+  hb = 2 * p + 1 < K;
+  return ((int64_t(n) * K + 2 * p) << lgD) + f;
+}
 
 // d_pack_w: the pairs of w = theta + z/rho
 struct LdPackW {
   const float *z, *th, *rho;
   int K, P, lgD;
-  __device__ float2 operator()(int64_t i) {
-    int n, p;
-    int64_t f;
-    op_index(i, lgD, P, n, p, f);
-    const int64_t D = int64_t(1) << lgD;
-    const float ir = 1.0f / rho[n];
-    const int64_t a = (int64_t(n) * K + 2 * p) * D + f;
-    float2 v = make_float2(th[a] + z[a] * ir, 0.f);
-    if (2 * p + 1 < K) v.y = th[a + D] + z[a + D] * ir;
-    return v;
+  struct Pre {
+    float za, zb, ta, tb, r;
+  };
+  __device__ Pre fetch(int64_t i) const {
+    int n;
+    bool hb;
+    const int64_t a = op_map(i, lgD, K, P, n, hb), D = int64_t(1) << lgD;
+    Pre q;
+    q.r = rho[n];
+    q.za = z[a];
+    q.ta = th[a];
+    q.zb = hb ? z[a + D] : 0.f;
+    q.tb = hb ? th[a + D] : 0.f;
+    return q;
+  }
+  __device__ float2 make(int64_t, const Pre& q) {
+    const float ir = 1.0f / q.r;
+    return make_float2(q.ta + q.za * ir, q.tb + q.zb * ir);
   }
   __device__ void flush(double*) {}
 };
@@ -304,21 +327,35 @@ struct LdAdjClip {
   double* bpart;
   int K, P, lgD;
   double bs;
-  __device__ float2 operator()(int64_t i) {
-    int n, p;
-    int64_t f;
-    op_index(i, lgD, P, n, p, f);
-    const int64_t D = int64_t(1) << lgD;
-    const float r = rho[n], ir = 1.0f / r;
-    const int64_t a = (int64_t(n) * K + 2 * p) * D + f;
+  struct Pre {
+    float zn[2], zb[2], tb[2], r;
+  };
+  __device__ Pre fetch(int64_t i) const {
+    int n;
+    bool hb;
+    const int64_t a = op_map(i, lgD, K, P, n, hb), D = int64_t(1) << lgD;
+    Pre q;
+    q.r = rho[n];
+    for (int s = 0; s < 2; ++s) {
+      const bool on = s == 0 || hb;
+      q.zn[s] = on ? znext[a + s * D] : 0.f;
+      q.zb[s] = on ? zbar[a + s * D] : 0.f;
+      q.tb[s] = on ? thbar[a + s * D] : 0.f;
+    }
+    return q;
+  }
+  __device__ float2 make(int64_t i, const Pre& q) {
+    int n;
+    bool hb;
+    const int64_t a = op_map(i, lgD, K, P, n, hb), D = int64_t(1) << lgD;
+    const float r = q.r, ir = 1.0f / r;
     float vbar[2] = {0.f, 0.f};
-    for (int s = 0; s < 2 && 2 * p + s < K; ++s) {
-      const float zn = znext[a + s * D];
-      const float zb = zbar[a + s * D];
-      const float t = thbar[a + s * D] + r * zb;
-      const bool pass = zn == 0.f;
+    for (int s = 0; s < 2 && (s == 0 || hb); ++s) {
+      const float zb = q.zb[s];
+      const float t = q.tb[s] + r * zb;
+      const bool pass = q.zn[s] == 0.f;
       const float ub = pass ? t : 0.f;
-      if (!pass) bs += (double)(zn < 0.f ? t : -t);
+      if (!pass) bs += (double)(q.zn[s] < 0.f ? t : -t);
       vbar[s] = ub - r * zb;
       zbar[a + s * D] = zb - ub * ir;
     }
@@ -334,13 +371,16 @@ struct LdAdjClip {
 struct LdMakeV {
   const float2 *E, *lam;
   int P, lgD;
-  __device__ float2 operator()(int64_t i) {
+  struct Pre {
+    float2 l, e;
+  };
+  __device__ Pre fetch(int64_t i) const {
     int n, p;
     int64_t f;
     op_index(i, lgD, P, n, p, f);
-    const int64_t D = int64_t(1) << lgD;
-    return cmul(lam[int64_t(n) * D + f], E[int64_t(p) * D + f]);
+    return Pre{lam[(int64_t(n) << lgD) + f], E[(int64_t(p) << lgD) + f]};
   }
+  __device__ float2 make(int64_t, const Pre& q) { return cmul(q.l, q.e); }
   __device__ void flush(double*) {}
 };
 
@@ -349,17 +389,28 @@ struct StAdjFinish {
   float *zbar, *thbar;
   const float* rho;
   int K, P, lgD;
-  __device__ void operator()(int64_t i, float2 c) {
-    int n, p;
-    int64_t f;
-    op_index(i, lgD, P, n, p, f);
-    const int64_t D = int64_t(1) << lgD;
-    const float ir = 1.0f / rho[n], invD = 1.0f / (float)D;
-    const int64_t a = (int64_t(n) * K + 2 * p) * D + f;
-    for (int s = 0; s < 2 && 2 * p + s < K; ++s) {
+  struct Pre {
+    float zb[2], r;
+  };
+  __device__ Pre fetch(int64_t i) const {
+    int n;
+    bool hb;
+    const int64_t a = op_map(i, lgD, K, P, n, hb), D = int64_t(1) << lgD;
+    Pre q;
+    q.r = rho[n];
+    q.zb[0] = zbar[a];
+    q.zb[1] = hb ? zbar[a + D] : 0.f;
+    return q;
+  }
+  __device__ void put(int64_t i, float2 c, const Pre& q) {
+    int n;
+    bool hb;
+    const int64_t a = op_map(i, lgD, K, P, n, hb), D = int64_t(1) << lgD;
+    const float ir = 1.0f / q.r, invD = 1.0f / (float)D;
+    for (int s = 0; s < 2 && (s == 0 || hb); ++s) {
       const float wb = (s ? c.y : c.x) * invD;
       thbar[a + s * D] = wb;
-      zbar[a + s * D] += wb * ir;
+      zbar[a + s * D] = q.zb[s] + wb * ir;
     }
   }
   __device__ void flush(double*) {}
@@ -369,7 +420,7 @@ struct StAdjFinish {
 template <int L, int DIR, class LD, class ST>
 __global__ __launch_bounds__(kOpThreads) void d_fft_axis_op(LD ld, ST sto, int64_t outer, int64_t inner, int lbi,
                                                             int lbo) {
-  constexpr int T = kOpTile, NT = kOpThreads, LP = L + 1;
+  constexpr int T = kOpTile, NT = kOpThreads, LP = L + 1, EPT = T / NT;
   __shared__ float2 tile[(T / L) * LP];
   __shared__ float2 tw[256];
   __shared__ double red[NT / 64];
@@ -379,21 +430,47 @@ __global__ __launch_bounds__(kOpThreads) void d_fft_axis_op(LD ld, ST sto, int64
   const int64_t t = blockIdx.x;
   const int64_t o0 = (t / tiles_in) << lbo;
   const int64_t i0 = (t % tiles_in) << lbi;
-  for (int e = threadIdx.x; e < T; e += NT) {
+  auto elem = [&](int k, int64_t& idx, int& slot) {
+    const int e = threadIdx.x + k * NT;
     const int b_in = e & (bi - 1);
     const int jj = (e >> lbi) & (L - 1);
     const int b_o = e >> lbi >> __builtin_ctz(L);
-    float2 v = make_float2(0.f, 0.f);
-    if (o0 + b_o < outer) v = ld(((o0 + b_o) * L + jj) * inner + i0 + b_in);
-    tile[((b_o << lbi) + b_in) * LP + jj] = v;
+    idx = ((o0 + b_o) * L + jj) * inner + i0 + b_in;
+    slot = ((b_o << lbi) + b_in) * LP + jj;
+    return o0 + b_o < outer;
+  };
+  {
+    typename LD::Pre pre[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      int64_t idx;
+      int slot;
+      if (elem(k, idx, slot)) pre[k] = ld.fetch(idx);
+    }
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      int64_t idx;
+      int slot;
+      const bool ok = elem(k, idx, slot);
+      tile[slot] = ok ? ld.make(idx, pre[k]) : make_float2(0.f, 0.f);
+    }
   }
   __syncthreads();
   fft_lines<L, T, NT, DIR, 1, LP>(tile, tw);
-  for (int e = threadIdx.x; e < T; e += NT) {
-    const int b_in = e & (bi - 1);
-    const int jj = (e >> lbi) & (L - 1);
-    const int b_o = e >> lbi >> __builtin_ctz(L);
-    if (o0 + b_o < outer) sto(((o0 + b_o) * L + jj) * inner + i0 + b_in, tile[((b_o << lbi) + b_in) * LP + jj]);
+  {
+    typename ST::Pre pre[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      int64_t idx;
+      int slot;
+      if (elem(k, idx, slot)) pre[k] = sto.fetch(idx);
+    }
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      int64_t idx;
+      int slot;
+      if (elem(k, idx, slot)) sto.put(idx, tile[slot], pre[k]);
+    }
   }
   ld.flush(red);
   sto.flush(red);
@@ -424,12 +501,23 @@ static hipError_t axis_op(LD ld, ST sto, int64_t outer, int L, int64_t inner, hi
 }
 
 // Transform of `count` grids in place (as fft_grids on the axis path) with
-// LD feeding the first pass and ST taking the last pass's output.
-template <int DIR, class LD, class ST>
+// LD feeding the first pass and ST taking the last pass's output.  The axes
+// go W, H, T, or with W_LAST T, H, W: the W pass moves whole contiguous
+// lines, so a store operator that writes per-map floats belongs there.
+template <int DIR, bool W_LAST = false, class LD, class ST>
 static hipError_t fft_fused(float2* data, int64_t count, const int g[3], LD ld, ST sto, hipStream_t st) {
   const int T = g[0], H = g[1], W = g[2];
-  hipError_t e = axis_op<DIR>(ld, StPlain{data}, count * T * H, W, 1, st);
-  if (e != hipSuccess) return e;
+  hipError_t e;
+  if (W_LAST) {
+    if (T > 1) {
+      if ((e = axis_op<DIR>(ld, StPlain{data}, count, T, int64_t(H) * W, st)) != hipSuccess) return e;
+      if ((e = axis_op<DIR>(LdPlain{data}, StPlain{data}, count * T, H, W, st)) != hipSuccess) return e;
+    } else if ((e = axis_op<DIR>(ld, StPlain{data}, count, H, W, st)) != hipSuccess) {
+      return e;
+    }
+    return axis_op<DIR>(LdPlain{data}, sto, count * T * H, W, 1, st);
+  }
+  if ((e = axis_op<DIR>(ld, StPlain{data}, count * T * H, W, 1, st)) != hipSuccess) return e;
   if (T > 1) {
     if ((e = axis_op<DIR>(LdPlain{data}, StPlain{data}, count * T, H, W, st)) != hipSuccess) return e;
     return axis_op<DIR>(LdPlain{data}, sto, count, T, int64_t(H) * W, st);
@@ -515,8 +603,8 @@ static hipError_t adjoint_iter(const Plan& pl, DiffWs& w, const float* z, const 
   hipLaunchKernelGGL(d_dbar, dim3(dblk(D), pl.p), dim3(kDW), 0, st, w.Vb, w.Wb, w.cw.E, w.lam, w.sbar, w.Dbar,
                      pl.n, pl.p, pl.g[0], pl.g[1], pl.g[2]);
   if (fused)
-    return fft_fused<+1>(w.Wb, np, pl.g, LdMakeV{w.cw.E, w.sbar, pl.p, lgD},
-                         StAdjFinish{w.zbar, w.thbar, rho, pl.k, pl.p, lgD}, st);
+    return fft_fused<+1, true>(w.Wb, np, pl.g, LdMakeV{w.cw.E, w.sbar, pl.p, lgD},
+                               StAdjFinish{w.zbar, w.thbar, rho, pl.k, pl.p, lgD}, st);
   launch_make_v(pl, w.cw.E, w.sbar, w.Wb, st);
   if ((e = fft_grids(w.Wb, np, pl.g, +1, st)) != hipSuccess) return e;
   hipLaunchKernelGGL(d_adj_finish, g3, dim3(kDW), 0, st, w.Wb, w.zbar, w.thbar, rho, pl.k, pl.p, D);

@@ -28,13 +28,24 @@ __global__ __launch_bounds__(kAxisThreads) void k_fft_axis(float2* __restrict__ 
   const int64_t t = blockIdx.x;
   const int64_t o0 = (t / tiles_in) << lbo;
   const int64_t i0 = (t % tiles_in) << lbi;
-  for (int e = threadIdx.x; e < T; e += NT) {
+  // all of a thread's loads are issued before the first LDS store
+  constexpr int EPT = T / NT;
+  float2 v[EPT];
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int e = threadIdx.x + k * NT;
     const int b_in = e & (bi - 1);
     const int jj = (e >> lbi) & (L - 1);
     const int b_o = e >> lbi >> __builtin_ctz(L);
-    float2 v = make_float2(0.f, 0.f);
-    if (o0 + b_o < outer) v = data[((o0 + b_o) * L + jj) * inner + i0 + b_in];
-    tile[((b_o << lbi) + b_in) * LP + jj] = v;
+    v[k] = o0 + b_o < outer ? data[((o0 + b_o) * L + jj) * inner + i0 + b_in] : make_float2(0.f, 0.f);
+  }
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int e = threadIdx.x + k * NT;
+    const int b_in = e & (bi - 1);
+    const int jj = (e >> lbi) & (L - 1);
+    const int b_o = e >> lbi >> __builtin_ctz(L);
+    tile[((b_o << lbi) + b_in) * LP + jj] = v[k];
   }
   __syncthreads();
   fft_lines<L, T, NT, DIR, 1, LP>(tile, tw);
@@ -56,7 +67,21 @@ __global__ __launch_bounds__(tile_threads(H * W)) void k_fft2d(float2* __restric
   __shared__ float2 tw[256];
   float2* g = data + (int64_t)blockIdx.x * D;
   load_twiddles(tw);
-  for (int e = threadIdx.x; e < D; e += NT) tile[(e / W) * WP + (e % W)] = g[e];
+  {
+    // all of a thread's loads are issued before the first LDS store
+    constexpr int EPT = (D + NT - 1) / NT;
+    float2 v[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const int e = threadIdx.x + k * NT;
+      if (e < D) v[k] = g[e];
+    }
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const int e = threadIdx.x + k * NT;
+      if (e < D) tile[(e / W) * WP + (e % W)] = v[k];
+    }
+  }
   __syncthreads();
   fft2d_tile<H, W, WP, NT, DIR>(tile, tw);
   for (int e = threadIdx.x; e < D; e += NT) g[e] = tile[(e / W) * WP + (e % W)];
