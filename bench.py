@@ -20,8 +20,9 @@ the same step.
 
 ``--calibrate-copy MIB`` only runs a plain device copy of that size (the
 reference kernel for scaling the FETCH_SIZE / WRITE_SIZE counters);
-``--profile-leg`` runs only the timed calls of the batched leg or of the
-plain solver of the differentiable leg, for counter collection.
+``--profile-leg`` runs only the timed calls of the batched leg, of the
+plain solver of the differentiable leg, or of that leg's forward + backward
+(``unrolled``), for kernel traces and counter collection.
 """
 import argparse
 import json
@@ -171,7 +172,7 @@ def bench_batched(dc, synth, np, torch, n_images, plain=True):
     return out
 
 
-def bench_backward(dc, synth, np, torch, reps=2, only_plain=False):
+def bench_backward(dc, synth, np, torch, reps=2, only_plain=False, only_fwd_bwd=False):
     """Differentiable form: N = 16 images 256x256, K = 100 filters 11x11,
     30 unrolled ADMM iterations with checkpoints every 5, loss of eq:CSC;
     forward + backward (gradients w.r.t. filters and beta) against the plain
@@ -201,6 +202,8 @@ def bench_backward(dc, synth, np, torch, reps=2, only_plain=False):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / n
 
+    if only_fwd_bwd:
+        return {"forward_backward_ms": timed(fwd_bwd, reps)}
     ms_plain = timed(lambda: dc.code(bt, d, cfg.beta, cfg.rho, cfg.t_in), reps)
     traffic = counter_traffic("unrolled_plain_call")
     alg = alg_bytes_per_iter(cfg.n, cfg.j, cfg.k, cfg.grid[0] * cfg.grid[1]) * cfg.t_in
@@ -308,7 +311,7 @@ def main():
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--batched-images", type=int, default=256)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB")
-    ap.add_argument("--profile-leg", choices=["batched", "unrolled-plain"], default=None,
+    ap.add_argument("--profile-leg", choices=["batched", "unrolled-plain", "unrolled"], default=None,
                     help="run only the timed calls of one leg (for counter collection)")
     ap.add_argument("--sweep", default=None, metavar="NAMES",
                     help="comma-separated scaling sweeps (gray_K, gray_N, rgb_K, rgb_N, video_K, or all): "
@@ -344,6 +347,9 @@ def main():
         return
     if args.profile_leg == "unrolled-plain":
         print(json.dumps(bench_backward(dc, synth, np, torch, only_plain=True)))
+        return
+    if args.profile_leg == "unrolled":
+        print(json.dumps(bench_backward(dc, synth, np, torch, only_fwd_bwd=True)))
         return
     cfg = synth.CONFIGS["learn"]
     b, d0 = synth.make_inputs(cfg)
