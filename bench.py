@@ -303,7 +303,7 @@ def run_sweeps(names):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-images", type=int, default=2)
@@ -375,17 +375,17 @@ def main():
     torch.cuda.synchronize()
     dc.trace_enable(True, every=TRACE_EVERY)
     stream = torch.cuda.current_stream()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
-    ev0.record(stream)
-    for _ in range(args.steps):
+    evs[0].record(stream)
+    for i in range(args.steps):
         step()
-    ev1.record(stream)
+        evs[i + 1].record(stream)
     torch.cuda.synchronize()
     dc.trace_enable(False)
-    ms_total = ev0.elapsed_time(ev1)
+    ms_total = evs[0].elapsed_time(evs[-1])
     ms_step = ms_total / args.steps
+    per_step = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
     maps_ms, maps_cnt = dc.trace_read(dc.TRACE_CODE_MAPS)
     spec_ms, spec_cnt = dc.trace_read(dc.TRACE_CODE_SPEC)
     la_ms, la_cnt = dc.trace_read(dc.TRACE_LEARN_A)
@@ -450,6 +450,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "step_ms_p10_p50_p90": [float(np.percentile(per_step, q)) for q in (10, 50, 90)],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
