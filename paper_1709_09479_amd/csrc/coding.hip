@@ -967,13 +967,14 @@ hipError_t replay_code(const Plan& pl, CodeWs& w, const float* rho, float beta, 
   const int T = pl.g[0], H = pl.g[1], W = pl.g[2];
   const float* s = rec + 2 * nz;
   hipLaunchKernelGGL(k_copy_f, dim3(nblk(N)), dim3(kEW), 0, st, w.rho, rho, N);
-  hipLaunchKernelGGL(k_copy_f, dim3(nblk(2 * nz)), dim3(kEW), 0, st, seg, rec, 2 * nz);
   hipLaunchKernelGGL(k_copy_f, dim3(nblk(2 * ns)), dim3(kEW), 0, st, (float*)w.yh, s, 2 * ns);
   hipLaunchKernelGGL(k_copy_f, dim3(nblk(2 * ns)), dim3(kEW), 0, st, (float*)w.Th, s + 2 * ns, 2 * ns);
   hipLaunchKernelGGL(k_copy_f, dim3(nblk(2 * ns)), dim3(kEW), 0, st, (float*)w.lam, s + 4 * ns, 2 * ns);
   for (int i = 1; i < nstates; ++i) {
-    float* zi = seg + int64_t(i) * 2 * nz;
-    hipLaunchKernelGGL(k_copy_f, dim3(nblk(nz)), dim3(kEW), 0, st, zi, zi - 2 * nz, nz);
+    // the iteration updates z in place: start from the previous state's codes
+    float* zi = seg + int64_t(i - 1) * 2 * nz;
+    const float* zprev = i == 1 ? rec : zi - 2 * nz;
+    hipLaunchKernelGGL(k_copy_f, dim3(nblk(nz)), dim3(kEW), 0, st, zi, zprev, nz);
     hipError_t e = iterate_maps(pl, w, zi, zi + nz, beta, st, nullptr);
     if (e != hipSuccess) return e;
     if (i < nstates - 1)

@@ -548,7 +548,7 @@ static size_t carve_diff(const Plan& pl, int every, void* base, DiffWs* w) {
   w->Dbar = c.take<float2>(P * D);
   w->zbar = c.take<float>(N * K * D);
   w->thbar = c.take<float>(N * K * D);
-  w->seg = c.take<float>(int64_t(every > 0 ? every + 1 : 2) * 2 * N * K * D);
+  w->seg = c.take<float>(int64_t(every > 0 ? every : 1) * 2 * N * K * D);
   w->nbpart = N * P * int64_t(dblk(D));
   w->bpart = c.take<double>(w->nbpart + 1);
   return c.off;
@@ -651,9 +651,10 @@ int run_backward(const Plan& pl, const float* b, const float* d, float beta, con
     const bool last_seg = sgi == nseg - 1;
     if (replay_code(pl, w.cw, rho, beta, ck, len + (last_seg ? 1 : 0), w.seg, st) != hipSuccess) return CSC_EHIP;
     for (int i = len - 1; i >= 0; --i) {
-      const float* zi = w.seg + int64_t(i) * 2 * nz;
-      const float* znext =
-          (i + 1 < len || last_seg) ? zi + 2 * nz : ckpt + int64_t(sgi + 1) * code_record_floats(pl);
+      // state i of the segment: the record (i = 0) or replay slot i - 1
+      const float* zi = i == 0 ? ck : w.seg + int64_t(i - 1) * 2 * nz;
+      const float* znext = (i + 1 < len || last_seg) ? w.seg + int64_t(i) * 2 * nz
+                                                     : ckpt + int64_t(sgi + 1) * code_record_floats(pl);
       if (adjoint_iter(pl, w, zi, zi + nz, znext, rho, st) != hipSuccess) return CSC_EHIP;
     }
   }

@@ -97,10 +97,12 @@ int run_code(const Plan& pl, const float* b, const float* d, float beta, float* 
              float* z, float* theta, double* resid, void* ws, hipStream_t st, float tol = 0.0f,
              int* iters_done = nullptr, float* ckpt = nullptr, int every = 0);
 int64_t code_record_floats(const Plan& pl);
-// Resumes run_code's fixed-step loop from a record: seg[i] ([2][N][K][grid],
-// z then theta) receives the state after i more iterations, i < nstates,
-// equal bit for bit to the states the uninterrupted loop passes through.  E,
-// G and xh of `w` must hold the spectra of the same images and filters.
+// Resumes run_code's fixed-step loop from a record: seg[i - 1]
+// ([2][N][K][grid], z then theta) receives the state after i more
+// iterations, 0 < i < nstates, equal bit for bit to the states the
+// uninterrupted loop passes through (the state after 0 iterations is the
+// record's own first [2][N][K][grid] floats).  E, G and xh of `w` must hold
+// the spectra of the same images and filters.
 hipError_t replay_code(const Plan& pl, CodeWs& w, const float* rho, float beta, const float* rec, int nstates, float* seg,
                        hipStream_t st);
 // part <- per-group spectral contributions sum_p DFT(maps pair) conj(E_p);
