@@ -76,7 +76,9 @@ __global__ void d_reduce_solve(const float2* __restrict__ buf, const float2* __r
   const int n = blockIdx.y;
   if (f >= D) return;
   const int64_t fn = dneg(f, T, H, W);
+  if (fn < f) return;  // the pair (f, -f) is handled by its lower index
   float2 y = make_float2(0.f, 0.f), ym = make_float2(0.f, 0.f);
+#pragma unroll 4
   for (int p = 0; p < P; ++p) {
     const float2* bp = buf + (int64_t(n) * P + p) * D;
     const float2* ep = E + int64_t(p) * D;
@@ -84,13 +86,18 @@ __global__ void d_reduce_solve(const float2* __restrict__ buf, const float2* __r
     ym = cadd(ym, cmulc(bp[fn], ep[fn]));
   }
   const float ir = 1.0f / rho[n];
-  float2 s = make_float2(0.5f * (y.x + ym.x), 0.5f * (y.y - ym.y));
-  if (xh) {
-    const float2 x = xh[int64_t(n) * D + f];
-    s = make_float2(s.x - x.x * ir, s.y - x.y * ir);
+  // at f from (y, ym) and at -f from (ym, y)
+  for (int side = 0; side < (fn == f ? 1 : 2); ++side) {
+    const int64_t ff = side ? fn : f;
+    const float2 a = side ? ym : y, b = side ? y : ym;
+    float2 s = make_float2(0.5f * (a.x + b.x), 0.5f * (a.y - b.y));
+    if (xh) {
+      const float2 x = xh[int64_t(n) * D + ff];
+      s = make_float2(s.x - x.x * ir, s.y - x.y * ir);
+    }
+    const float den = G[ff].x + ir;
+    out[int64_t(n) * D + ff] = make_float2(s.x / den, s.y / den);
   }
-  const float den = G[f].x + ir;
-  out[int64_t(n) * D + f] = make_float2(s.x / den, s.y / den);
 }
 
 // Adjoint of the clip and z updates.  The clip's branch at each code is the
