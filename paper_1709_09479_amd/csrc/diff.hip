@@ -147,6 +147,11 @@ __global__ void d_dbar(const float2* __restrict__ Vb, const float2* __restrict__
   const int p = blockIdx.y;
   if (f >= D) return;
   const int64_t fn = dneg(f, T, H, W);
+  // the pair (f, -f) is handled by its lower index: the unpacked values at
+  // -f are the exact conjugates of those at f, so both outputs come from
+  // one read of the pair spectra (lam and sbar are read at both)
+  if (fn < f) return;
+  const int sides = fn == f ? 1 : 2;
   float2 da = make_float2(0.f, 0.f), db = make_float2(0.f, 0.f);
   if (Wb) {
     const float2 ef = E[int64_t(p) * D + f], em = E[int64_t(p) * D + fn];
@@ -154,27 +159,38 @@ __global__ void d_dbar(const float2* __restrict__ Vb, const float2* __restrict__
     da = make_float2(0.5f * (ef.x + em.x), 0.5f * (-ef.y + em.y));
     db = make_float2(0.5f * (ef.y + em.y), 0.5f * (ef.x - em.x));
   }
-  float2 acc_a = make_float2(0.f, 0.f), acc_b = make_float2(0.f, 0.f);
+  float2 acc_a[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+  float2 acc_b[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
   for (int n = 0; n < N; ++n) {
     const float2* vp = Vb + (int64_t(n) * P + p) * D;
     float2 va, vb;
     dunpack(vp[f], vp[fn], va, vb);
-    const float2 l = lam[int64_t(n) * D + f];
-    acc_a = cadd(acc_a, cmulc(l, va));
-    acc_b = cadd(acc_b, cmulc(l, vb));
+    float2 wa = make_float2(0.f, 0.f), wb = make_float2(0.f, 0.f);
     if (Wb) {
       const float2* wp = Wb + (int64_t(n) * P + p) * D;
-      float2 wa, wb;
       dunpack(wp[f], wp[fn], wa, wb);
-      const float2 s = sbar[int64_t(n) * D + f];
-      const float re2 = 2.0f * (l.x * s.x + l.y * s.y);
-      acc_a = cadd(acc_a, csub(cmulc(s, wa), cscale(da, re2)));
-      acc_b = cadd(acc_b, csub(cmulc(s, wb), cscale(db, re2)));
+    }
+    for (int side = 0; side < sides; ++side) {
+      const int64_t ff = side ? fn : f;
+      const float2 va_s = side ? cconj(va) : va, vb_s = side ? cconj(vb) : vb;
+      const float2 l = lam[int64_t(n) * D + ff];
+      acc_a[side] = cadd(acc_a[side], cmulc(l, va_s));
+      acc_b[side] = cadd(acc_b[side], cmulc(l, vb_s));
+      if (Wb) {
+        const float2 wa_s = side ? cconj(wa) : wa, wb_s = side ? cconj(wb) : wb;
+        const float2 da_s = side ? cconj(da) : da, db_s = side ? cconj(db) : db;
+        const float2 s = sbar[int64_t(n) * D + ff];
+        const float re2 = 2.0f * (l.x * s.x + l.y * s.y);
+        acc_a[side] = cadd(acc_a[side], csub(cmulc(s, wa_s), cscale(da_s, re2)));
+        acc_b[side] = cadd(acc_b[side], csub(cmulc(s, wb_s), cscale(db_s, re2)));
+      }
     }
   }
-  float2* o = Dbar + int64_t(p) * D + f;
-  const float2 cur = *o;
-  *o = make_float2(cur.x + acc_a.x - acc_b.y, cur.y + acc_a.y + acc_b.x);
+  for (int side = 0; side < sides; ++side) {
+    float2* o = Dbar + int64_t(p) * D + (side ? fn : f);
+    const float2 cur = *o;
+    *o = make_float2(cur.x + acc_a[side].x - acc_b[side].y, cur.y + acc_a[side].y + acc_b[side].x);
+  }
 }
 
 // thetabar = wbar, zbar += wbar / rho, from W = D * (wbar_2p + i wbar_2p+1).
