@@ -52,6 +52,7 @@ extern "C" {
 #define CSC_EWORKSPACE (-2)   /* workspace NULL, too small or not 256-B aligned */
 #define CSC_EUNSUPPORTED (-3) /* geometry outside the supported set */
 #define CSC_EHIP (-4)         /* a HIP runtime call failed */
+#define CSC_ENONFINITE (-5)   /* NaN or infinity found (csc_check_finite's flag, raised by the binding) */
 
 /* Workspace query operations. */
 #define CSC_OP_CODE 1
@@ -319,6 +320,19 @@ int csc_batch_autotune(const csc_batch* batch, const float* b, const float* d,
  */
 int csc_trace_enable(int on);
 int csc_trace_read(int cls, double* total_ms, int* count);
+
+/*
+ * Non-finite detection.  The library never synchronises with the device,
+ * so a NaN or infinity in a result (diverging iterations, bad inputs) is
+ * found by a check the caller enqueues and reads: csc_check_finite writes
+ * *flag = 1 if any of x[0 .. n) is NaN or +-infinity, else 0, on `stream`
+ * after the work already enqueued there.  x, flag: device pointers
+ * (caller-owned; x may be NULL when n = 0); n >= 0 (n = 0 writes 0).  A
+ * caller that finds the flag set reports CSC_ENONFINITE (the Python binding
+ * raises it).
+ * Errors: CSC_EINVAL (NULL flag, NULL x with n > 0, n < 0), CSC_EHIP.
+ */
+int csc_check_finite(const float* x, int64_t n, int* flag, void* stream);
 
 /* Static description of a return code. */
 const char* csc_strerror(int code);

@@ -13,6 +13,7 @@ filters d [K][J][*fsupp], codes z [N][K][*grid], all float32 on the GPU.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 from typing import Optional, Sequence, Tuple
 
@@ -27,7 +28,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 _LIB_NAME = "libdualcsc.so"
 
 ABI_VERSION = 2
-OK, EINVAL, EWORKSPACE, EUNSUPPORTED, EHIP = 0, -1, -2, -3, -4
+OK, EINVAL, EWORKSPACE, EUNSUPPORTED, EHIP, ENONFINITE = 0, -1, -2, -3, -4, -5
 OP_CODE, OP_LEARN, OP_OBJECTIVE = 1, 2, 3
 ADAPTIVE_RHO, Z_ZERO, THETA_ZERO, GAMMA_ZERO, USE_GRAPH = 0x1, 0x2, 0x4, 0x8, 0x10
 
@@ -112,6 +113,8 @@ def load() -> ctypes.CDLL:
     lib.csc_objective.argtypes = [sp, vp, vp, vp, f32, vp, vp, sz, vp]
     lib.csc_trace_enable.restype = i32
     lib.csc_trace_enable.argtypes = [i32]
+    lib.csc_check_finite.restype = i32
+    lib.csc_check_finite.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
     lib.csc_trace_read.restype = i32
     lib.csc_trace_read.argtypes = [i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
     bp = ctypes.POINTER(Batch)
@@ -382,6 +385,20 @@ def objective(b, d, z, beta: float):
 TRACE_CODE_MAPS, TRACE_CODE_SPEC, TRACE_LEARN_A, TRACE_LEARN_B = 0, 1, 2, 3
 
 
+def check_finite(*tensors) -> None:
+    """Raise DualCSCError(ENONFINITE) if any of the given float32 device
+    tensors holds a NaN or an infinity (csc_check_finite; waits for the
+    stream)."""
+    torch = _torch()
+    lib = load()
+    flags = torch.empty(max(1, len(tensors)), dtype=torch.int32, device=tensors[0].device if tensors else "cuda")
+    for i, t in enumerate(tensors):
+        _need(t, "tensor")
+        _check(lib.csc_check_finite(_ptr(t), t.numel(), flags[i:].data_ptr(), _stream()))
+    if tensors and int(flags[:len(tensors)].max().item()):
+        raise DualCSCError(ENONFINITE, lib.csc_strerror(ENONFINITE).decode())
+
+
 def trace_enable(on: bool = True, every: int = 1) -> None:
     """Start (clearing earlier records) or stop event tracing of launches;
     with ``every`` = n only every n-th launch of each class is bracketed."""
@@ -442,6 +459,8 @@ def learn_dictionary(b, d0, beta: float, rho, t_in: int, t_out: int, inner_iters
         steps += 1
         if tau is not None and len(objs) >= 4:
             f_new, f_old = float(objs[-1].item()), float(objs[-3].item())
+            if not (math.isfinite(f_new) and math.isfinite(f_old)):
+                raise DualCSCError(ENONFINITE, load().csc_strerror(ENONFINITE).decode())
             if abs(f_new - f_old) <= tau * abs(f_old):
                 break
     out = {"d": d, "z": z, "theta": theta, "mu": mu, "gamma": gamma, "rho": rho_t,

@@ -184,6 +184,11 @@ extern "C" {
 
 int csc_abi_version(void) { return CSC_ABI_VERSION; }
 
+int csc_check_finite(const float* x, int64_t n, int* flag, void* stream) {
+  if (!flag || n < 0 || (n > 0 && !x)) return CSC_EINVAL;
+  return launch_check_finite(x, n, flag, static_cast<hipStream_t>(stream)) == hipSuccess ? CSC_OK : CSC_EHIP;
+}
+
 int csc_trace_enable(int on) {
   if (on < 0) return CSC_EINVAL;
   std::lock_guard<std::mutex> lk(g_trace_mu);
@@ -233,6 +238,7 @@ const char* csc_strerror(int code) {
     case CSC_EWORKSPACE: return "workspace missing, too small or not 256-byte aligned";
     case CSC_EUNSUPPORTED: return "geometry not supported";
     case CSC_EHIP: return "HIP runtime error";
+    case CSC_ENONFINITE: return "non-finite value (NaN or infinity) in a result";
     default: return "unknown error";
   }
 }

@@ -20,6 +20,8 @@
 // of sum_j lamhat_j E_jp yields D^T lam for both maps (real and imaginary
 // part), and one complex forward FFT C of (z_2p + i z_2p+1) gives their
 // contribution to yhat as (Y(f) + conj(Y(-f)))/2 with Y = C conj(E).
+#include <algorithm>
+
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -980,6 +982,32 @@ hipError_t replay_code(const Plan& pl, CodeWs& w, const float* rho, float beta, 
     if (i < nstates - 1)
       LAUNCH_J(k_spec, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.part, w.G, w.xh, w.yh, w.Th, w.lam, w.rho, w.rdual,
                w.ngp, T, H, W, 1, nullptr);
+  }
+  return hipGetLastError();
+}
+
+__global__ void k_flag_zero(int* __restrict__ flag) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) flag[0] = 0;
+}
+// Every workgroup that sees a NaN or an infinity stores 1 (the same value
+// from any number of workgroups, so no atomics and no ordering are needed).
+__global__ __launch_bounds__(kEW) void k_check_finite(const float* __restrict__ x, int64_t n, int* __restrict__ flag) {
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  int mine = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    mine |= !isfinite(x[i]);
+  if (mine) bad = 1;
+  __syncthreads();
+  if (threadIdx.x == 0 && bad) flag[0] = 1;
+}
+
+hipError_t launch_check_finite(const float* x, int64_t n, int* flag, hipStream_t st) {
+  hipLaunchKernelGGL(k_flag_zero, dim3(1), dim3(64), 0, st, flag);
+  if (n > 0) {
+    const int64_t blocks = std::min<int64_t>((n + kEW - 1) / kEW, 4096);
+    hipLaunchKernelGGL(k_check_finite, dim3((unsigned)blocks), dim3(kEW), 0, st, x, n, flag);
   }
   return hipGetLastError();
 }

@@ -120,6 +120,9 @@ void launch_objective_tail(const Plan& pl, CodeWs& w, float beta, double* out, h
 // calls replay the executable graph.  Returns a CSC_* code.
 int graph_call(const std::vector<int64_t>& key, hipStream_t st, int (*enqueue)(void*), void* ctx);
 
+// *flag = 1 if any of x[0 .. n) is NaN or +-infinity, else 0 (enqueued).
+hipError_t launch_check_finite(const float* x, int64_t n, int* flag, hipStream_t st);
+
 // Launch tracing.  While enabled (csc_trace_enable), a sampled TraceScope
 // times the launches made in its lifetime with a pair of HIP events on the
 // launching stream; csc_trace_read sums the elapsed times per class.  A

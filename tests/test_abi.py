@@ -175,3 +175,13 @@ def test_unrolled_record_size():
         assert lib.csc_unrolled_record_floats(ctypes.byref(s)) == n * grid[0] * grid[1] * (2 * k + 6)
     assert lib.csc_unrolled_record_floats(ctypes.byref(shape(j=3))) == 0
     assert lib.csc_unrolled_record_floats(ctypes.byref(shape(grid=(60, 64)))) == 0
+
+
+def test_check_finite_argument_errors():
+    """csc_check_finite validates its arguments on the host; CSC_ENONFINITE
+    has its own message."""
+    lib = dc.load()
+    assert lib.csc_check_finite(None, 4, FAKE, None) == dc.EINVAL
+    assert lib.csc_check_finite(FAKE, -1, FAKE, None) == dc.EINVAL
+    assert lib.csc_check_finite(FAKE, 4, None, None) == dc.EINVAL
+    assert b"non-finite" in lib.csc_strerror(dc.ENONFINITE)

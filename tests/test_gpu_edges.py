@@ -90,3 +90,20 @@ def test_learn_degenerate_shapes(lib, grid, k, fs, n, amp, beta):
     assert np.abs(N(d) - d_ref).max() <= 1e-4 * max(1.0, float(np.abs(d_ref).max()))
     np.testing.assert_allclose(N(mu), mu_ref, rtol=1e-4)
     assert np.abs(N(gamma) - g_ref).max() <= 1e-4 * max(1.0, float(np.abs(g_ref).max()))
+
+
+def test_check_finite(lib):
+    """Non-finite detection (csc_check_finite through the binding): finite
+    data passes; a NaN, +inf or -inf anywhere (also the last element of a
+    tensor larger than one pass of the grid) raises CSC_ENONFINITE; an empty
+    tensor passes."""
+    import torch
+    x = torch.randn(3_000_001, device="cuda")
+    lib.check_finite(x, torch.zeros(0, device="cuda"))
+    for bad, at in ((float("nan"), 17), (float("inf"), -1), (float("-inf"), 1_500_000)):
+        y = x.clone()
+        y[at] = bad
+        with pytest.raises(lib.DualCSCError) as e:
+            lib.check_finite(x, y)
+        assert e.value.code == lib.ENONFINITE
+    lib.check_finite(x)
