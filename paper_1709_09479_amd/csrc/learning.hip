@@ -452,21 +452,55 @@ __global__ __launch_bounds__(256) void l_prune_uc(const float2* __restrict__ Upa
   }
 }
 
-// Filter recovery (eq:Learning_Solution) from pass A of gamma:
-// d_k,j[m] = -u_k,j[m] for the two filters of pair p (one workgroup per
-// (pair, channel)).
-__global__ __launch_bounds__(256) void l_drec_u(const float2* __restrict__ Upart, const float* __restrict__ mu,
-                                                float* __restrict__ d, int K, int J, int P, int H, int W, int M1,
-                                                int M2, int G) {
-  const int p = blockIdx.x, j = blockIdx.y, MM = M1 * M2;
+// Filter recovery (eq:Learning_Solution) from pass A of gamma and the
+// multiplier update (eq:mu_update) in one workgroup per pair p:
+// d_k,j[m] = -u_k,j[m] for the two filters of the pair over every channel,
+// then ||d_k|| over channels and taps, mu_k <- mu_k ||d_k|| (kept when the
+// norm is 0) and, with `project`, d_k <- d_k / max(1, ||d_k||).  A thread
+// keeps its (at most one per channel, M1 M2 <= 256) taps in registers.
+template <int J>
+__global__ __launch_bounds__(256) void l_drec_mu(const float2* __restrict__ Upart, float* __restrict__ mu,
+                                                 float* __restrict__ d, int K, int P, int H, int W, int M1, int M2,
+                                                 int G, int project) {
+  __shared__ double red[256 / 64];
+  __shared__ double bc[2];
+  const int p = blockIdx.x, MM = M1 * M2, o = threadIdx.x;
+  const bool hb = 2 * p + 1 < K;
   const float invD = 1.0f / (float)(H * W);
   const float sa = invD / (2.0f * mu[2 * p]);
-  const float sb = (2 * p + 1 < K) ? invD / (2.0f * mu[2 * p + 1]) : 0.f;
-  const float2* up = Upart + (int64_t(j) * P + p) * G * MM;
-  for (int o = threadIdx.x; o < MM; o += 256) {
-    const float2 a = sum_upart(up, G, MM, o, sa, sb);
-    d[(int64_t(2 * p) * J + j) * MM + o] = -a.x;
-    if (2 * p + 1 < K) d[(int64_t(2 * p + 1) * J + j) * MM + o] = -a.y;
+  const float sb = hb ? invD / (2.0f * mu[2 * p + 1]) : 0.f;
+  float va[J], vb[J];
+  double qa = 0.0, qb = 0.0;
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    va[j] = vb[j] = 0.f;
+    if (o < MM) {
+      const float2 a = sum_upart(Upart + (int64_t(j) * P + p) * G * MM, G, MM, o, sa, sb);
+      va[j] = -a.x;
+      vb[j] = -a.y;
+      qa += (double)va[j] * va[j];
+      qb += (double)vb[j] * vb[j];
+    }
+  }
+  const double ta = block_sum(qa, red);
+  if (threadIdx.x == 0) bc[0] = sqrt(ta);
+  __syncthreads();
+  const double tb = block_sum(qb, red);
+  if (threadIdx.x == 0) bc[1] = sqrt(tb);
+  __syncthreads();
+  const double na = bc[0], nb = bc[1];
+  const float ca = (project && na > 1.0) ? (float)(1.0 / na) : 1.f;
+  const float cb = (project && nb > 1.0) ? (float)(1.0 / nb) : 1.f;
+  if (o < MM) {
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      d[(int64_t(2 * p) * J + j) * MM + o] = ca == 1.f ? va[j] : va[j] * ca;
+      if (hb) d[(int64_t(2 * p + 1) * J + j) * MM + o] = cb == 1.f ? vb[j] : vb[j] * cb;
+    }
+  }
+  if (threadIdx.x == 0) {
+    if (na > 0.0) mu[2 * p] = (float)((double)mu[2 * p] * na);
+    if (hb && nb > 0.0) mu[2 * p + 1] = (float)((double)mu[2 * p + 1] * nb);
   }
 }
 
@@ -841,16 +875,16 @@ static hipError_t pruned_zt_proj(const Plan& pl, LearnWs& w, const float2* v, co
   return hipGetLastError();
 }
 
-// d_k = -S Z_k^T gamma / (2 mu_k) through pass A and the column stage.
-static hipError_t pruned_drecover(const Plan& pl, LearnWs& w, const float* mu, float* d, hipStream_t st) {
+// d_k = -S Z_k^T gamma / (2 mu_k) through pass A and the column stage, then
+// the multiplier update (and with `project` the unit-ball projection).
+static hipError_t pruned_drecover(const Plan& pl, LearnWs& w, float* mu, float* d, bool project, hipStream_t st) {
   const int H = pl.g[1], W = pl.g[2], R = 256 / W, M1 = pl.fs[1], M2 = pl.fs[2], G = passa_groups(pl);
   {
     TraceScope trace(kTraceLearnA, st, true);
     LAUNCH_J_TRACED(trace, l_passA_rows, pl.j, dim3(G, pl.p), dim3(256), st, w.Zh, w.gh, w.Upart, pl.n, pl.p, H, W, M1, M2,
        lanes_for(2 * R * M2, W), nullptr);
   }
-  hipLaunchKernelGGL(l_drec_u, dim3(pl.p, pl.j), dim3(256), 0, st, w.Upart, mu, d, pl.k, pl.j, pl.p, H, W, M1, M2,
-                     G);
+  LJ(l_drec_mu, pl.j, dim3(pl.p), dim3(256), st, w.Upart, mu, d, pl.k, pl.p, H, W, M1, M2, G, project ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -955,16 +989,16 @@ int run_learn(const Plan& pl, const float* b, const float* z, float* d, float* m
       sc_out = t;
     }
     // d_k = -S Z_k^T gamma / (2 mu_k) ; mu_k <- mu_k ||d_k||
+    const bool last = it == inner_iters - 1;
     if (pruned) {
-      if ((e = pruned_drecover(pl, w, mu, d, st)) != hipSuccess) return CSC_EHIP;
+      if ((e = pruned_drecover(pl, w, mu, d, last, st)) != hipSuccess) return CSC_EHIP;
     } else {
       LJ(l_passA, pl.j, dim3(lblk(D), pl.p), dim3(kLW), st, w.Zh, w.gh, w.Tp, pl.n, pl.p, T, H, W, nullptr);
       if ((e = fft_grids(w.Tp, J * pl.p, pl.g, +1, st)) != hipSuccess) return CSC_EHIP;
       hipLaunchKernelGGL(l_drecover, dim3(lblk(pl.msz), pl.k, pl.j), dim3(kLW), 0, st, w.Tp, mu, d, pl.k, pl.j,
                          pl.p, T, H, W, pl.fs[0], pl.fs[1], pl.fs[2]);
+      hipLaunchKernelGGL(l_mu_update, dim3(pl.k), dim3(kLW), 0, st, d, mu, int64_t(J) * pl.msz, 1, last ? 1 : 0);
     }
-    const bool last = it == inner_iters - 1;
-    hipLaunchKernelGGL(l_mu_update, dim3(pl.k), dim3(kLW), 0, st, d, mu, int64_t(J) * pl.msz, 1, last ? 1 : 0);
   }
   // gamma back to the spatial domain
   hipMemcpyAsync(w.rh, w.gh, sizeof(float2) * ns, hipMemcpyDeviceToDevice, st);
