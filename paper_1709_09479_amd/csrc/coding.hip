@@ -850,9 +850,16 @@ hipError_t forward_maps(const Plan& pl, const float* maps, CodeWs& w, double* l1
 }
 
 // One ADMM iteration's map work: back-projection, soft threshold, forward.
+// One ADMM iteration's map kernels.  zin: the codes to start from (null: z,
+// updated in place); the split path reads them directly, the others copy
+// them into z first.
 static hipError_t iterate_maps(const Plan& pl, CodeWs& w, float* z, float* theta, float beta, hipStream_t st,
-                               const int* stop) {
+                               const int* stop, const float* zin = nullptr) {
   const int64_t D = pl.dsz;
+  if (zin && pl.zoff) return hipErrorInvalidValue;  // dense layouts only
+  if (zin && !pl.split)
+    hipLaunchKernelGGL(k_copy_f, dim3(nblk(int64_t(pl.n) * pl.k * D)), dim3(kEW), 0, st, z, zin,
+                       int64_t(pl.n) * pl.k * D);
   // one kernel on the single-tile path (timed at its own start and end),
   // several otherwise (timed around them)
   TraceScope trace(kTraceCodeMaps, st, pl.lds);
@@ -863,7 +870,7 @@ static hipError_t iterate_maps(const Plan& pl, CodeWs& w, float* z, float* theta
       return hipErrorInvalidValue;
     return hipGetLastError();
   }
-  if (pl.split) return split_maps(pl, w.E, w.lam, w.buf, z, theta, w.rho, beta, w.part, w.rpri, 0, st, stop);
+  if (pl.split) return split_maps(pl, w.E, w.lam, w.buf, z, theta, w.rho, beta, w.part, w.rpri, 0, st, stop, zin);
   LAUNCH_J(k_make_v, pl.j, dim3(nblk(D), pl.p, pl.n), dim3(kEW), st, w.E, w.lam, w.buf, pl.p, D, stop);
   hipError_t e = fft_grids(w.buf, int64_t(pl.n) * pl.p, pl.g, +1, st);
   if (e != hipSuccess) return e;
@@ -976,8 +983,7 @@ hipError_t replay_code(const Plan& pl, CodeWs& w, const float* rho, float beta, 
     // the iteration updates z in place: start from the previous state's codes
     float* zi = seg + int64_t(i - 1) * 2 * nz;
     const float* zprev = i == 1 ? rec : zi - 2 * nz;
-    hipLaunchKernelGGL(k_copy_f, dim3(nblk(nz)), dim3(kEW), 0, st, zi, zprev, nz);
-    hipError_t e = iterate_maps(pl, w, zi, zi + nz, beta, st, nullptr);
+    hipError_t e = iterate_maps(pl, w, zi, zi + nz, beta, st, nullptr, zprev);
     if (e != hipSuccess) return e;
     if (i < nstates - 1)
       LAUNCH_J(k_spec, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.part, w.G, w.xh, w.yh, w.Th, w.lam, w.rho, w.rdual,

@@ -51,7 +51,7 @@ int split_row_blocks(const Plan& pl);
 // With `stop` (tolerance mode) the kernels return at once when stop[0] is set.
 hipError_t split_maps(const Plan& pl, const float2* E, const float2* lam, float2* buf, float* z, float* theta,
                       const float* rho, float beta, float2* part, double* rpart, int mode, hipStream_t st,
-                      const int* stop);
+                      const int* stop, const float* zin = nullptr);
 
 // Workspace carving: aligned sub-buffers of one caller-provided block.
 struct Carver {

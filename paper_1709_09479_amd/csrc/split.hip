@@ -72,11 +72,14 @@ __global__ __launch_bounds__(kSplitNT) void k_split_rows_inv(const float2* __res
 }
 
 // ---------------------------------------------------------------- columns
-// MODE 0 (iteration): column-IDFT, soft-threshold step, column-DFT.
+// MODE 0 (iteration): column-IDFT, soft-threshold step, column-DFT; the
+// codes are read from zin (the same layout as z; null: z itself, updated in
+// place) and written to z.
 // MODE 1 (forward only): the map pair enters from z, l1 partials.
 // rpart[n][p * gridDim.x + blockIdx.x]: sum (z' - z)^2, or sum |z|.
 template <int H, int MODE>
 __global__ __launch_bounds__(kSplitNT) void k_split_cols(float2* __restrict__ buf, float* __restrict__ z,
+                                                         const float* zin,
                                                          float* __restrict__ theta, const int64_t* __restrict__ zoff,
                                                          const float* __restrict__ rho_cur, float beta,
                                                          double* __restrict__ rpart, int K, int P, int W,
@@ -102,6 +105,9 @@ __global__ __launch_bounds__(kSplitNT) void k_split_cols(float2* __restrict__ bu
   const int64_t zbase = map_base(zoff, n, K, D);
   float* za = z + zbase + int64_t(ka) * D;
   float* zb = z + zbase + int64_t(hb ? kb : ka) * D;
+  const float* zsrc = (MODE == 0 && zin) ? zin : z;
+  const float* zia = zsrc + zbase + int64_t(ka) * D;
+  const float* zib = zsrc + zbase + int64_t(hb ? kb : ka) * D;
   const int tid = opaque_tid();
   double rsum = 0.0;
   float2 v[F0::JPT][F0::R];
@@ -128,7 +134,7 @@ __global__ __launch_bounds__(kSplitNT) void k_split_cols(float2* __restrict__ bu
       for (int r = 0; r < CL::R; ++r) {
         const int64_t f = int64_t(CL::out_pos(j, r)) * W + c0 + b;
         const float va = v[q][r].x * invD, vb = v[q][r].y * invD;
-        const float a0 = za[f], b0 = hb ? zb[f] : 0.f;
+        const float a0 = zia[f], b0 = hb ? zib[f] : 0.f;
         const float a1 = soft_thresh(fmaf(-rho, va, a0), thr);
         const float b1 = hb ? soft_thresh(fmaf(-rho, vb, b0), thr) : 0.f;
         const float da = a1 - a0, db = b1 - b0;
@@ -250,7 +256,7 @@ int split_row_blocks(const Plan& pl) { return pl.g[1] / (kSplitT / pl.g[2]); }
 template <int J>
 static hipError_t split_iter_j(const Plan& pl, const float2* E, const float2* lam, float2* buf, float* z,
                                float* theta, const float* rho, float beta, float2* part, double* rpart, int mode,
-                               hipStream_t st, const int* stop) {
+                               hipStream_t st, const int* stop, const float* zin) {
   const int H = pl.g[1], W = pl.g[2];
   const dim3 blk(kSplitNT);
   if (mode == 0) {
@@ -261,14 +267,18 @@ static hipError_t split_iter_j(const Plan& pl, const float2* E, const float2* la
   const dim3 g2(split_col_blocks(pl), pl.p, pl.n);
   if (mode == 0) {
     if (H == 256)
-      hipLaunchKernelGGL((k_split_cols<256, 0>), g2, blk, 0, st, buf, z, theta, pl.zoff, rho, beta, rpart, pl.k, pl.p, W, stop);
+      hipLaunchKernelGGL((k_split_cols<256, 0>), g2, blk, 0, st, buf, z, zin, theta, pl.zoff, rho, beta, rpart, pl.k,
+                         pl.p, W, stop);
     else
-      hipLaunchKernelGGL((k_split_cols<128, 0>), g2, blk, 0, st, buf, z, theta, pl.zoff, rho, beta, rpart, pl.k, pl.p, W, stop);
+      hipLaunchKernelGGL((k_split_cols<128, 0>), g2, blk, 0, st, buf, z, zin, theta, pl.zoff, rho, beta, rpart, pl.k,
+                         pl.p, W, stop);
   } else {
     if (H == 256)
-      hipLaunchKernelGGL((k_split_cols<256, 1>), g2, blk, 0, st, buf, z, nullptr, pl.zoff, rho, 0.f, rpart, pl.k, pl.p, W, stop);
+      hipLaunchKernelGGL((k_split_cols<256, 1>), g2, blk, 0, st, buf, z, nullptr, nullptr, pl.zoff, rho, 0.f, rpart,
+                         pl.k, pl.p, W, stop);
     else
-      hipLaunchKernelGGL((k_split_cols<128, 1>), g2, blk, 0, st, buf, z, nullptr, pl.zoff, rho, 0.f, rpart, pl.k, pl.p, W, stop);
+      hipLaunchKernelGGL((k_split_cols<128, 1>), g2, blk, 0, st, buf, z, nullptr, nullptr, pl.zoff, rho, 0.f, rpart,
+                         pl.k, pl.p, W, stop);
   }
   const dim3 g3(split_row_blocks(pl) * pl.ng * pl.n);
   if (W == 256) hipLaunchKernelGGL((k_split_rows_fwd<256, J>), g3, blk, 0, st, E, buf, part, pl.p, H, pl.ppg, pl.ng, stop);
@@ -280,10 +290,10 @@ static hipError_t split_iter_j(const Plan& pl, const float2* E, const float2* la
 // the given maps (z), l1 partials in rpart.
 hipError_t split_maps(const Plan& pl, const float2* E, const float2* lam, float2* buf, float* z, float* theta,
                       const float* rho, float beta, float2* part, double* rpart, int mode, hipStream_t st,
-                      const int* stop) {
-  if (pl.j == 1) return split_iter_j<1>(pl, E, lam, buf, z, theta, rho, beta, part, rpart, mode, st, stop);
-  if (pl.j == 2) return split_iter_j<2>(pl, E, lam, buf, z, theta, rho, beta, part, rpart, mode, st, stop);
-  return split_iter_j<3>(pl, E, lam, buf, z, theta, rho, beta, part, rpart, mode, st, stop);
+                      const int* stop, const float* zin) {
+  if (pl.j == 1) return split_iter_j<1>(pl, E, lam, buf, z, theta, rho, beta, part, rpart, mode, st, stop, zin);
+  if (pl.j == 2) return split_iter_j<2>(pl, E, lam, buf, z, theta, rho, beta, part, rpart, mode, st, stop, zin);
+  return split_iter_j<3>(pl, E, lam, buf, z, theta, rho, beta, part, rpart, mode, st, stop, zin);
 }
 
 }  // namespace dcsc
