@@ -936,14 +936,23 @@ int run_code(const Plan& pl, const float* b, const float* d, float beta, float* 
     hipLaunchKernelGGL(k_fill_f2, dim3(nblk(nz)), dim3(kEW), 0, st, (float2*)ckpt, nz);
     save_spec(ckpt);
   }
+  // on the split path a record iteration writes its codes straight into the
+  // record and the next iteration reads them from there (records are never
+  // at the last iteration, so z ends with the final codes); elsewhere they
+  // are copied
+  const float* zsrc = nullptr;  // where the current codes are, when not in z
   for (int it = 0; it < iters; ++it) {
     const bool last = it == iters - 1;
     // theta is written by the last iteration, or by every one when the loop may stop early
     float* th_out = (last || tol_mode) ? theta : nullptr;
     float* rec = (ckpt && !last && (it + 1) % every == 0) ? ckpt + int64_t((it + 1) / every) * rec_floats : nullptr;
     if (rec) th_out = rec + nz;
-    if ((e = iterate_maps(pl, w, z, th_out, beta, st, stop)) != hipSuccess) return CSC_EHIP;
-    if (rec) hipLaunchKernelGGL(k_copy_f, dim3(nblk(nz)), dim3(kEW), 0, st, rec, z, nz);
+    const bool into_rec = rec && pl.split;
+    // the input is wherever the current codes are (z unless a record holds them)
+    const float* zin = into_rec ? (zsrc ? zsrc : z) : zsrc;
+    if ((e = iterate_maps(pl, w, into_rec ? rec : z, th_out, beta, st, stop, zin)) != hipSuccess) return CSC_EHIP;
+    zsrc = into_rec ? rec : nullptr;
+    if (rec && !into_rec) hipLaunchKernelGGL(k_copy_f, dim3(nblk(nz)), dim3(kEW), 0, st, rec, z, nz);
     const int solve_next = (!last && !adaptive) ? 1 : 0;
     {
       TraceScope trace(kTraceCodeSpec, st, true);

@@ -46,14 +46,23 @@ def test_unrolled_forward_is_the_coding_iteration(lib):
             assert np.array_equal(z, z_code), (grid, every)
 
 
-def test_unrolled_records_hold_the_states(lib):
+@pytest.mark.parametrize("split", [False, True])
+def test_unrolled_records_hold_the_states(lib, split):
     """Records 0, 1, 2 of iters = 9, every = 4 hold (z, theta) after 0, 4
     and 8 iterations (csc_code's, bit for bit), at the record stride the
-    library reports, and nothing is written past the last record."""
+    library reports, and nothing is written past the last record; on a
+    single-tile grid and on a 128 x 256 grid (split path, where record
+    iterations write their codes straight into the record)."""
     import ctypes
     import torch
     cfg = synth.CONFIGS["small"]
-    b, d = synth.make_inputs(cfg, n=2)
+    if split:
+        rng = np.random.default_rng(12)
+        b = np.stack([synth.contrast_normalize(synth.one_over_f(rng, (128, 256)))[None] * 10 for _ in range(2)])
+        b = b.astype(np.float32)
+        d = synth.unit_filters(cfg.k, 1, (11, 11), 5)
+    else:
+        b, d = synth.make_inputs(cfg, n=2)
     bt, dt = T(b), T(d)
     shape = lib._shape_of(bt, dt)
     L = lib.load()
