@@ -27,7 +27,7 @@ constexpr int kLW = 256;
 #define LEARN_PRUNED 1
 #endif
 #ifndef LEARN_A_U4
-#define LEARN_A_U4 4  // pass A: images whose loads are issued together
+#define LEARN_A_U4 5  // pass A: images whose loads are issued together
 #endif
 #ifndef LEARN_B_NB1
 #define LEARN_B_NB1 10  // pass B: largest image chunk for one channel
