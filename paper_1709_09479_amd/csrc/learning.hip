@@ -375,6 +375,11 @@ __device__ __forceinline__ float2 sum_upart(const float2* __restrict__ up, int G
 #define LEARN_UC_COLS 8  // columns per workgroup of the back-row and last stages
 #endif
 constexpr int kUcCols = LEARN_UC_COLS;
+#ifndef LEARN_UC_ACC
+#define LEARN_UC_ACC 16  // partials of pass A loaded together per thread (a power of two)
+#endif
+constexpr int kUcAcc = LEARN_UC_ACC;
+static_assert((kUcAcc & (kUcAcc - 1)) == 0, "kUcAcc must be a power of two");
 __global__ __launch_bounds__(256) void l_prune_uc(const float2* __restrict__ Upart, float4* __restrict__ Uc,
                                                   const float* __restrict__ mu, int K, int P, int H, int W, int M1,
                                                   int M2, int G, const int* __restrict__ cgf) {
@@ -390,21 +395,26 @@ __global__ __launch_bounds__(256) void l_prune_uc(const float2* __restrict__ Upa
   const float sb = (2 * p + 1 < K) ? invD / (2.0f * mu[2 * p + 1]) : 0.f;
   const float2* up = Upart + (int64_t(j) * P + p) * G * MM;
   // u = sum of the G partials: with M1 M2 <= 128 the two halves of the
-  // workgroup take the even and the odd partials, added in that order
+  // workgroup take the even and the odd partials, added in that order into
+  // kUcAcc accumulators (as many loads in flight per thread)
   if (MM <= 128) {
     const int o = threadIdx.x & 127, hf = threadIdx.x >> 7;
-    float2 a[4];
+    float2 a[kUcAcc];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) a[t] = make_float2(0.f, 0.f);
+    for (int t = 0; t < kUcAcc; ++t) a[t] = make_float2(0.f, 0.f);
     if (o < MM) {
       int gi = hf;
-      for (; gi + 6 < G; gi += 8) {
+      for (; gi + 2 * (kUcAcc - 1) < G; gi += 2 * kUcAcc) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) a[t] = cadd(a[t], up[int64_t(gi + 2 * t) * MM + o]);
+        for (int t = 0; t < kUcAcc; ++t) a[t] = cadd(a[t], up[int64_t(gi + 2 * t) * MM + o]);
       }
       for (; gi < G; gi += 2) a[0] = cadd(a[0], up[int64_t(gi) * MM + o]);
     }
-    const float2 t = cadd(cadd(a[0], a[1]), cadd(a[2], a[3]));
+#pragma unroll
+    for (int h = kUcAcc / 2; h > 0; h /= 2)
+#pragma unroll
+      for (int t = 0; t < h; ++t) a[t] = cadd(a[t], a[t + h]);
+    const float2 t = a[0];
     if (hf && o < MM) half[o] = t;
     __syncthreads();
     if (!hf && o < MM) {
