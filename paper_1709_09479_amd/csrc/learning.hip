@@ -630,14 +630,23 @@ __global__ __launch_bounds__(64 * kBW) void l_passB_c(const float2* __restrict__
   }
 }
 
-// Fixed-order sum of `cnt` partials by one block (all threads get the total).
-__device__ __forceinline__ double sum_partials(const double* __restrict__ p, int cnt, double* red, double* bcast) {
-  double s = 0.0;
-  for (int i = threadIdx.x; i < cnt; i += blockDim.x) s += p[i];
-  const double t = block_sum(s, red);
-  if (threadIdx.x == 0) *bcast = t;
+// Fixed-order sums of two arrays of `cnt` partials by one block, read in one
+// pass (thread t adds elements t, t + blockDim.x, ..., then block_sum); every
+// thread gets both totals.  bcast holds two values.
+__device__ __forceinline__ void sum_partials2(const double* __restrict__ a, const double* __restrict__ b, int cnt,
+                                              double* red, double* bcast, double& sa, double& sb) {
+  double u = 0.0, v = 0.0;
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+    u += a[i];
+    v += b[i];
+  }
+  const double ta = block_sum(u, red);
+  if (threadIdx.x == 0) bcast[0] = ta;
+  const double tb = block_sum(v, red);
+  if (threadIdx.x == 0) bcast[1] = tb;
   __syncthreads();
-  return *bcast;
+  sa = bcast[0];
+  sb = bcast[1];
 }
 
 // One conjugate-gradient step in the arrangement of Chronopoulos and Gear
@@ -661,16 +670,34 @@ __global__ __launch_bounds__(kLW) void l_cg_cg(float2* __restrict__ x, float2* _
                                                const double* __restrict__ bb, double tol2, int* __restrict__ count) {
   if (cgf && cgf[0]) return;
   __shared__ double red[kLW / 64];
-  __shared__ double bc;
+  __shared__ double bc[2];
   const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int n = blockIdx.y;
   const bool lead = blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0;
+  const bool in = f < D;
+  // the vectors do not depend on the scalars: their loads are issued first
+  // and are in flight during the reduction of the partials
+  float2 rv[J], wv[J], po[J], so[J], xv[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    rv[j] = wv[j] = po[j] = so[j] = xv[j] = make_float2(0.f, 0.f);
+    if (in) {
+      const int64_t o = (int64_t(n) * J + j) * D + f;
+      rv[j] = r[o];
+      wv[j] = w[o];
+      xv[j] = x[o];
+      if (!first) {
+        po[j] = p[o];
+        so[j] = s[o];
+      }
+    }
+  }
   double al[J], be[J];
   bool conv = cgf != nullptr;
 #pragma unroll
   for (int j = 0; j < J; ++j) {
-    const double gam = sum_partials(gpart + int64_t(j) * npart, npart, red, &bc);
-    const double del = sum_partials(dpart + int64_t(j) * npart, npart, red, &bc);
+    double gam, del;
+    sum_partials2(gpart + int64_t(j) * npart, dpart + int64_t(j) * npart, npart, red, bc, gam, del);
     const double gp = first ? 0.0 : sc_in[j], ap = first ? 0.0 : sc_in[J + j];
     const double b = gp > 0.0 ? gam / gp : 0.0;
     const double den = ap > 0.0 ? del - b * gam / ap : del;
@@ -687,23 +714,20 @@ __global__ __launch_bounds__(kLW) void l_cg_cg(float2* __restrict__ x, float2* _
     return;
   }
   if (count && lead) count[0] += 1;
-  if (f < D) {
+  if (in) {
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const int64_t o = (int64_t(n) * J + j) * D + f;
       const float a = (float)al[j], b = (float)be[j];
-      const float2 rv = r[o], wv = w[o];
-      float2 pp = rv, ss = wv;
+      float2 pp = rv[j], ss = wv[j];
       if (!first) {
-        const float2 po = p[o], so = s[o];
-        pp = make_float2(fmaf(b, po.x, rv.x), fmaf(b, po.y, rv.y));
-        ss = make_float2(fmaf(b, so.x, wv.x), fmaf(b, so.y, wv.y));
+        pp = make_float2(fmaf(b, po[j].x, rv[j].x), fmaf(b, po[j].y, rv[j].y));
+        ss = make_float2(fmaf(b, so[j].x, wv[j].x), fmaf(b, so[j].y, wv[j].y));
       }
-      const float2 xv = x[o];
       p[o] = pp;
       s[o] = ss;
-      x[o] = make_float2(fmaf(a, pp.x, xv.x), fmaf(a, pp.y, xv.y));
-      r[o] = make_float2(fmaf(-a, ss.x, rv.x), fmaf(-a, ss.y, rv.y));
+      x[o] = make_float2(fmaf(a, pp.x, xv[j].x), fmaf(a, pp.y, xv[j].y));
+      r[o] = make_float2(fmaf(-a, ss.x, rv[j].x), fmaf(-a, ss.y, rv[j].y));
     }
   }
 }
