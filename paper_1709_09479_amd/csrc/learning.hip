@@ -320,8 +320,20 @@ __global__ __launch_bounds__(256) void l_passA_rows(const float2* __restrict__ Z
     for (int ob = threadIdx.x / lanes; ob - threadIdx.x / lanes < O; ob += 256 / lanes) {
       const int o = ob < O ? ob : O - 1;
       const int slot = o / M2, m2 = o % M2;
-      float2 acc = make_float2(0.f, 0.f);
-      for (int c = l; c < W; c += lanes) acc = cadd(acc, cmul(ts[slot * W + c], twl(tw, (c * m2) & (W - 1), W, +1)));
+      // four independent chains over the lane's columns c = l, l + lanes, ...
+      float2 a4[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) a4[t] = make_float2(0.f, 0.f);
+      int c = l;
+      for (; c + 3 * lanes < W; c += 4 * lanes) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int cc = c + t * lanes;
+          a4[t] = cadd(a4[t], cmul(ts[slot * W + cc], twl(tw, (cc * m2) & (W - 1), W, +1)));
+        }
+      }
+      for (; c < W; c += lanes) a4[0] = cadd(a4[0], cmul(ts[slot * W + c], twl(tw, (c * m2) & (W - 1), W, +1)));
+      float2 acc = cadd(cadd(a4[0], a4[1]), cadd(a4[2], a4[3]));
       for (int off = lanes >> 1; off > 0; off >>= 1) {
         acc.x += __shfl_down(acc.x, off, lanes);
         acc.y += __shfl_down(acc.y, off, lanes);
