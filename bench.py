@@ -10,7 +10,7 @@ the objective.  Inputs are resident in HBM before timing starts.
 
 Printed: one JSON line.  ``value`` = code-pixel-iterations per second over the
 whole step (N * K * H * W * coding iterations / step time).  ``roofline``
-covers the kernel with the largest share of the step (learning pass A), its
+covers learning pass A (with pass B, the largest shares of the step), its
 launch duration measured with HIP events on its own stream during the timed
 steps; ``roofline_extra`` gives the same for learning pass B and the fused
 coding kernel.  ``traffic`` is taken from the committed rocprofv3 counter
