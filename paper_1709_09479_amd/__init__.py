@@ -79,9 +79,8 @@ _lib = None
 
 
 def lib_path() -> str:
-    """The in-tree library, or the file named by DUALCSC_LIB (another build of
-    the same sources, e.g. for A/B timing)."""
-    return os.environ.get("DUALCSC_LIB") or os.path.join(_PKG, _LIB_NAME)
+    """The in-tree library (built by ``paper_1709_09479_amd.build``)."""
+    return os.path.join(_PKG, _LIB_NAME)
 
 
 def load() -> ctypes.CDLL:

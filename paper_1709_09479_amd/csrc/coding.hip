@@ -418,14 +418,8 @@ __global__ void k_fill_i(int* __restrict__ out, int v) {
 // Threads per workgroup of the fused kernel: 32 elements per thread (512
 // threads for the largest tiles).  J = 1 keeps its accumulator in
 // registers; J > 1 accumulates into its partial slice in global memory.
-#ifndef FUSED_GACC
-#define FUSED_GACC 0
-#endif
-#ifndef FUSED_NT16K
-#define FUSED_NT16K 1024
-#endif
 constexpr int fused_threads(int t, int j) {
-  return j == 1 ? (t >= 16384 ? FUSED_NT16K : (t / 32 < 64 ? 64 : t / 32))
+  return j == 1 ? (t >= 16384 ? 1024 : (t / 32 < 64 ? 64 : t / 32))
                 : (t >= 16384 ? 1024 : (t / 16 < 64 ? 64 : t / 16));
 }
 
@@ -458,7 +452,7 @@ __global__ __launch_bounds__(fused_threads(H * W, J)) void k_fused(
   using P8 = typename PL::FwdRowL;
   static_assert(P4::JPT == P6::JPT && P4::R == P6::R, "register hand-off mismatch");
   static_assert(P1::JPT == P8::JPT && P1::R == P8::R, "register hand-off mismatch");
-  constexpr bool kRegAcc = (J == 1) && !FUSED_GACC;
+  constexpr bool kRegAcc = J == 1;
   __shared__ float2 tile[H * WP];
   __shared__ float2 tw[256];
   __shared__ double red[NT / 64];

@@ -307,9 +307,6 @@ __device__ __forceinline__ void pass_to_regs(int tid, const float2* tile, const 
   P::compute(tid, v);
 }
 
-#ifndef TILE_ROW_JFAST
-#define TILE_ROW_JFAST false
-#endif
 // Row stride of a padded W-wide tile (odd).
 constexpr int tile_stride(int W) { return W + W / 8 + 1; }
 // Pass types of the fused H x W tile transforms.
@@ -321,13 +318,13 @@ struct TilePlan {
   static constexpr int B0 = plan_r(H, 0), BL = plan_r(H, NB - 1);
   // inverse: rows (A0 from registers [, AL]), then columns ([B0,] BL to registers)
   using InvRow0 = TilePass<W, T, NT, 1, A0, 1, true, true, WP>;
-  using InvRow1 = TilePass<W, T, NT, 1, AL, A0, TILE_ROW_JFAST, true, WP>;
+  using InvRow1 = TilePass<W, T, NT, 1, AL, A0, false, true, WP>;
   using InvCol0 = TilePass<H, T, NT, 1, B0, 1, false, false, WP>;
   using InvColL = TilePass<H, T, NT, 1, BL, H / BL, false, false, WP>;
   // forward: columns (BL from registers [, B0]), then rows ([AL,] A0 to registers)
   using FwdCol0 = TilePass<H, T, NT, -1, BL, 1, false, false, WP>;
   using FwdCol1 = TilePass<H, T, NT, -1, B0, BL, false, false, WP>;
-  using FwdRow0 = TilePass<W, T, NT, -1, AL, 1, TILE_ROW_JFAST, true, WP>;
+  using FwdRow0 = TilePass<W, T, NT, -1, AL, 1, false, true, WP>;
   using FwdRowL = TilePass<W, T, NT, -1, A0, W / A0, true, true, WP>;
 };
 

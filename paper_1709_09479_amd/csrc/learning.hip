@@ -23,18 +23,8 @@ hipError_t fft_grids(float2* data, int64_t count, const int g[3], int dir, hipSt
 
 constexpr int kLW = 256;
 
-#ifndef LEARN_PRUNED
-#define LEARN_PRUNED 1
-#endif
-#ifndef LEARN_A_U4
-#define LEARN_A_U4 5  // pass A: images whose loads are issued together
-#endif
-#ifndef LEARN_B_NB1
-#define LEARN_B_NB1 10  // pass B: largest image chunk for one channel
-#endif
-#ifndef LEARN_BW
-#define LEARN_BW 16  // pass B: wavefronts per workgroup
-#endif
+constexpr int kPassAImgs = 5;    // pass A: images whose loads are issued together
+constexpr int kPassBChunk1 = 10; // pass B: largest image chunk for one channel
 
 static unsigned lblk(int64_t n, int b = kLW) { return (unsigned)((n + b - 1) / b); }
 
@@ -281,7 +271,7 @@ __global__ __launch_bounds__(256) void l_passA_rows(const float2* __restrict__ Z
 #pragma unroll
   for (int j = 0; j < J; ++j) ta[j] = tb[j] = make_float2(0.f, 0.f);
   if (act) {
-    constexpr int U4 = LEARN_A_U4;
+    constexpr int U4 = kPassAImgs;
     for (int n = 0; n < N; n += U4) {
       float2 zf[U4], zm[U4], x[U4][J];
 #pragma unroll
@@ -383,14 +373,8 @@ __device__ __forceinline__ float2 sum_upart(const float2* __restrict__ up, int G
 // and their mirrors W - c, and writes Uc[j][p][i] = (U_2p, U_2p+1) at the
 // canonical frequencies i = (f1, f2) of the slice (f2 in the slice), pair
 // unpacked, with U(f) = sum_m1 r[m1][f2] e^{-2 pi i f1 m1 / H}.
-#ifndef LEARN_UC_COLS
-#define LEARN_UC_COLS 8  // columns per workgroup of the back-row and last stages
-#endif
-constexpr int kUcCols = LEARN_UC_COLS;
-#ifndef LEARN_UC_ACC
-#define LEARN_UC_ACC 16  // partials of pass A loaded together per thread (a power of two)
-#endif
-constexpr int kUcAcc = LEARN_UC_ACC;
+constexpr int kUcCols = 8;  // columns per workgroup of the back-row and last stages
+constexpr int kUcAcc = 16;  // partials of pass A loaded together per thread (a power of two)
 static_assert((kUcAcc & (kUcAcc - 1)) == 0, "kUcAcc must be a power of two");
 __global__ __launch_bounds__(256) void l_prune_uc(const float2* __restrict__ Upart, float4* __restrict__ Uc,
                                                   const float* __restrict__ mu, int K, int P, int H, int W, int M1,
@@ -535,11 +519,11 @@ __global__ __launch_bounds__(256) void l_drec_mu(const float2* __restrict__ Upar
 // becomes -x - q.  Dot partials (sum over the block's frequencies of
 // Re(v conj q), or |q|^2 with xh, over the block's images) go to
 // dots[j nblk + block] with nblk = gridDim.x gridDim.y.
-constexpr int kBW = LEARN_BW;
+constexpr int kBW = 16;  // pass B: wavefronts per workgroup
 
 template <int J>
 constexpr int passb_nb() {
-  return J == 1 ? LEARN_B_NB1 : (J == 2 ? 4 : 2);
+  return J == 1 ? kPassBChunk1 : (J == 2 ? 4 : 2);
 }
 
 template <int J>
@@ -813,12 +797,7 @@ __global__ __launch_bounds__(kLW) void l_mu_update(float* __restrict__ d, float*
   } while (0)
 
 static bool pruned2d(const Plan& pl) {
-#if LEARN_PRUNED
   return pl.g[0] == 1 && pl.fs[1] <= kPruneMax && pl.fs[2] <= kPruneMax;
-#else
-  (void)pl;
-  return false;
-#endif
 }
 
 // 64-frequency blocks covering the canonical half of the spectrum
@@ -833,7 +812,7 @@ static int pow2_floor(int x) {
 // lanes per output for `outs` outputs of `len`-term sums on 256 threads
 static int lanes_for(int outs, int len) { return std::max(1, std::min(std::min(64, len), pow2_floor(256 / outs))); }
 
-static int passb_nb_host(int J) { return J == 1 ? LEARN_B_NB1 : (J == 2 ? 4 : 2); }
+static int passb_nb_host(int J) { return J == 1 ? kPassBChunk1 : (J == 2 ? 4 : 2); }
 static int passb_chunks(const Plan& pl) { return (pl.n + passb_nb_host(pl.j) - 1) / passb_nb_host(pl.j); }
 
 // pass-A row groups of the pruned path (R = 256 / W canonical rows each)

@@ -6,10 +6,9 @@ import pytest
 
 import oracle
 import synth
+from tolerances import code_tol
 
 pytestmark = pytest.mark.gpu
-
-CODE_TOL = 1e-4
 
 
 def T(x):
@@ -40,8 +39,7 @@ def test_batched_matches_oracle(lib):
     for im, zg in zip(imgs, z):
         ref = oracle.code(im[None], d, 1.0, 10.0, 12)["z"][0]
         dens.append(np.count_nonzero(ref) / ref.size)
-        tol = max(CODE_TOL, 3e-6 * np.abs(ref).max())
-        assert np.abs(zg.cpu().numpy() - ref).max() <= tol
+        assert np.abs(zg.cpu().numpy() - ref).max() <= code_tol(ref)
     assert np.mean(dens) > 0.005
 
 
@@ -89,7 +87,7 @@ def test_batched_autotune_table(lib, tmp_path, monkeypatch):
     z = pb.z_views(lib.code_batched(pb, dt, 1.0, 10.0, 8, graph=False))
     for im, zg in zip(imgs, z):
         ref = oracle.code(im[None], d, 1.0, 10.0, 8)["z"][0]
-        assert np.abs(zg.cpu().numpy() - ref).max() <= max(CODE_TOL, 3e-6 * np.abs(ref).max())
+        assert np.abs(zg.cpu().numpy() - ref).max() <= code_tol(ref)
 
 
 def test_batched_rejects_bad_tables(lib):

@@ -12,10 +12,9 @@ import pytest
 
 import oracle
 import synth
+from tolerances import CODE_TOL, code_tol
 
 pytestmark = pytest.mark.gpu
-
-CODE_TOL = 1e-4
 
 
 def T(x):
@@ -27,8 +26,6 @@ def N(t):
     return t.detach().cpu().numpy().astype(np.float64)
 
 
-def code_tol(z_ref):
-    return max(CODE_TOL, 3e-6 * float(np.abs(z_ref).max()))
 
 
 def case(seed, n, j, k, grid, fsupp, amp=10.0):

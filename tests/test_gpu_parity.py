@@ -1,11 +1,12 @@
 """GPU parity: the HIP library (through the C ABI) against the FP64 oracle on
 identical float32 inputs.
 
-Tolerances: codes within 1e-4 max-abs of the oracle after a fixed iteration
-count, objectives within 1e-5 relative.  Inputs whose codes exceed |z| ~ 30
-use a relative bound of 3e-6 * max|z| instead (float32 carries ~7 digits; see
-the test for the reasoning).  Every coding comparison also asserts a non-zero
-code density so that an all-zero result cannot pass.
+Tolerances (tests/tolerances.py): codes within 1e-4 max-abs of the oracle
+after a fixed iteration count, objectives within 1e-5 relative.  Inputs whose
+codes exceed |z| ~ 30 use 3e-6 * max|z| instead, and the chained alternation
+uses bounds tied to a measured float32 floor (tests/test_float32_floor.py).
+Every coding comparison also asserts a non-zero code density so that an
+all-zero result cannot pass.
 """
 import dataclasses
 
@@ -14,11 +15,10 @@ import pytest
 
 import oracle
 import synth
+from tolerances import (CHAIN_CODE_TOL, CHAIN_FILTER_TOL, CHAIN_MU_RTOL, CHAIN_OBJ_RTOL, CODE_TOL, OBJ_RTOL,
+                        code_tol)
 
 pytestmark = pytest.mark.gpu
-
-CODE_TOL = 1e-4
-OBJ_RTOL = 1e-5
 
 
 def T(x):
@@ -28,12 +28,6 @@ def T(x):
 
 def N(t):
     return t.detach().cpu().numpy().astype(np.float64)
-
-
-def code_tol(z_ref):
-    # 1e-4 absolute; for large-amplitude codes the float32 spectra carry a
-    # rounding floor ~ few ulp of max|z| accumulated over the iterations.
-    return max(CODE_TOL, 3e-6 * float(np.abs(z_ref).max()))
 
 
 def density(z):
@@ -224,15 +218,10 @@ def test_learn_dictionary_small_config(lib):
 
     Each half step is compared with the oracle started from the GPU's own
     state (identical float32 inputs): codes within 1e-4, filters within 1e-4.
-    The chained run (each side feeding itself) drifts further because
-    float32 errors in the learned filters feed the next coding step: its codes
-    are held to 1e-4 of max|z| (a relative bound) and its filters to 1e-3.
-    The objective the GPU reports for its final state matches the oracle's
-    objective of that same state (1e-5 relative), and the chained objective
-    sequences agree within what the two state bounds allow to first order,
-    sum|df/dz| dz + sum|df/dd| dd with the gradients at the oracle's final
-    state (errors only accumulate along the chain, so the final state's bound
-    covers the earlier half steps too)."""
+    The chained run (each side feeding itself) is compared with the oracle's
+    chained run at the bounds tied to the float32 floor of this workload
+    (tests/tolerances.py): codes, filters and multipliers at the end, the
+    objective after every half step."""
     import torch
     cfg = synth.CONFIGS["small"]
     b, d0 = synth.make_inputs(cfg)
@@ -247,24 +236,34 @@ def test_learn_dictionary_small_config(lib):
         ref = oracle.code(b, d_in, cfg.beta, cfg.rho, cfg.t_in, z0=z_in, theta0=th_in)
         z, theta, _, _ = lib.code(bt, d, cfg.beta, cfg.rho, cfg.t_in, z=z, theta=theta, want_theta=True)
         assert density(ref["z"]) > 0.01
-        assert np.abs(N(z) - ref["z"]).max() <= CODE_TOL, step
+        ez = np.abs(N(z) - ref["z"]).max()
         zf = N(z).astype(np.float32)
         mu_in = N(mu).astype(np.float32)
         g_in = None if gamma is None else N(gamma).astype(np.float32)
         d_ref, mu_ref, _ = oracle.learn(b, zf, cfg.fsupp, mu_in, g_in, cfg.learn_inner, cfg.learn_cg)
         d, mu, gamma = lib.learn(bt, z, cfg.fsupp, mu, gamma, cfg.learn_inner, cfg.learn_cg)
-        assert np.abs(N(d) - d_ref).max() <= 1e-4, step
-        np.testing.assert_allclose(N(mu), mu_ref, rtol=1e-4)
+        ed = np.abs(N(d) - d_ref).max()
+        emu = np.abs(N(mu) / mu_ref - 1).max()
+        print("half steps of outer step %d from the GPU's state: codes %.2e, filters %.2e, mu %.2e"
+              % (step, ez, ed, emu))
+        assert ez <= CODE_TOL, step
+        assert ed <= 1e-4, step
+        assert emu <= 1e-4, step
 
     ref = oracle.learn_dictionary(b, d0, cfg.beta, cfg.rho, cfg.t_in, cfg.t_out, cfg.learn_inner, cfg.learn_cg)
     out = lib.learn_dictionary(bt, T(d0), cfg.beta, cfg.rho, cfg.t_in, cfg.t_out, cfg.learn_inner, cfg.learn_cg)
-    zmax = np.abs(ref["z"]).max()
-    dz_tol, dd_tol = 1e-4 * zmax, 1e-3
-    assert np.abs(N(out["z"]) - ref["z"]).max() <= dz_tol
-    assert np.abs(N(out["d"]) - ref["d"]).max() <= dd_tol
-    f_end, gz, gd, _ = oracle.objective_grad(b, ref["d"], ref["z"], cfg.beta)
-    assert abs(f_end - ref["objectives"][-1]) <= 1e-9 * f_end
+    ez = np.abs(N(out["z"]) - ref["z"]).max()
+    ed = np.abs(N(out["d"]) - ref["d"]).max()
+    emu = np.abs(N(out["mu"]) / ref["mu"] - 1).max()
+    eobj = np.abs(N(out["objectives"]) / np.asarray(ref["objectives"]) - 1)
+    print("chained run: codes %.2e (bound %.1e), filters %.2e (%.1e), mu %.2e (%.1e), objective per half step %s (%.1e)"
+          % (ez, CHAIN_CODE_TOL, ed, CHAIN_FILTER_TOL, emu, CHAIN_MU_RTOL,
+             " ".join("%.2e" % e for e in eobj), CHAIN_OBJ_RTOL))
+    assert density(ref["z"]) > 0.01
+    assert ez <= CHAIN_CODE_TOL
+    assert ed <= CHAIN_FILTER_TOL
+    assert emu <= CHAIN_MU_RTOL
+    assert eobj.max() <= CHAIN_OBJ_RTOL
+    # the GPU's objective of its own final state against the oracle's objective of that state
     _, f_own = oracle.objective(b, N(out["d"]), N(out["z"]), cfg.beta)
     assert abs(N(out["objectives"])[-1] - f_own) <= OBJ_RTOL * f_own
-    obj_tol = np.abs(gz).sum() * dz_tol + np.abs(gd).sum() * dd_tol
-    assert np.abs(N(out["objectives"]) - np.asarray(ref["objectives"])).max() <= obj_tol

@@ -389,6 +389,66 @@ def test_alternation_monotone_with_tight_inner_solves():
     assert objs[-1] < objs[0]
 
 
+def _alg1_by_hand(b, d0, beta, rho, t_in, t_out, inner, cg, cold=False, reset_mu=False, reset_rho=False):
+    """Alg. 1 written out from its description: z, theta start at zero, mu at
+    1, gamma at 0, rho at its initial value, all set once before the loop and
+    carried from one outer step to the next (coding warm-starts from the
+    previous codes and split variable, learning from the previous gamma and
+    multipliers).  The flags plant the mistakes the pin must catch."""
+    K = d0.shape[0]
+    d, z, th, mu, gamma = np.asarray(d0, float), None, None, np.ones(K), None
+    rho_v = np.full(b.shape[0], float(rho))
+    objs = []
+    for _ in range(t_out):
+        if cold:
+            z = th = None
+        if reset_mu:
+            mu, gamma = np.ones(K), None
+        if reset_rho:
+            rho_v = np.full(b.shape[0], float(rho))
+        out = oracle.code(b, d, beta, rho_v, t_in, z0=z, theta0=th, adaptive=True)
+        z, th, rho_v = out["z"], out["theta"], out["rho"][-1]
+        objs.append(oracle.objective(b, d, z, beta)[1])
+        d, mu, gamma = oracle.learn(b, z, d0.shape[2:], mu, gamma, inner, cg)
+        objs.append(oracle.objective(b, d, z, beta)[1])
+    return d, z, th, mu, gamma, objs
+
+
+def test_learn_dictionary_is_alg1_with_carried_state():
+    """learn_dictionary equals Alg. 1 written out by hand (3 outer steps,
+    adaptive rho) bit for bit, and each planted mistake -- a cold restart of
+    z and theta, a reset of mu and gamma, a reset of rho -- moves the result
+    far beyond rounding, so any of them inside learn_dictionary fails here."""
+    grid, fs, K = (16, 16), (5, 5), 4
+    rng = np.random.default_rng(12)
+    b = np.stack([synth.contrast_normalize(synth.one_over_f(rng, grid))[None] * 10 for _ in range(2)])
+    d0 = rand_filters(K, 1, fs, rng)
+    out = oracle.learn_dictionary(b, d0, 1.0, 10.0, 6, 3, 3, 4, adaptive=True)
+    d, z, th, mu, gamma, objs = _alg1_by_hand(b, d0, 1.0, 10.0, 6, 3, 3, 4)
+    assert np.count_nonzero(z) / z.size > 0.01
+    for got, want in ((out["d"], d), (out["z"], z), (out["theta"], th), (out["mu"], mu), (out["gamma"], gamma)):
+        assert np.array_equal(got, want)
+    assert out["objectives"] == objs
+    for mistake in ("cold", "reset_mu", "reset_rho"):
+        bad = _alg1_by_hand(b, d0, 1.0, 10.0, 6, 3, 3, 4, **{mistake: True})
+        assert np.abs(bad[0] - d).max() > 1e-6 or np.abs(bad[1] - z).max() > 1e-6, mistake
+
+
+def test_learn_dictionary_monotone_with_tight_inner_solves():
+    """P12 through learn_dictionary itself: with tight inner solves (1500
+    coding iterations, 60 multiplier updates of 150 CG steps) and the final
+    projection into the unit ball, the objective does not increase across
+    half steps."""
+    grid, fs, K = (16, 16), (5, 5), 4
+    rng = np.random.default_rng(21)
+    b = rng.standard_normal((2, 1) + grid) * 3
+    d0 = rand_filters(K, 1, fs, rng)
+    out = oracle.learn_dictionary(b, d0, 0.5, 1.0, 1500, 3, 60, 150)
+    objs = out["objectives"]
+    assert all(o2 <= o1 * (1 + 1e-7) for o1, o2 in zip(objs, objs[1:])), objs
+    assert objs[-1] < objs[0]
+
+
 def test_learn_dictionary_runs_and_logs():
     grid, fs, K = (12, 12), (3, 3), 3
     b = RNG.standard_normal((2, 1) + grid) * 3
