@@ -53,6 +53,7 @@ extern "C" {
 #define CSC_EUNSUPPORTED (-3) /* geometry outside the supported set */
 #define CSC_EHIP (-4)         /* a HIP runtime call failed */
 #define CSC_ENONFINITE (-5)   /* NaN or infinity found (csc_check_finite's flag, raised by the binding) */
+#define CSC_ESCRATCH (-6)     /* csc_code_noalloc: the problem needs more than the static scratch holds */
 
 /* Workspace query operations. */
 #define CSC_OP_CODE 1
@@ -117,6 +118,28 @@ size_t csc_workspace_bytes(const csc_shape* shape, int op, unsigned flags);
 int csc_code(const csc_shape* shape, const float* b, const float* d, float beta,
              float* rho, int iters, unsigned flags, float* z, float* theta,
              double* resid, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * csc_code for callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid allocation).  Same
+ * operation, arguments, flags (except CSC_USE_GRAPH) and results as csc_code,
+ * bit for bit, but without a workspace argument: the scratch comes from one
+ * static device array of CSC_NOALLOC_SCRATCH_BYTES bytes that the library
+ * holds on every device it runs on until the process ends (its address is
+ * looked up once per device, on the first call there).  The call allocates
+ * nothing and frees nothing.
+ *   Every call on one device shares that device's array and leaves its
+ *   contents behind: two calls that overlap on one device (different
+ *   streams, or different host threads without ordering) race and give
+ *   wrong results.  Order them on one stream.
+ *   Errors: as csc_code; CSC_ESCRATCH when csc_workspace_bytes(shape,
+ *           CSC_OP_CODE, flags) exceeds CSC_NOALLOC_SCRATCH_BYTES (nothing
+ *           is enqueued); CSC_EINVAL for CSC_USE_GRAPH.
+ */
+#define CSC_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int csc_code_noalloc(const csc_shape* shape, const float* b, const float* d, float beta,
+                     float* rho, int iters, unsigned flags, float* z, float* theta,
+                     double* resid, void* stream);
 
 /*
  * csc_code with a stopping rule (the convergence-driven mode; the paper runs

@@ -28,7 +28,8 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 _LIB_NAME = "libdualcsc.so"
 
 ABI_VERSION = 2
-OK, EINVAL, EWORKSPACE, EUNSUPPORTED, EHIP, ENONFINITE = 0, -1, -2, -3, -4, -5
+OK, EINVAL, EWORKSPACE, EUNSUPPORTED, EHIP, ENONFINITE, ESCRATCH = 0, -1, -2, -3, -4, -5, -6
+NOALLOC_SCRATCH_BYTES = 64 << 20
 OP_CODE, OP_LEARN, OP_OBJECTIVE = 1, 2, 3
 ADAPTIVE_RHO, Z_ZERO, THETA_ZERO, GAMMA_ZERO, USE_GRAPH = 0x1, 0x2, 0x4, 0x8, 0x10
 
@@ -102,6 +103,8 @@ def load() -> ctypes.CDLL:
     lib.csc_workspace_bytes.argtypes = [sp, i32, u32]
     lib.csc_code.restype = i32
     lib.csc_code.argtypes = [sp, vp, vp, f32, vp, i32, u32, vp, vp, vp, vp, sz, vp]
+    lib.csc_code_noalloc.restype = i32
+    lib.csc_code_noalloc.argtypes = [sp, vp, vp, f32, vp, i32, u32, vp, vp, vp, vp]
     lib.csc_learn.restype = i32
     lib.csc_learn.argtypes = [sp, vp, vp, vp, vp, vp, i32, i32, u32, vp, sz, vp]
     lib.csc_code_tol.restype = i32

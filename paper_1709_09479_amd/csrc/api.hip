@@ -178,6 +178,31 @@ bool TraceScope::events(hipEvent_t* start, hipEvent_t* stop) const {
 
 }  // namespace dcsc
 
+// Scratch of csc_code_noalloc: one static array on every device the library
+// runs on.  In host code `scratch` names a host-side stand-in, so the array's
+// device address is looked up once per device (with that device current) and
+// only that address is ever handed to kernels.
+__device__ __align__(256) char scratch[CSC_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_address(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return CSC_EHIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return CSC_EHIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return CSC_OK;
+}
+}  // namespace
+
 using namespace dcsc;
 
 extern "C" {
@@ -239,6 +264,7 @@ const char* csc_strerror(int code) {
     case CSC_EUNSUPPORTED: return "geometry not supported";
     case CSC_EHIP: return "HIP runtime error";
     case CSC_ENONFINITE: return "non-finite value (NaN or infinity) in a result";
+    case CSC_ESCRATCH: return "problem needs more scratch than csc_code_noalloc's static array holds (64 MiB)";
     default: return "unknown error";
   }
 }
@@ -290,6 +316,19 @@ int csc_code(const csc_shape* shape, const float* b, const float* d, float beta,
                                       c->ws, c->st);
                     },
                     &c);
+}
+
+int csc_code_noalloc(const csc_shape* shape, const float* b, const float* d, float beta, float* rho, int iters,
+                     unsigned flags, float* z, float* theta, double* resid, void* stream) {
+  Plan pl;
+  int rc = make_plan(shape, &pl);
+  if (rc != CSC_OK) return rc;
+  if (!b || !d || !rho || !z || iters < 0 || !(beta >= 0.0f)) return CSC_EINVAL;
+  if (flags & ~(CSC_ADAPTIVE_RHO | CSC_Z_ZERO | CSC_THETA_ZERO)) return CSC_EINVAL;
+  if (run_code_ws(pl) > CSC_NOALLOC_SCRATCH_BYTES) return CSC_ESCRATCH;
+  void* ws = nullptr;
+  if ((rc = scratch_address(&ws)) != CSC_OK) return rc;
+  return run_code(pl, b, d, beta, rho, iters, flags, z, theta, resid, ws, static_cast<hipStream_t>(stream));
 }
 
 int csc_learn(const csc_shape* shape, const float* b, const float* z, float* d, float* mu, float* gamma,

@@ -185,3 +185,21 @@ def test_check_finite_argument_errors():
     assert lib.csc_check_finite(FAKE, -1, FAKE, None) == dc.EINVAL
     assert lib.csc_check_finite(FAKE, 4, None, None) == dc.EINVAL
     assert b"non-finite" in lib.csc_strerror(dc.ENONFINITE)
+
+
+def test_noalloc_rejects_before_enqueue():
+    """csc_code_noalloc validates like csc_code and refuses a problem whose
+    scratch exceeds its static array before touching the device."""
+    lib = dc.load()
+    big = shape(n=16, k=100, grid=(256, 256))
+    assert lib.csc_workspace_bytes(ctypes.byref(big), dc.OP_CODE, 0) > dc.NOALLOC_SCRATCH_BYTES
+    call = lambda s, **kw: lib.csc_code_noalloc(
+        ctypes.byref(s), kw.get("b", FAKE), FAKE, kw.get("beta", 1.0), FAKE, kw.get("iters", 5),
+        kw.get("flags", 0), FAKE, None, None, None)
+    assert call(big) == dc.ESCRATCH
+    assert call(shape(), b=None) == dc.EINVAL
+    assert call(shape(), beta=-1.0) == dc.EINVAL
+    assert call(shape(), iters=-1) == dc.EINVAL
+    assert call(shape(), flags=dc.USE_GRAPH) == dc.EINVAL
+    assert call(shape(grid=(60, 64))) == dc.EINVAL
+    assert b"64 MiB" in lib.csc_strerror(dc.ESCRATCH)
