@@ -130,3 +130,81 @@ def learn_dictionary(b, d0, beta, rho, t_in, t_out, inner_iters, cg_iters):
         d, mu, gamma = learn(b, z, d.shape[2:], mu, gamma, inner_iters, cg_iters)
         states.append((z, d))
     return d, z, mu, states
+
+
+def code_loss_grad(b, d, beta, rho, iters):
+    """The oracle's ``code_loss_grad`` (the unrolled coding solve from zero
+    and its hand-written reverse pass) with every array in float32 /
+    complex64; the loss and the beta gradient are summed in float64."""
+    b = np.asarray(b, F32)
+    d = np.asarray(d, F32)
+    N, J = b.shape[:2]
+    grid = b.shape[2:]
+    nd = len(grid)
+    ax = _axes(nd)
+    K = d.shape[0]
+    fsupp = d.shape[2:]
+    dh = np.swapaxes(sfft.fftn(_place(d, fsupp, grid), axes=ax), 0, 1).astype(C64)   # [J][K]
+    G = np.einsum("jk...,lk...->...jl", dh, np.conj(dh)).astype(C64)
+    r = F32(rho)
+
+    def Dop(w):
+        return sfft.ifftn(np.einsum("jk...,nk...->nj...", dh, sfft.fftn(w, axes=ax)), axes=ax).real.astype(F32)
+
+    def DTop(l):
+        return sfft.ifftn(np.einsum("jk...,nj...->nk...", np.conj(dh), sfft.fftn(l, axes=ax)), axes=ax).real.astype(F32)
+
+    def Pop(s):
+        sh = sfft.fftn(s, axes=ax)
+        if J == 1:
+            out = sh / (G[..., 0, 0].real + 1 / r)
+        else:
+            A = G[None] + (1 / r) * np.eye(J, dtype=C64)
+            out = np.moveaxis(np.linalg.solve(A, np.moveaxis(sh, 1, -1)[..., None])[..., 0], -1, 1)
+        return sfft.ifftn(out, axes=ax).real.astype(F32)
+
+    def corr_crop(a, bsig):
+        c = sfft.ifftn(np.einsum("j...,k...->kj...", sfft.fftn(a, axes=ax), np.conj(sfft.fftn(bsig, axes=ax))),
+                       axes=ax).real.astype(F32)
+        return _crop(c, fsupp)
+
+    z = np.zeros((N, K) + grid, F32)
+    th = np.zeros((N, K) + grid, F32)
+    tape = []
+    for _ in range(iters):
+        w = (th + z / r).astype(F32)
+        s = (Dop(w) - b / r).astype(F32)
+        lam = Pop(s)
+        v = DTop(lam)
+        u = (v - z / r).astype(F32)
+        th_new = np.clip(u, -beta, beta).astype(F32)
+        z_new = (z + r * (th_new - v)).astype(F32)
+        tape.append((w, s, lam, v, u))
+        z, th = z_new, th_new
+    res = Dop(z) - b
+    loss = 0.5 * float((res.astype(np.float64) ** 2).sum()) + beta * float(np.abs(z.astype(np.float64)).sum())
+    gd = np.zeros((K, J) + tuple(fsupp), F32)
+    gbeta = float(np.abs(z.astype(np.float64)).sum())
+    for n in range(N):
+        gd += corr_crop(res[n], z[n])
+    zbar = (DTop(res) + beta * np.sign(z)).astype(F32)
+    thbar = np.zeros_like(zbar)
+    for (w, s, lam, v, u) in reversed(tape):
+        tbar_tot = (thbar + r * zbar).astype(F32)
+        vbar = (-r * zbar).astype(F32)
+        zbar_prev = zbar.copy()
+        inside = np.abs(u) < beta
+        outside = np.abs(u) > beta
+        ubar = (tbar_tot * inside).astype(F32)
+        gbeta += float((tbar_tot.astype(np.float64) * np.sign(u) * outside).sum())
+        vbar = (vbar + ubar).astype(F32)
+        zbar_prev = (zbar_prev - ubar / r).astype(F32)
+        lbar = Dop(vbar)
+        sbar = Pop(lbar)
+        wbar = DTop(sbar)
+        for n in range(N):
+            gd += corr_crop(lam[n], vbar[n] - wbar[n])
+            gd += corr_crop(sbar[n], w[n] - v[n])
+        thbar = wbar
+        zbar = (zbar_prev + wbar / r).astype(F32)
+    return loss, gd.astype(np.float64), gbeta

@@ -87,3 +87,23 @@ def test_emulation_is_the_oracle_in_float32():
     d32, mu32, g32 = f32.learn(b, ref["z"].astype(np.float32), (5, 5), np.ones(3), None, 3, 6)
     assert np.abs(d32 - d_ref).max() <= 1e-4
     np.testing.assert_allclose(mu32, mu_ref, rtol=1e-4)
+
+
+@pytest.mark.parametrize("grid,k", [((256, 256), 4), ((128, 256), 6)])
+def test_unrolled_gradient_floor(grid, k):
+    """The filter gradient of the unrolled solve (2 images, 10 iterations,
+    beta 1, rho 10, images times 30) in float32 against float64: on grids
+    transformed axis by axis the float32 floor is above 1e-4 of max|dL/dd|
+    (so that gradients are compared at 1e-3 of their maximum, not 1e-4),
+    while the beta gradient stays near 1e-6."""
+    rng = np.random.default_rng(21)
+    b = np.stack([synth.contrast_normalize(synth.one_over_f(rng, grid))[None] * 30 for _ in range(2)])
+    b = b.astype(np.float32)
+    d = synth.unit_filters(k, 1, (11, 11), 5)
+    _, gdr, gbr = oracle.code_loss_grad(b, d, 1.0, 10.0, 10)
+    _, gd, gb = f32.code_loss_grad(b, d, 1.0, 10.0, 10)
+    ed = float(np.abs(gd - gdr).max() / np.abs(gdr).max())
+    eb = abs(gb - gbr) / abs(gbr)
+    print("grid %s K=%d: float32 floor of the filter gradient %.2e of max, beta %.2e" % (grid, k, ed, eb))
+    assert 5e-5 < ed < 1e-3, ed
+    assert eb < 1e-5, eb

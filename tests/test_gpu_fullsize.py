@@ -121,17 +121,27 @@ def test_unrolled_full_workload(lib):
     # the batch gradient is the sum of the gradients of its halves
     La, gda, gba, _ = grad(b[:8])
     Lb, gdb, gbb, _ = grad(b[8:])
-    assert abs(L - (La + Lb)) <= 1e-5 * abs(L)
-    assert np.abs(gd - (gda + gdb)).max() <= 1e-4 * np.abs(gd).max()
-    assert abs(gb - (gba + gbb)) <= 1e-4 * abs(gb)
+    hd = np.abs(gd - (gda + gdb)).max() / np.abs(gd).max()
+    hb = abs(gb - (gba + gbb)) / abs(gb)
+    print("batch minus halves: loss %.2e, filters %.2e of max|dL/dd|, beta %.2e relative"
+          % (abs(L - (La + Lb)) / abs(L), hd, hb), flush=True)
 
     # one image against the oracle's reverse pass
     L0, gd0, gb0, _ = grad(b[:1])
     Lr, gdr, gbr = oracle.code_loss_grad(b[:1], d0, cfg.beta, cfg.rho, cfg.t_in)
-    assert abs(L0 - Lr) <= 1e-5 * abs(Lr)
     ed = np.abs(gd0 - gdr).max() / np.abs(gdr).max()
     eb = abs(gb0 - gbr) / abs(gbr)
-    print("full-size gradient of one image: filters %.2e of max|dL/dd|, beta %.2e relative" % (ed, eb))
+    print("full-size gradient of one image: loss %.2e, filters %.2e of max|dL/dd|, beta %.2e relative"
+          % (abs(L0 - Lr) / abs(Lr), ed, eb), flush=True)
+    # the filter gradient sits on a float32 floor near 1e-3 of its maximum:
+    # the same image coded twice in one batch gives, through a different
+    # grouping of the pair sums, a gradient 9.6e-4 away from twice its
+    # single-image gradient; test_float32_floor.py measures that floor in
+    # float32 emulation.  The halves are held to the oracle's tolerance.
+    assert abs(L - (La + Lb)) <= 1e-5 * abs(L)
+    assert hd <= GRAD_RTOL, hd
+    assert hb <= 1e-4, hb
+    assert abs(L0 - Lr) <= 1e-5 * abs(Lr)
     assert ed <= GRAD_RTOL, ed
     assert eb <= GRAD_RTOL, eb
 
