@@ -70,6 +70,16 @@ extern "C" {
                                  identical arguments (pointers, sizes, scalars, stream);
                                  ignored on the NULL stream.  Buffer contents may change
                                  between replays, pointers may not. */
+#define CSC_NUCLEAR 0x20u     /* csc_code, csc_code_tol, csc_code_noalloc, csc_objective_reg,
+                                 csc_workspace_bytes: the regulariser is beta sum_k ||z_k||_*,
+                                 the nuclear norm of each code map as an H x W matrix, in place
+                                 of the l1 norm (Sec. 5: low-rank maps).  The projection of
+                                 eq:Inference_solution becomes the projection onto the
+                                 beta-ball of the spectral norm, i.e. the z step is singular
+                                 value thresholding of z - rho D^T lambda at rho beta, map by
+                                 map.  2-D grids with 8 <= H, W <= 128 (CSC_EUNSUPPORTED
+                                 otherwise); theta, resid, adaptive rho and the stopping rule
+                                 keep their meaning. */
 
 typedef struct csc_shape {
   int32_t abi_version; /* must equal CSC_ABI_VERSION */
@@ -81,8 +91,9 @@ typedef struct csc_shape {
   int32_t fsupp[3];    /* filter support, first ndim entries used */
 } csc_shape;
 
-/* Bytes of workspace needed by `op` (CSC_OP_*) for `shape` and `flags`;
- * 0 if the shape is invalid. */
+/* Bytes of workspace needed by `op` (CSC_OP_*) for `shape` and `flags`
+ * (CSC_NUCLEAR changes the coding and objective workspaces; other flags do
+ * not matter); 0 if the shape is invalid or unsupported. */
 size_t csc_workspace_bytes(const csc_shape* shape, int op, unsigned flags);
 
 /*
@@ -111,9 +122,11 @@ size_t csc_workspace_bytes(const csc_shape* shape, int op, unsigned flags);
  *          CSC_THETA_ZERO the input contents are ignored.
  *   resid  NULL or [iters][N][3] float64: r_pri = ||theta' - D^T lambda'||,
  *          r_dual = rho ||D (theta' - theta)||, and the rho used.
- *   flags  CSC_ADAPTIVE_RHO, CSC_Z_ZERO, CSC_THETA_ZERO, CSC_USE_GRAPH.
+ *   flags  CSC_ADAPTIVE_RHO, CSC_Z_ZERO, CSC_THETA_ZERO, CSC_USE_GRAPH,
+ *          CSC_NUCLEAR.
  *   Errors: CSC_EINVAL for a bad shape, beta < 0, iters < 0, NULL b/d/rho/z,
- *           unknown flags; CSC_EWORKSPACE; CSC_EHIP.
+ *           unknown flags; CSC_EUNSUPPORTED (CSC_NUCLEAR on a grid it does
+ *           not cover); CSC_EWORKSPACE; CSC_EHIP.
  */
 int csc_code(const csc_shape* shape, const float* b, const float* d, float beta,
              float* rho, int iters, unsigned flags, float* z, float* theta,
@@ -156,7 +169,7 @@ int csc_code_noalloc(const csc_shape* shape, const float* b, const float* d, flo
  *   resid       if given, rows [0, iterations done) are written.
  *   iters_done  NULL or a device int: the number of iterations carried out
  *               (max_iters if the rule never fired).
- *   flags       CSC_ADAPTIVE_RHO, CSC_Z_ZERO, CSC_THETA_ZERO.
+ *   flags       CSC_ADAPTIVE_RHO, CSC_Z_ZERO, CSC_THETA_ZERO, CSC_NUCLEAR.
  *   Errors: as csc_code, and CSC_EINVAL for tol <= 0 or not finite.
  */
 int csc_code_tol(const csc_shape* shape, const float* b, const float* d, float beta,
@@ -214,6 +227,18 @@ int csc_learn_tol(const csc_shape* shape, const float* b, const float* z, float*
 int csc_objective(const csc_shape* shape, const float* b, const float* d,
                   const float* z, float beta, double* out, void* ws,
                   size_t ws_bytes, void* stream);
+
+/*
+ * csc_objective with the regulariser chosen by `flags`: 0 (the l1 norm, as
+ * csc_objective) or CSC_NUCLEAR (beta sum_k ||z_k||_*, the nuclear norm of
+ * each map, its singular values found by the Jacobi method in float64).
+ * Arguments, workspace (csc_workspace_bytes(shape, CSC_OP_OBJECTIVE, flags))
+ * and errors as csc_objective, plus CSC_EINVAL for other flags and
+ * CSC_EUNSUPPORTED as for csc_code.
+ */
+int csc_objective_reg(const csc_shape* shape, const float* b, const float* d,
+                      const float* z, float beta, unsigned flags, double* out,
+                      void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Differentiable coding (grayscale, J = 1; J > 1 gives CSC_EUNSUPPORTED).

@@ -14,6 +14,10 @@ from .csc import (  # noqa: F401
     filter_spectra,
     reconstruct,
     objective,
+    regularizer,
+    nuclear_norm,
+    project_spectral_ball,
+    svt,
     objective_grad,
     soft,
     code,

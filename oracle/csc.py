@@ -76,21 +76,66 @@ def reconstruct(d, z, grid=None):
     return _ifft_real(np.einsum("jk...,nk...->nj...", dh, zh), nd)
 
 
-def objective(b, d, z, beta):
+def nuclear_norm(z):
+    """Sum of the singular values of every code map taken as an H x W matrix
+    (the trailing two axes).  z [..][H][W] -> [..]."""
+    return np.linalg.svd(np.asarray(z, _f64), compute_uv=False).sum(axis=-1)
+
+
+def regularizer(z, reg="l1"):
+    """The sparsity term per image without its weight: sum_k ||z_k||_1
+    (eq:CSC), or with reg="nuclear" sum_k ||z_k||_* (the nuclear norm of
+    each 2-D map, the low-rank regulariser of Sec. 5).  z [N][K][..] -> [N]."""
+    z = np.asarray(z, _f64)
+    if reg == "l1":
+        return np.abs(z).sum(axis=tuple(range(1, z.ndim)))
+    if reg == "nuclear":
+        return nuclear_norm(z).sum(axis=1)
+    raise ValueError(reg)
+
+
+def objective(b, d, z, beta, reg="l1"):
     """eq:CSC: 1/2 ||x - sum_k d_k * z_k||^2 + beta sum_k ||z_k||_1, summed
-    over channels; returns (per-image values [N], total)."""
+    over channels (with reg="nuclear" the l1 norm becomes the nuclear norm of
+    each map); returns (per-image values [N], total)."""
     b = np.asarray(b, _f64)
     z = np.asarray(z, _f64)
-    nd = np.asarray(d).ndim - 2
     res = b - reconstruct(d, z)
     red = tuple(range(1, b.ndim))
-    per = 0.5 * (res * res).sum(axis=red) + beta * np.abs(z).sum(axis=tuple(range(1, z.ndim)))
+    per = 0.5 * (res * res).sum(axis=red) + beta * regularizer(z, reg)
     return per, float(per.sum())
 
 
 def soft(u, t):
     """Soft threshold sign(u) max(|u| - t, 0)."""
     return np.sign(u) * np.maximum(np.abs(u) - t, 0.0)
+
+
+def project_spectral_ball(u, beta):
+    """Projection onto {theta : ||theta_k||_2 <= beta for every map}, the
+    unit ball of the spectral norm (the dual norm of the nuclear norm) scaled
+    by beta: with u_k = U diag(s) V^T, the projection is U diag(min(s, beta))
+    V^T, map by map over the trailing two axes."""
+    U, sv, Vt = np.linalg.svd(np.asarray(u, _f64), full_matrices=False)
+    return (U * np.minimum(sv, beta)[..., None, :]) @ Vt
+
+
+def svt(u, t):
+    """Singular value thresholding U diag(max(s - t, 0)) V^T per map: the
+    proximal operator of t ||.||_* (the nuclear-norm analogue of soft)."""
+    U, sv, Vt = np.linalg.svd(np.asarray(u, _f64), full_matrices=False)
+    return (U * np.maximum(sv - t, 0.0)[..., None, :]) @ Vt
+
+
+def project_dual_ball(u, beta, reg="l1"):
+    """Pi_C of eq:Inference_solution: C is the beta-ball of the dual norm of
+    the regulariser: the l-infinity ball for l1 (a clip), the spectral-norm
+    ball for the nuclear norm."""
+    if reg == "l1":
+        return np.clip(u, -beta, beta)
+    if reg == "nuclear":
+        return project_spectral_ball(u, beta)
+    raise ValueError(reg)
 
 
 def _gram(dh):
@@ -124,7 +169,7 @@ def _adapt_rho(rho, r_pri, r_dual, mu_b, tau_b):
 
 
 def code(b, d, beta, rho, iters, z0=None, theta0=None, adaptive=False,
-         rho_schedule=None, mu_b=10.0, tau_b=2.0, tol=None):
+         rho_schedule=None, mu_b=10.0, tau_b=2.0, tol=None, reg="l1"):
     """Coding subproblem by ADMM on its dual (eq:Inference_Dual,
     eq:Inference_ADMM), literal updates of eq:Inference_solution in the
     Fourier domain, run for a fixed number of iterations per image (the coding
@@ -143,12 +188,16 @@ def code(b, d, beta, rho, iters, z0=None, theta0=None, adaptive=False,
     every image has r_pri <= tol sqrt(K D) and r_dual <= tol sqrt(J D), i.e.
     both RMS residuals at most tol (Boyd et al. 2011, Sec. 3.3.1, with zero
     relative tolerance); ``iters`` is then the largest count.
+    ``reg="nuclear"`` replaces the l1 term by beta sum_k ||z_k||_* (Sec. 5:
+    low-rank maps); C is then the spectral-norm ball (2-D grids only).
     Returns dict(z, theta, resid [done][N][2], rho [done+1][N], iters = done).
     """
     b = np.asarray(b, _f64)
     N, J = b.shape[:2]
     grid = b.shape[2:]
     nd = len(grid)
+    if reg == "nuclear" and nd != 2:
+        raise ValueError("the nuclear norm is defined on 2-D maps")
     d = np.asarray(d, _f64)
     K = d.shape[0]
     dh = filter_spectra(d, grid)                     # [J][K][*grid]
@@ -169,7 +218,7 @@ def code(b, d, beta, rho, iters, z0=None, theta0=None, adaptive=False,
         rhs = np.einsum("jk...,nk...->nj...", dh, wh) - xh / r       # D theta + D z/rho - x/rho
         lam = _dual_solve(G, rhs, rho_v)                             # [N][J][*grid]
         v = _ifft_real(np.einsum("jk...,nj...->nk...", np.conj(dh), lam), nd)  # D^T lam
-        th_new = np.clip(v - z / r, -beta, beta)                     # projection onto C
+        th_new = project_dual_ball(v - z / r, beta, reg)              # projection onto C
         z_new = z + r * (th_new - v)
         red = tuple(range(1, z.ndim))
         r_pri = np.sqrt(((th_new - v) ** 2).sum(axis=red))
@@ -338,7 +387,7 @@ def learn(b, z, fsupp, mu, gamma=None, inner_iters=10, cg_iters=10, cg_tol=None,
 
 
 def learn_dictionary(b, d0, beta, rho, t_in, t_out, inner_iters=10, cg_iters=10,
-                     adaptive=False, tau=None, tol=None, cg_tol=None):
+                     adaptive=False, tau=None, tol=None, cg_tol=None, reg="l1"):
     """Alg. 1 (coordinate descent between the two dual subproblems): z and
     theta start at zero and are carried (warm) into every later coding call,
     d starts from d0, mu at 1 and gamma at 0; each outer step codes, then
@@ -347,7 +396,8 @@ def learn_dictionary(b, d0, beta, rho, t_in, t_out, inner_iters=10, cg_iters=10,
     relative to the previous step's (Sec. 4); ``tol`` and ``cg_tol`` are the
     stopping rules of code() and learn().  Returns dict(d, z, theta, mu,
     gamma, objectives, steps) where objectives lists f(d, z) after each half
-    step and steps is the number of outer steps taken."""
+    step and steps is the number of outer steps taken.  ``reg`` selects the
+    regulariser of the coding step and the objective (see code)."""
     b = np.asarray(b, _f64)
     d = np.asarray(d0, _f64)
     N = b.shape[0]
@@ -360,13 +410,13 @@ def learn_dictionary(b, d0, beta, rho, t_in, t_out, inner_iters=10, cg_iters=10,
     objs = []
     steps = 0
     for _ in range(t_out):
-        out = code(b, d, beta, rho_v, t_in, z, theta, adaptive=adaptive, tol=tol)
+        out = code(b, d, beta, rho_v, t_in, z, theta, adaptive=adaptive, tol=tol, reg=reg)
         z, theta = out["z"], out["theta"]
         if adaptive:
             rho_v = out["rho"][-1]
-        objs.append(objective(b, d, z, beta)[1])
+        objs.append(objective(b, d, z, beta, reg)[1])
         d, mu, gamma = learn(b, z, fsupp, mu, gamma, inner_iters, cg_iters, cg_tol)
-        objs.append(objective(b, d, z, beta)[1])
+        objs.append(objective(b, d, z, beta, reg)[1])
         steps += 1
         if tau is not None and len(objs) >= 4 and abs(objs[-1] - objs[-3]) <= tau * abs(objs[-3]):
             break

@@ -31,7 +31,14 @@ ABI_VERSION = 2
 OK, EINVAL, EWORKSPACE, EUNSUPPORTED, EHIP, ENONFINITE, ESCRATCH = 0, -1, -2, -3, -4, -5, -6
 NOALLOC_SCRATCH_BYTES = 64 << 20
 OP_CODE, OP_LEARN, OP_OBJECTIVE = 1, 2, 3
-ADAPTIVE_RHO, Z_ZERO, THETA_ZERO, GAMMA_ZERO, USE_GRAPH = 0x1, 0x2, 0x4, 0x8, 0x10
+ADAPTIVE_RHO, Z_ZERO, THETA_ZERO, GAMMA_ZERO, USE_GRAPH, NUCLEAR = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
+_REG_FLAGS = {"l1": 0, "nuclear": NUCLEAR}
+
+
+def _reg_flag(reg: str) -> int:
+    if reg not in _REG_FLAGS:
+        raise DualCSCError(EINVAL, "reg must be 'l1' or 'nuclear'")
+    return _REG_FLAGS[reg]
 
 
 class DualCSCError(RuntimeError):
@@ -113,6 +120,8 @@ def load() -> ctypes.CDLL:
     lib.csc_learn_tol.argtypes = [sp, vp, vp, vp, vp, vp, i32, i32, f32, u32, vp, vp, sz, vp]
     lib.csc_objective.restype = i32
     lib.csc_objective.argtypes = [sp, vp, vp, vp, f32, vp, vp, sz, vp]
+    lib.csc_objective_reg.restype = i32
+    lib.csc_objective_reg.argtypes = [sp, vp, vp, vp, f32, u32, vp, vp, sz, vp]
     lib.csc_trace_enable.restype = i32
     lib.csc_trace_enable.argtypes = [i32]
     lib.csc_check_finite.restype = i32
@@ -172,7 +181,7 @@ def _workspace(shape: Shape, op: int, flags: int, device):
     nbytes = load().csc_workspace_bytes(ctypes.byref(shape), op, flags)
     if nbytes == 0:
         _check(EINVAL)
-    key = (str(device), op)
+    key = (str(device), op, flags & NUCLEAR)
     buf = _WS.get(key)
     if buf is None or buf.numel() < nbytes + 256:
         buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
@@ -230,12 +239,13 @@ _SIDE_STREAM = None
 
 
 def code(b, d, beta: float, rho, iters: int, z=None, theta=None, adaptive: bool = False,
-         want_theta: bool = False, want_resid: bool = False, graph: bool = False):
+         want_theta: bool = False, want_resid: bool = False, graph: bool = False, reg: str = "l1"):
     """ADMM coding (eq:Inference_solution) for ``iters`` iterations.
 
     b [N][J][*grid], d [K][J][*fsupp]; rho: float or [N] tensor (updated in
     place when adaptive).  z / theta: warm starts (modified in place) or None
-    (start from zero).  Returns (z, theta or None, resid [iters][N][3] or None,
+    (start from zero).  reg: "l1" (eq:CSC) or "nuclear" (beta sum_k ||z_k||_*,
+    low-rank maps).  Returns (z, theta or None, resid [iters][N][3] or None,
     rho tensor)."""
     torch = _torch()
     lib = load()
@@ -244,7 +254,7 @@ def code(b, d, beta: float, rho, iters: int, z=None, theta=None, adaptive: bool 
     shape = _shape_of(b, d)
     N, K = b.shape[0], d.shape[0]
     dev = b.device
-    flags = ADAPTIVE_RHO if adaptive else 0
+    flags = (ADAPTIVE_RHO if adaptive else 0) | _reg_flag(reg)
     if z is None:
         z = torch.empty((N, K) + tuple(b.shape[2:]), dtype=torch.float32, device=dev)
         flags |= Z_ZERO
@@ -302,7 +312,7 @@ def learn(b, z, fsupp: Sequence[int], mu=None, gamma=None, inner_iters: int = 10
 
 
 def code_until(b, d, beta: float, rho, max_iters: int, tol: float, z=None, theta=None, adaptive: bool = False,
-               want_theta: bool = False, want_resid: bool = False):
+               want_theta: bool = False, want_resid: bool = False, reg: str = "l1"):
     """ADMM coding until every image's RMS primal and dual residuals are at
     most ``tol`` (at most ``max_iters`` iterations; the decision is taken on
     the device).  Returns (z, theta or None, resid [done][N][3] or None, rho
@@ -314,7 +324,7 @@ def code_until(b, d, beta: float, rho, max_iters: int, tol: float, z=None, theta
     shape = _shape_of(b, d)
     N, K = b.shape[0], d.shape[0]
     dev = b.device
-    flags = ADAPTIVE_RHO if adaptive else 0
+    flags = (ADAPTIVE_RHO if adaptive else 0) | _reg_flag(reg)
     if z is None:
         z = torch.empty((N, K) + tuple(b.shape[2:]), dtype=torch.float32, device=dev)
         flags |= Z_ZERO
@@ -368,18 +378,24 @@ def learn_until(b, z, fsupp: Sequence[int], mu=None, gamma=None, inner_iters: in
     return d, mu, gamma, [int(c) for c in counts.cpu()]
 
 
-def objective(b, d, z, beta: float):
-    """eq:CSC objective: returns a float64 tensor [N + 1] (per image, total)."""
+def objective(b, d, z, beta: float, reg: str = "l1"):
+    """eq:CSC objective (with reg="nuclear" the regulariser is the nuclear
+    norm of each map): returns a float64 tensor [N + 1] (per image, total)."""
     torch = _torch()
     lib = load()
     _need(b, "b")
     _need(d, "d")
     _need(z, "z")
     shape = _shape_of(b, d)
+    flags = _reg_flag(reg)
     out = torch.empty(b.shape[0] + 1, dtype=torch.float64, device=b.device)
-    ws, nbytes = _workspace(shape, OP_OBJECTIVE, 0, b.device)
-    rc = lib.csc_objective(ctypes.byref(shape), _ptr(b), _ptr(d), _ptr(z), float(beta), _ptr(out), ws, nbytes,
-                           _stream())
+    ws, nbytes = _workspace(shape, OP_OBJECTIVE, flags, b.device)
+    if flags:
+        rc = lib.csc_objective_reg(ctypes.byref(shape), _ptr(b), _ptr(d), _ptr(z), float(beta), flags, _ptr(out), ws,
+                                   nbytes, _stream())
+    else:
+        rc = lib.csc_objective(ctypes.byref(shape), _ptr(b), _ptr(d), _ptr(z), float(beta), _ptr(out), ws, nbytes,
+                               _stream())
     _check(rc)
     return out
 
@@ -419,7 +435,7 @@ def trace_read(cls: int) -> Tuple[float, int]:
 
 def learn_dictionary(b, d0, beta: float, rho, t_in: int, t_out: int, inner_iters: int = 10,
                      cg_iters: int = 10, adaptive: bool = False, log_objective: bool = True, tau=None, tol=None,
-                     cg_tol=None):
+                     cg_tol=None, reg: str = "l1"):
     """Alg. 1: alternate coding (warm-started z, theta) and learning
     (warm-started gamma, carried mu) for ``t_out`` outer steps.  Returns a dict
     with d, z, theta, mu, gamma, rho, the objective after each half step
@@ -430,7 +446,8 @@ def learn_dictionary(b, d0, beta: float, rho, t_in: int, t_out: int, inner_iters
     relative to the previous step's (this reads the objective back each
     step); ``tol`` and ``cg_tol`` are the stopping rules of code_until and
     learn_until (then ``t_in`` and ``cg_iters`` are the largest counts, and
-    the counts taken are returned under "coding_iters" and "cg_counts")."""
+    the counts taken are returned under "coding_iters" and "cg_counts").
+    ``reg`` selects the regulariser of the coding steps and the objective."""
     torch = _torch()
     N, K = b.shape[0], d0.shape[0]
     d = d0.clone()
@@ -445,19 +462,20 @@ def learn_dictionary(b, d0, beta: float, rho, t_in: int, t_out: int, inner_iters
     for _ in range(t_out):
         if tol is not None:
             z, theta, _, rho_t, n = code_until(b, d, beta, rho_t, t_in, tol, z=z, theta=theta, adaptive=adaptive,
-                                                want_theta=True)
+                                                want_theta=True, reg=reg)
             code_its.append(n)
         else:
-            z, theta, _, rho_t = code(b, d, beta, rho_t, t_in, z=z, theta=theta, adaptive=adaptive, want_theta=True)
+            z, theta, _, rho_t = code(b, d, beta, rho_t, t_in, z=z, theta=theta, adaptive=adaptive, want_theta=True,
+                                      reg=reg)
         if log_objective:
-            objs.append(objective(b, d, z, beta)[-1:].clone())
+            objs.append(objective(b, d, z, beta, reg)[-1:].clone())
         if cg_tol is not None:
             d, mu, gamma, c = learn_until(b, z, fsupp, mu, gamma, inner_iters, cg_iters, cg_tol)
             cg_counts.append(c)
         else:
             d, mu, gamma = learn(b, z, fsupp, mu, gamma, inner_iters, cg_iters)
         if log_objective:
-            objs.append(objective(b, d, z, beta)[-1:].clone())
+            objs.append(objective(b, d, z, beta, reg)[-1:].clone())
         steps += 1
         if tau is not None and len(objs) >= 4:
             f_new, f_old = float(objs[-1].item()), float(objs[-3].item())

@@ -13,7 +13,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libdualcsc.so")
 BUILD = os.path.join(PKG, "_build")
-SOURCES = ["api.hip", "coding.hip", "split.hip", "learning.hip", "fftops.hip", "batched.hip", "diff.hip"]
+SOURCES = ["api.hip", "coding.hip", "split.hip", "learning.hip", "fftops.hip", "batched.hip", "diff.hip",
+           "nuclear.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

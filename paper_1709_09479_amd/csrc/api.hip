@@ -87,6 +87,21 @@ int make_plan(const csc_shape* s, Plan* pl) {
   return CSC_OK;
 }
 
+int make_plan_flags(const csc_shape* s, unsigned flags, Plan* pl) {
+  int rc = make_plan(s, pl);
+  if (rc != CSC_OK) return rc;
+  if (flags & CSC_NUCLEAR) {
+    if (!nuclear_supported(pl->g[0], pl->g[1], pl->g[2])) return CSC_EUNSUPPORTED;
+    // every map goes through the axis-by-axis transforms and the per-map
+    // thresholding kernel
+    pl->nuclear = true;
+    pl->lds = false;
+    pl->split = false;
+    pl->ng = pl->ppg = 1;
+  }
+  return CSC_OK;
+}
+
 static int check_ws(void* ws, size_t have, size_t need) {
   if (need == 0) return CSC_OK;
   if (!ws || have < need || (reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return CSC_EWORKSPACE;
@@ -270,9 +285,8 @@ const char* csc_strerror(int code) {
 }
 
 size_t csc_workspace_bytes(const csc_shape* shape, int op, unsigned flags) {
-  (void)flags;
   Plan pl;
-  if (make_plan(shape, &pl) != CSC_OK) return 0;
+  if (make_plan_flags(shape, op == CSC_OP_LEARN ? 0u : (flags & CSC_NUCLEAR), &pl) != CSC_OK) return 0;
   switch (op) {
     case CSC_OP_CODE:
     case CSC_OP_OBJECTIVE: return run_code_ws(pl);
@@ -284,13 +298,13 @@ size_t csc_workspace_bytes(const csc_shape* shape, int op, unsigned flags) {
 int csc_code(const csc_shape* shape, const float* b, const float* d, float beta, float* rho, int iters,
              unsigned flags, float* z, float* theta, double* resid, void* ws, size_t ws_bytes, void* stream) {
   Plan pl;
-  int rc = make_plan(shape, &pl);
+  if (flags & ~(CSC_ADAPTIVE_RHO | CSC_Z_ZERO | CSC_THETA_ZERO | CSC_USE_GRAPH | CSC_NUCLEAR)) return CSC_EINVAL;
+  int rc = make_plan_flags(shape, flags, &pl);
   if (rc != CSC_OK) return rc;
   if (!b || !d || !rho || !z || iters < 0 || !(beta >= 0.0f)) return CSC_EINVAL;
-  if (flags & ~(CSC_ADAPTIVE_RHO | CSC_Z_ZERO | CSC_THETA_ZERO | CSC_USE_GRAPH)) return CSC_EINVAL;
   if ((rc = check_ws(ws, ws_bytes, run_code_ws(pl))) != CSC_OK) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const unsigned f = flags & ~CSC_USE_GRAPH;
+  const unsigned f = flags & ~(CSC_USE_GRAPH | CSC_NUCLEAR);
   if (!(flags & CSC_USE_GRAPH) || st == nullptr)
     return run_code(pl, b, d, beta, rho, iters, f, z, theta, resid, ws, st);
   struct Ctx {
@@ -307,7 +321,7 @@ int csc_code(const csc_shape* shape, const float* b, const float* d, float beta,
   } c{&pl, b, d, beta, rho, iters, f, z, theta, resid, ws, st};
   std::vector<int64_t> key{1};
   shape_key(key, shape);
-  key.insert(key.end(), {pbits(b), pbits(d), fbits(beta), pbits(rho), iters, (int64_t)f, pbits(z), pbits(theta),
+  key.insert(key.end(), {pbits(b), pbits(d), fbits(beta), pbits(rho), iters, (int64_t)flags, pbits(z), pbits(theta),
                          pbits(resid), pbits(ws), (int64_t)ws_bytes, pbits(st)});
   return graph_call(key, st,
                     [](void* p) -> int {
@@ -321,14 +335,15 @@ int csc_code(const csc_shape* shape, const float* b, const float* d, float beta,
 int csc_code_noalloc(const csc_shape* shape, const float* b, const float* d, float beta, float* rho, int iters,
                      unsigned flags, float* z, float* theta, double* resid, void* stream) {
   Plan pl;
-  int rc = make_plan(shape, &pl);
+  if (flags & ~(CSC_ADAPTIVE_RHO | CSC_Z_ZERO | CSC_THETA_ZERO | CSC_NUCLEAR)) return CSC_EINVAL;
+  int rc = make_plan_flags(shape, flags, &pl);
   if (rc != CSC_OK) return rc;
   if (!b || !d || !rho || !z || iters < 0 || !(beta >= 0.0f)) return CSC_EINVAL;
-  if (flags & ~(CSC_ADAPTIVE_RHO | CSC_Z_ZERO | CSC_THETA_ZERO)) return CSC_EINVAL;
   if (run_code_ws(pl) > CSC_NOALLOC_SCRATCH_BYTES) return CSC_ESCRATCH;
   void* ws = nullptr;
   if ((rc = scratch_address(&ws)) != CSC_OK) return rc;
-  return run_code(pl, b, d, beta, rho, iters, flags, z, theta, resid, ws, static_cast<hipStream_t>(stream));
+  return run_code(pl, b, d, beta, rho, iters, flags & ~CSC_NUCLEAR, z, theta, resid, ws,
+                  static_cast<hipStream_t>(stream));
 }
 
 int csc_learn(const csc_shape* shape, const float* b, const float* z, float* d, float* mu, float* gamma,
@@ -368,14 +383,14 @@ int csc_code_tol(const csc_shape* shape, const float* b, const float* d, float b
                  float tol, unsigned flags, float* z, float* theta, double* resid, int* iters_done, void* ws,
                  size_t ws_bytes, void* stream) {
   Plan pl;
-  int rc = make_plan(shape, &pl);
+  if (flags & ~(CSC_ADAPTIVE_RHO | CSC_Z_ZERO | CSC_THETA_ZERO | CSC_NUCLEAR)) return CSC_EINVAL;
+  int rc = make_plan_flags(shape, flags, &pl);
   if (rc != CSC_OK) return rc;
   if (!b || !d || !rho || !z || max_iters < 0 || !(beta >= 0.0f) || !(tol > 0.0f) || !std::isfinite(tol))
     return CSC_EINVAL;
-  if (flags & ~(CSC_ADAPTIVE_RHO | CSC_Z_ZERO | CSC_THETA_ZERO)) return CSC_EINVAL;
   if ((rc = check_ws(ws, ws_bytes, run_code_ws(pl))) != CSC_OK) return rc;
-  return run_code(pl, b, d, beta, rho, max_iters, flags, z, theta, resid, ws, static_cast<hipStream_t>(stream), tol,
-                  iters_done);
+  return run_code(pl, b, d, beta, rho, max_iters, flags & ~CSC_NUCLEAR, z, theta, resid, ws,
+                  static_cast<hipStream_t>(stream), tol, iters_done);
 }
 
 int csc_learn_tol(const csc_shape* shape, const float* b, const float* z, float* d, float* mu, float* gamma,
@@ -441,6 +456,17 @@ int csc_loss_grad(const csc_shape* shape, const float* b, const float* d, const 
   if (!b || !d || !z || !loss || !zbar || !dd || !dbeta || !(beta >= 0.0f)) return CSC_EINVAL;
   if ((rc = check_ws(ws, ws_bytes, run_diff_ws(pl, 1))) != CSC_OK) return rc;
   return run_loss_grad(pl, b, d, z, beta, loss, zbar, dd, dbeta, ws, static_cast<hipStream_t>(stream));
+}
+
+int csc_objective_reg(const csc_shape* shape, const float* b, const float* d, const float* z, float beta,
+                      unsigned flags, double* out, void* ws, size_t ws_bytes, void* stream) {
+  Plan pl;
+  if (flags & ~CSC_NUCLEAR) return CSC_EINVAL;
+  int rc = make_plan_flags(shape, flags, &pl);
+  if (rc != CSC_OK) return rc;
+  if (!b || !d || !z || !out || !(beta >= 0.0f)) return CSC_EINVAL;
+  if ((rc = check_ws(ws, ws_bytes, run_code_ws(pl))) != CSC_OK) return rc;
+  return run_objective(pl, b, d, z, beta, out, ws, static_cast<hipStream_t>(stream));
 }
 
 int csc_objective(const csc_shape* shape, const float* b, const float* d, const float* z, float beta, double* out,

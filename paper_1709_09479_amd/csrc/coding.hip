@@ -799,6 +799,7 @@ size_t carve_code(const Plan& pl, void* base, CodeWs* w) {
   w->rho = c.take<float>(N);
   w->rres = c.take<double>(2 * N);
   w->stop = c.take<int>(2);
+  w->rmap = pl.nuclear ? c.take<double>(N * int64_t(pl.k)) : nullptr;
   return c.off;
 }
 
@@ -868,8 +869,13 @@ static hipError_t iterate_maps(const Plan& pl, CodeWs& w, float* z, float* theta
   LAUNCH_J(k_make_v, pl.j, dim3(nblk(D), pl.p, pl.n), dim3(kEW), st, w.E, w.lam, w.buf, pl.p, D, stop);
   hipError_t e = fft_grids(w.buf, int64_t(pl.n) * pl.p, pl.g, +1, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_spatial, dim3(nblk(D), pl.p, pl.n), dim3(kEW), 0, st, w.buf, z, theta, pl.zoff, w.rho, beta,
-                     w.rpri, pl.k, pl.p, D, stop);
+  if (pl.nuclear) {
+    // z holds the input codes (copied from zin above when given)
+    if ((e = launch_svt(pl, w.buf, z, nullptr, theta, w.rho, beta, w.rmap, 0, st, stop)) != hipSuccess) return e;
+  } else {
+    hipLaunchKernelGGL(k_spatial, dim3(nblk(D), pl.p, pl.n), dim3(kEW), 0, st, w.buf, z, theta, pl.zoff, w.rho,
+                       beta, w.rpri, pl.k, pl.p, D, stop);
+  }
   e = fft_grids(w.buf, int64_t(pl.n) * pl.p, pl.g, -1, st);
   if (e != hipSuccess) return e;
   LAUNCH_J(k_accum, pl.j, dim3(nblk(D), pl.n), dim3(kEW), st, w.buf, w.E, w.part, pl.p, D, stop);
@@ -955,8 +961,9 @@ int run_code(const Plan& pl, const float* b, const float* d, float beta, float* 
     }
     if (rec) save_spec(rec);
     if (need_rho)
-      hipLaunchKernelGGL(k_rho, dim3((unsigned)N), dim3(64), 0, st, w.rpri, w.npri, w.rdual, w.ndual, w.rho, resid,
-                         it, (int)N, D, adaptive ? 1 : 0, stop, tol_mode ? w.rres : nullptr);
+      hipLaunchKernelGGL(k_rho, dim3((unsigned)N), dim3(64), 0, st, pl.nuclear ? w.rmap : w.rpri,
+                         pl.nuclear ? pl.k : w.npri, w.rdual, w.ndual, w.rho, resid, it, (int)N, D, adaptive ? 1 : 0,
+                         stop, tol_mode ? w.rres : nullptr);
     if (tol_mode) hipLaunchKernelGGL(k_stop, dim3(1), dim3(64), 0, st, w.rres, (int)N, thr_pri, thr_dual, w.stop);
     if (adaptive && !last)
       LAUNCH_J(k_solve, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.G, w.xh, w.yh, w.Th, w.rho, w.lam, D, stop);
@@ -1048,8 +1055,12 @@ int run_objective(const Plan& pl, const float* b, const float* d, const float* z
   if (setup_spectra(pl, b, d, w, st) != hipSuccess) return CSC_EHIP;
   if (forward_maps(pl, z, w, w.rpri, st) != hipSuccess) return CSC_EHIP;
   LAUNCH_J(k_obj_spec, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.part, w.xh, w.opart, w.ngp, T, H, W);
-  hipLaunchKernelGGL(k_obj_final, dim3((unsigned)N), dim3(kEW), 0, st, w.opart, w.ndual, w.rpri, w.npri, out, (int)N,
-                     D, beta);
+  if (pl.nuclear &&
+      launch_svt(pl, nullptr, const_cast<float*>(z), nullptr, nullptr, nullptr, 0.f, w.rmap, 1, st, nullptr) !=
+          hipSuccess)
+    return CSC_EHIP;
+  hipLaunchKernelGGL(k_obj_final, dim3((unsigned)N), dim3(kEW), 0, st, w.opart, w.ndual,
+                     pl.nuclear ? w.rmap : w.rpri, pl.nuclear ? pl.k : w.npri, out, (int)N, D, beta);
   hipLaunchKernelGGL(k_obj_total, dim3(1), dim3(64), 0, st, out, (int)N);
   return hipGetLastError() == hipSuccess ? CSC_OK : CSC_EHIP;
 }

@@ -23,6 +23,7 @@ struct Plan {
   int64_t msz = 0;                 // taps per filter channel
   bool lds = false;                // whole grid fits one LDS tile (fused path)
   bool split = false;              // 2-D grid beyond one tile: row / column / row phases
+  bool nuclear = false;            // nuclear-norm regulariser (maps through the global path)
   int ng = 1;                      // pair groups per image in the fused kernel
   int ppg = 1;                     // pairs per group
   // Optional device tables (batched form): element offset of image n's
@@ -39,6 +40,16 @@ void set_grouping(Plan* pl, int ppg_override);
 constexpr int kTileMax = 16384;
 
 int make_plan(const csc_shape* s, Plan* pl);
+// make_plan, then the plan changes that `flags` ask for (CSC_NUCLEAR).
+int make_plan_flags(const csc_shape* s, unsigned flags, Plan* pl);
+
+// Nuclear-norm regulariser (nuclear.hip): 2-D grids with 8 <= H, W <= 128.
+bool nuclear_supported(int T, int H, int W);
+// mode 0: the ADMM z step by singular value thresholding of every map
+// (buf holds D * (D^T lam) pairs and receives the new pairs; rmap [N][K]
+// gets sum (z' - z)^2 per map); mode 1: rmap [N][K] = nuclear norms of z.
+hipError_t launch_svt(const Plan& pl, float2* buf, float* z, const float* zin, float* theta, const float* rho,
+                      float beta, double* rmap, int mode, hipStream_t st, const int* stop);
 
 // Large 2-D grids (128 x 256, 256 x 128, 256 x 256): the coding map work in
 // three phases (split.hip).  Column / row workgroups per grid:
@@ -79,6 +90,7 @@ struct CodeWs {
   float2 *E, *G, *xh, *yh, *Th, *lam, *part, *buf;
   double *rpri, *rdual, *opart;
   double* rres;  // per-image r_pri, r_dual of the last iteration (tolerance mode)
+  double* rmap;  // nuclear-norm plans: per-map partials [N][K]
   int* stop;     // tolerance mode: [0] converged flag, [1] iterations carried out
   float* rho;
   int npri, ndual, ngp;  // partial counts per image; pair groups written to part
