@@ -59,6 +59,7 @@ extern "C" {
 #define CSC_OP_CODE 1
 #define CSC_OP_LEARN 2
 #define CSC_OP_OBJECTIVE 3
+#define CSC_OP_DCT 4          /* csc_code_dct and csc_objective_dct */
 
 /* Flags. */
 #define CSC_ADAPTIVE_RHO 0x1u /* csc_code: residual-balancing step size */
@@ -153,6 +154,36 @@ int csc_code(const csc_shape* shape, const float* b, const float* d, float beta,
 int csc_code_noalloc(const csc_shape* shape, const float* b, const float* d, float beta,
                      float* rho, int iters, unsigned flags, float* z, float* theta,
                      double* resid, void* stream);
+
+/*
+ * Coding with symmetric boundaries: the DCT-domain variant (Sec. 3 notes,
+ * after Bristow et al., that the DCT can replace the DFT where the circular
+ * boundary is a problem).  Images and code maps are extended half-sample
+ * symmetrically at both ends of each axis, and every filter is whole-sample
+ * symmetric about its centre: `q` holds one quadrant of each,
+ *   h_kj[m1][m2] = q[k][j][|m1|][|m2|],  |m1| < fsupp[0], |m2| < fsupp[1],
+ * a (2 fsupp[0] - 1) x (2 fsupp[1] - 1) filter.  The 2-D DCT-II then
+ * diagonalises each convolution with real eigenvalues and the updates of
+ * eq:Inference_solution (as csc_code: eq:Inference_Dual, eq:Inference_ADMM,
+ * J x J blocks for J > 1) run with the DCT in place of the DFT:
+ *   min_z 1/2 || x - sum_k h_k *_s z_k ||^2 + beta sum_k ||z_k||_1.
+ *   shape  ndim 2; grid sides powers of two in [8, 128] with H W <= 16384;
+ *          fsupp = quadrant size, 1 <= fsupp <= min(grid, 16) per axis.
+ *   q      [K][J][fsupp] quadrants (device).
+ *   Other arguments, flags (CSC_ADAPTIVE_RHO, CSC_Z_ZERO, CSC_THETA_ZERO) and
+ *   resid as csc_code; workspace: csc_workspace_bytes(shape, CSC_OP_DCT, 0).
+ *   Errors: CSC_EINVAL, CSC_EUNSUPPORTED (geometry), CSC_EWORKSPACE, CSC_EHIP.
+ */
+int csc_code_dct(const csc_shape* shape, const float* b, const float* q, float beta,
+                 float* rho, int iters, unsigned flags, float* z, float* theta,
+                 double* resid, void* ws, size_t ws_bytes, void* stream);
+
+/* Objective of the symmetric-boundary problem above, per image and total
+ * (out: device float64 [N + 1]); arguments as csc_code_dct, workspace
+ * csc_workspace_bytes(shape, CSC_OP_DCT, 0).  Errors as csc_code_dct. */
+int csc_objective_dct(const csc_shape* shape, const float* b, const float* q,
+                      const float* z, float beta, double* out, void* ws,
+                      size_t ws_bytes, void* stream);
 
 /*
  * csc_code with a stopping rule (the convergence-driven mode; the paper runs

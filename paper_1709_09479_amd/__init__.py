@@ -21,7 +21,7 @@ __all__ = [
     "DualCSCError", "load", "lib_path", "Shape", "code", "learn", "objective",
     "learn_dictionary", "workspace_bytes", "trace_enable", "trace_read", "ADAPTIVE_RHO", "Z_ZERO", "THETA_ZERO",
     "GAMMA_ZERO", "USE_GRAPH", "PackedBatch", "code_batched", "autotune_batched", "unrolled_code", "csc_loss",
-    "code_until", "learn_until",
+    "code_until", "learn_until", "code_dct", "objective_dct", "NUCLEAR",
 ]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -30,7 +30,7 @@ _LIB_NAME = "libdualcsc.so"
 ABI_VERSION = 2
 OK, EINVAL, EWORKSPACE, EUNSUPPORTED, EHIP, ENONFINITE, ESCRATCH = 0, -1, -2, -3, -4, -5, -6
 NOALLOC_SCRATCH_BYTES = 64 << 20
-OP_CODE, OP_LEARN, OP_OBJECTIVE = 1, 2, 3
+OP_CODE, OP_LEARN, OP_OBJECTIVE, OP_DCT = 1, 2, 3, 4
 ADAPTIVE_RHO, Z_ZERO, THETA_ZERO, GAMMA_ZERO, USE_GRAPH, NUCLEAR = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
 _REG_FLAGS = {"l1": 0, "nuclear": NUCLEAR}
 
@@ -120,6 +120,10 @@ def load() -> ctypes.CDLL:
     lib.csc_learn_tol.argtypes = [sp, vp, vp, vp, vp, vp, i32, i32, f32, u32, vp, vp, sz, vp]
     lib.csc_objective.restype = i32
     lib.csc_objective.argtypes = [sp, vp, vp, vp, f32, vp, vp, sz, vp]
+    lib.csc_code_dct.restype = i32
+    lib.csc_code_dct.argtypes = [sp, vp, vp, f32, vp, i32, u32, vp, vp, vp, vp, sz, vp]
+    lib.csc_objective_dct.restype = i32
+    lib.csc_objective_dct.argtypes = [sp, vp, vp, vp, f32, vp, vp, sz, vp]
     lib.csc_objective_reg.restype = i32
     lib.csc_objective_reg.argtypes = [sp, vp, vp, vp, f32, u32, vp, vp, sz, vp]
     lib.csc_trace_enable.restype = i32
@@ -397,6 +401,53 @@ def objective(b, d, z, beta: float, reg: str = "l1"):
         rc = lib.csc_objective(ctypes.byref(shape), _ptr(b), _ptr(d), _ptr(z), float(beta), _ptr(out), ws, nbytes,
                                _stream())
     _check(rc)
+    return out
+
+
+def code_dct(b, q, beta: float, rho, iters: int, z=None, theta=None, adaptive: bool = False,
+             want_theta: bool = False, want_resid: bool = False):
+    """Coding with symmetric boundaries (the DCT-domain variant, csc_code_dct):
+    b [N][J][H][W]; q [K][J][M1][M2] quadrants of whole-sample symmetric
+    filters (h[m1][m2] = q[|m1|][|m2|]).  Other arguments and results as
+    code()."""
+    torch = _torch()
+    lib = load()
+    _need(b, "b")
+    _need(q, "q")
+    shape = _shape_of(b, q)
+    N, K = b.shape[0], q.shape[0]
+    dev = b.device
+    flags = ADAPTIVE_RHO if adaptive else 0
+    if z is None:
+        z = torch.empty((N, K) + tuple(b.shape[2:]), dtype=torch.float32, device=dev)
+        flags |= Z_ZERO
+    _need(z, "z")
+    if theta is None and want_theta:
+        theta = torch.empty_like(z)
+        flags |= THETA_ZERO
+    if theta is not None:
+        _need(theta, "theta")
+    rho_t = rho if isinstance(rho, torch.Tensor) else torch.full((N,), float(rho), dtype=torch.float32, device=dev)
+    _need(rho_t, "rho")
+    resid = torch.empty((iters, N, 3), dtype=torch.float64, device=dev) if (want_resid and iters > 0) else None
+    ws, nbytes = _workspace(shape, OP_DCT, 0, dev)
+    _check(lib.csc_code_dct(ctypes.byref(shape), _ptr(b), _ptr(q), float(beta), _ptr(rho_t), int(iters), flags,
+                            _ptr(z), _ptr(theta), _ptr(resid), ws, nbytes, _stream()))
+    return z, theta, resid, rho_t
+
+
+def objective_dct(b, q, z, beta: float):
+    """Objective of the symmetric-boundary problem: float64 tensor [N + 1]."""
+    torch = _torch()
+    lib = load()
+    _need(b, "b")
+    _need(q, "q")
+    _need(z, "z")
+    shape = _shape_of(b, q)
+    out = torch.empty(b.shape[0] + 1, dtype=torch.float64, device=b.device)
+    ws, nbytes = _workspace(shape, OP_DCT, 0, b.device)
+    _check(lib.csc_objective_dct(ctypes.byref(shape), _ptr(b), _ptr(q), _ptr(z), float(beta), _ptr(out), ws, nbytes,
+                                 _stream()))
     return out
 
 

@@ -102,6 +102,12 @@ int make_plan_flags(const csc_shape* s, unsigned flags, Plan* pl) {
   return CSC_OK;
 }
 
+// Geometry the DCT-domain variant covers: 2-D, single-tile grids, filter
+// quadrants of at most 16 x 16 taps.
+static bool dct_plan_ok(const Plan& pl) {
+  return pl.nd == 2 && dct_supported(pl.g[0], pl.g[1], pl.g[2]) && pl.fs[1] <= 16 && pl.fs[2] <= 16;
+}
+
 static int check_ws(void* ws, size_t have, size_t need) {
   if (need == 0) return CSC_OK;
   if (!ws || have < need || (reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return CSC_EWORKSPACE;
@@ -291,6 +297,7 @@ size_t csc_workspace_bytes(const csc_shape* shape, int op, unsigned flags) {
     case CSC_OP_CODE:
     case CSC_OP_OBJECTIVE: return run_code_ws(pl);
     case CSC_OP_LEARN: return run_learn_ws(pl);
+    case CSC_OP_DCT: return dct_plan_ok(pl) ? dct_ws_bytes(pl) : 0;
     default: return 0;
   }
 }
@@ -467,6 +474,29 @@ int csc_objective_reg(const csc_shape* shape, const float* b, const float* d, co
   if (!b || !d || !z || !out || !(beta >= 0.0f)) return CSC_EINVAL;
   if ((rc = check_ws(ws, ws_bytes, run_code_ws(pl))) != CSC_OK) return rc;
   return run_objective(pl, b, d, z, beta, out, ws, static_cast<hipStream_t>(stream));
+}
+
+int csc_code_dct(const csc_shape* shape, const float* b, const float* q, float beta, float* rho, int iters,
+                 unsigned flags, float* z, float* theta, double* resid, void* ws, size_t ws_bytes, void* stream) {
+  Plan pl;
+  int rc = make_plan(shape, &pl);
+  if (rc != CSC_OK) return rc;
+  if (!dct_plan_ok(pl)) return CSC_EUNSUPPORTED;
+  if (!b || !q || !rho || !z || iters < 0 || !(beta >= 0.0f)) return CSC_EINVAL;
+  if (flags & ~(CSC_ADAPTIVE_RHO | CSC_Z_ZERO | CSC_THETA_ZERO)) return CSC_EINVAL;
+  if ((rc = check_ws(ws, ws_bytes, dct_ws_bytes(pl))) != CSC_OK) return rc;
+  return run_code_dct(pl, b, q, beta, rho, iters, flags, z, theta, resid, ws, static_cast<hipStream_t>(stream));
+}
+
+int csc_objective_dct(const csc_shape* shape, const float* b, const float* q, const float* z, float beta,
+                      double* out, void* ws, size_t ws_bytes, void* stream) {
+  Plan pl;
+  int rc = make_plan(shape, &pl);
+  if (rc != CSC_OK) return rc;
+  if (!dct_plan_ok(pl)) return CSC_EUNSUPPORTED;
+  if (!b || !q || !z || !out || !(beta >= 0.0f)) return CSC_EINVAL;
+  if ((rc = check_ws(ws, ws_bytes, dct_ws_bytes(pl))) != CSC_OK) return rc;
+  return run_objective_dct(pl, b, q, z, beta, out, ws, static_cast<hipStream_t>(stream));
 }
 
 int csc_objective(const csc_shape* shape, const float* b, const float* d, const float* z, float beta, double* out,

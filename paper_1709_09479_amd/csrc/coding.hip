@@ -196,70 +196,6 @@ __global__ void k_sym_reduce(const float2* __restrict__ part, float2* __restrict
 
 // --------------------------------------------- per-frequency dual solve
 
-// lam = (G + I/rho)^-1 r for one frequency.  J = 1 is a division; J > 1 is a
-// Cholesky factorisation of the Hermitian positive-definite J x J block,
-// carried out in float64.
-template <int J>
-__device__ __forceinline__ void dual_solve(const float2* __restrict__ Gf, float inv_rho, const float2* r,
-                                           float2* lam) {
-  if constexpr (J == 1) {
-    const float den = Gf[0].x + inv_rho;
-    lam[0] = make_float2(r[0].x / den, r[0].y / den);
-  } else {
-    double Lr[J][J], Li[J][J];
-#pragma unroll
-    for (int a = 0; a < J; ++a)
-#pragma unroll
-      for (int c = 0; c < J; ++c) Lr[a][c] = Li[a][c] = 0.0;
-#pragma unroll
-    for (int c = 0; c < J; ++c) {
-      double s = (double)Gf[c * J + c].x + (double)inv_rho;
-#pragma unroll
-      for (int m = 0; m < c; ++m) s -= Lr[c][m] * Lr[c][m] + Li[c][m] * Li[c][m];
-      const double lcc = sqrt(s);
-      Lr[c][c] = lcc;
-#pragma unroll
-      for (int a = c + 1; a < J; ++a) {
-        // L[a][c] = (A[a][c] - sum_m L[a][m] conj(L[c][m])) / L[c][c]
-        double sr = Gf[a * J + c].x, si = Gf[a * J + c].y;
-#pragma unroll
-        for (int m = 0; m < c; ++m) {
-          sr -= Lr[a][m] * Lr[c][m] + Li[a][m] * Li[c][m];
-          si -= Li[a][m] * Lr[c][m] - Lr[a][m] * Li[c][m];
-        }
-        Lr[a][c] = sr / lcc;
-        Li[a][c] = si / lcc;
-      }
-    }
-    double yr[J], yi[J];
-#pragma unroll
-    for (int a = 0; a < J; ++a) {  // L y = r
-      double sr = r[a].x, si = r[a].y;
-#pragma unroll
-      for (int m = 0; m < a; ++m) {
-        sr -= Lr[a][m] * yr[m] - Li[a][m] * yi[m];
-        si -= Lr[a][m] * yi[m] + Li[a][m] * yr[m];
-      }
-      yr[a] = sr / Lr[a][a];
-      yi[a] = si / Lr[a][a];
-    }
-#pragma unroll
-    for (int a = J - 1; a >= 0; --a) {  // L^H x = y
-      double sr = yr[a], si = yi[a];
-#pragma unroll
-      for (int m = a + 1; m < J; ++m) {
-        // conj(L[m][a]) * x[m]
-        sr -= Lr[m][a] * yr[m] + Li[m][a] * yi[m];
-        si -= Lr[m][a] * yi[m] - Li[m][a] * yr[m];
-      }
-      yr[a] = sr / Lr[a][a];
-      yi[a] = si / Lr[a][a];
-    }
-#pragma unroll
-    for (int a = 0; a < J; ++a) lam[a] = make_float2((float)yr[a], (float)yi[a]);
-  }
-}
-
 template <int J>
 __global__ void k_solve(const float2* __restrict__ G, const float2* __restrict__ xh, const float2* __restrict__ yh,
                         const float2* __restrict__ Th, const float* __restrict__ rho_cur, float2* __restrict__ lam,
@@ -1029,6 +965,18 @@ hipError_t launch_check_finite(const float* x, int64_t n, int* flag, hipStream_t
 }
 
 size_t run_code_ws(const Plan& pl) { return code_ws_bytes(pl); }
+
+void launch_rho(const double* rpri, int npri, const double* rdual, int ndual, float* rho, double* resid, int it,
+                int N, int64_t D, int adaptive, hipStream_t st) {
+  hipLaunchKernelGGL(k_rho, dim3((unsigned)N), dim3(64), 0, st, rpri, npri, rdual, ndual, rho, resid, it, N, D,
+                     adaptive, nullptr, nullptr);
+}
+
+void launch_obj_final(const double* opart, int nopart, const double* l1, int nl1, double* out, int N, int64_t D,
+                      float beta, hipStream_t st) {
+  hipLaunchKernelGGL(k_obj_final, dim3((unsigned)N), dim3(kEW), 0, st, opart, nopart, l1, nl1, out, N, D, beta);
+  hipLaunchKernelGGL(k_obj_total, dim3(1), dim3(64), 0, st, out, N);
+}
 
 void launch_make_v(const Plan& pl, const float2* E, const float2* lam, float2* buf, hipStream_t st) {
   LAUNCH_J(k_make_v, pl.j, dim3(nblk(pl.dsz), pl.p, pl.n), dim3(kEW), st, E, lam, buf, pl.p, pl.dsz, nullptr);

@@ -127,6 +127,22 @@ void launch_sym_reduce(const Plan& pl, const float2* part, int ng, float2* dst, 
 // objective from part (after forward_maps) and l1 partials in w.rpri
 void launch_objective_tail(const Plan& pl, CodeWs& w, float beta, double* out, hipStream_t st);
 
+// Residual norms and the residual-balancing step per image (k_rho), and
+// the objective's final sums (k_obj_final, k_obj_total), for other paths.
+void launch_rho(const double* rpri, int npri, const double* rdual, int ndual, float* rho, double* resid, int it,
+                int N, int64_t D, int adaptive, hipStream_t st);
+void launch_obj_final(const double* opart, int nopart, const double* l1, int nl1, double* out, int N, int64_t D,
+                      float beta, hipStream_t st);
+
+// DCT-domain variant (dct.hip): 2-D grids with 8 <= H, W <= 128 and
+// H W <= 16384.
+bool dct_supported(int T, int H, int W);
+size_t dct_ws_bytes(const Plan& pl);
+int run_code_dct(const Plan& pl, const float* b, const float* q, float beta, float* rho, int iters, unsigned flags,
+                 float* z, float* theta, double* resid, void* ws, hipStream_t st);
+int run_objective_dct(const Plan& pl, const float* b, const float* q, const float* z, float beta, double* out,
+                      void* ws, hipStream_t st);
+
 // hipGraph capture/replay keyed by every argument of a call.  `enqueue`
 // enqueues the call on `st`; the first call with a key captures it, later
 // calls replay the executable graph.  Returns a CSC_* code.

@@ -151,6 +151,19 @@ def unit_filters(k: int, j: int, fsupp: Sequence[int], seed: int) -> np.ndarray:
     return d.astype(np.float32)
 
 
+def symmetric_quadrants(k: int, j: int, m: Sequence[int], seed: int) -> np.ndarray:
+    """[K][J][M1][M2] float32 quadrants of whole-sample symmetric filters
+    (h[m1][m2] = q[|m1|][|m2|], (2 M1 - 1) x (2 M2 - 1) taps): i.i.d. N(0,1)
+    quadrant taps, scaled so that each full filter has unit L2 norm (a tap
+    off an axis appears four times, one on an axis twice, the centre once)."""
+    rng = np.random.default_rng(seed)
+    q = rng.standard_normal((k, j) + tuple(m))
+    mult = np.outer(np.where(np.arange(m[0]) == 0, 1.0, 2.0), np.where(np.arange(m[1]) == 0, 1.0, 2.0))
+    nrm = np.sqrt((q ** 2 * mult).reshape(k, -1).sum(axis=1))
+    q /= nrm.reshape(k, 1, 1, 1)
+    return q.astype(np.float32)
+
+
 def ragged_sizes(n: int, lo: int, hi: int, seed: int, square: bool = False):
     """List of n (H, W) sides drawn uniformly from {lo..hi} (independently per
     axis unless ``square``)."""
