@@ -225,6 +225,122 @@ def bench_backward(dc, synth, np, torch, reps=2, only_plain=False, only_fwd_bwd=
     }
 
 
+def timed_ms(torch, fn, reps):
+    """Average milliseconds of `fn` over `reps` calls after one untimed call
+    (HIP events on the current stream)."""
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def bench_tensor(dc, synth, np, torch, reps=3):
+    """Tensor CSC (Sec. 3.3): 32 RGB images 128x128 with K = 64 colour filters
+    11x11x3 (beta 0.5, rho 10, 20 iterations), and the 16-frame RGB video
+    volume 16x128x128 with K = 64 filters 3x11x11x3: one csc_code call each."""
+    out = {}
+    for name in ("tensor", "video"):
+        cfg = synth.CONFIGS[name]
+        b, d0 = synth.make_inputs(cfg)
+        bt = torch.from_numpy(b).cuda()
+        dt = torch.from_numpy(d0).cuda()
+        ms = timed_ms(torch, lambda: dc.code(bt, dt, cfg.beta, cfg.rho, cfg.t_in), reps)
+        D = int(np.prod(cfg.grid))
+        out[name] = {
+            "workload": "N=%d J=%d grid %s, K=%d filters %s, beta=%g, rho=%g, %d iterations" % (
+                cfg.n, cfg.j, "x".join(map(str, cfg.grid)), cfg.k, "x".join(map(str, cfg.fsupp)), cfg.beta, cfg.rho,
+                cfg.t_in),
+            "ms_per_call": ms,
+            "cp_it_per_s": cfg.n * cfg.k * D * cfg.t_in / (ms / 1e3),
+            "alg_gbps": alg_bytes_per_iter(cfg.n, cfg.j, cfg.k, D) * cfg.t_in / (ms / 1e3) / 1e9,
+        }
+    return out
+
+
+def bench_variants(dc, synth, np, torch, reps=3):
+    """The two variants on the benchmark's images (10 x 128^2, 10 iterations,
+    rho 10), each against the plain circular l1 solver on the same images:
+    the nuclear-norm regulariser (K = 100 filters 11x11, beta = 1: code maps of
+    rank 4..15 of 128) and the DCT-domain variant with symmetric boundaries
+    (K = 100 whole-sample symmetric 11x11 filters from 6x6 quadrants,
+    beta = 1).  The coding map kernel of each iteration is timed by the
+    library's tracer at its own start and end (DCT) or around the map
+    sequence (nuclear: back-projection, inverse FFT, thresholding, FFT)."""
+    cfg = synth.CONFIGS["learn"]
+    b, d0 = synth.make_inputs(cfg)
+    bt = torch.from_numpy(b).cuda()
+    dt = torch.from_numpy(d0).cuda()
+    q = torch.from_numpy(synth.symmetric_quadrants(cfg.k, 1, (6, 6), 2100)).cuda()
+    N, K, it = cfg.n, cfg.k, cfg.t_in
+    D = cfg.grid[0] * cfg.grid[1]
+    cpit = N * K * D * it
+    alg = alg_bytes_per_iter(N, 1, K, D)
+    ms_plain = timed_ms(torch, lambda: dc.code(bt, dt, 1.0, 10.0, it), reps)
+    out = {"plain_l1_ms": ms_plain}
+    for name, fn in (("nuclear", lambda: dc.code(bt, dt, 1.0, 10.0, it, reg="nuclear")),
+                     ("dct", lambda: dc.code_dct(bt, q, 1.0, 10.0, it))):
+        fn()
+        torch.cuda.synchronize()
+        dc.trace_enable(True, every=1)
+        ms = timed_ms(torch, fn, reps)
+        dc.trace_enable(False)
+        maps_ms, maps_cnt = dc.trace_read(dc.TRACE_CODE_MAPS)
+        avg = maps_ms / max(1, maps_cnt)
+        out[name] = {
+            "ms_per_call": ms,
+            "cp_it_per_s": cpit / (ms / 1e3),
+            "vs_plain_l1": ms / ms_plain,
+            "map_work_avg_ms": avg,
+            "map_work_alg_gbps": alg / (avg / 1e3) / 1e9,
+        }
+    out["workload"] = ("10 images 128x128, 10 iterations, rho 10: nuclear norm (K=100 11x11, beta 1) and DCT "
+                       "symmetric boundaries (K=100 symmetric 11x11, beta 1) against the circular l1 solver")
+    return out
+
+
+def cpu_all_cores(n_images, procs):
+    """The oracle's coding of the benchmark's first `n_images` images (10
+    ADMM iterations, adaptive rho, one image per task, as the coding problem
+    separates over images) in `procs` worker processes.  Runs in a child
+    process that never touches the GPU; prints one JSON object."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    import synth
+    cfg = synth.CONFIGS["learn"]
+    b, d0 = synth.make_inputs(cfg)
+    tasks = [(b[i:i + 1], d0, cfg.beta, cfg.rho0, cfg.t_in) for i in range(n_images)]
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(procs) as pool:
+        pool.map(_cpu_code_one, tasks)
+    t = time.perf_counter() - t0
+    D = cfg.grid[0] * cfg.grid[1]
+    print(json.dumps({"value": n_images * cfg.k * D * cfg.t_in / t, "seconds": t, "procs": procs}))
+
+
+def _cpu_code_one(task):
+    import oracle
+    b, d0, beta, rho, iters = task
+    oracle.code(b, d0, beta, rho, iters, adaptive=True)
+    return 0
+
+
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def bench_sweep_point(dc, synth, np, torch, cfg, steps=5, conv_steps=30):
     """One point of a scaling sweep: the time of one outer step of the
     alternation at fixed counts (coding, learning, objective; median, p10,
@@ -310,8 +426,12 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--batched-images", type=int, default=256)
+    ap.add_argument("--no-tensor", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--cpu-all-cores", type=int, default=0, metavar="PROCS", help=argparse.SUPPRESS)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB")
-    ap.add_argument("--profile-leg", choices=["batched", "unrolled-plain", "unrolled"], default=None,
+    ap.add_argument("--profile-leg", choices=["batched", "unrolled-plain", "unrolled", "tensor", "variants"],
+                    default=None,
                     help="run only the timed calls of one leg (for counter collection)")
     ap.add_argument("--sweep", default=None, metavar="NAMES",
                     help="comma-separated scaling sweeps (gray_K, gray_N, rgb_K, rgb_N, video_K, or all): "
@@ -322,6 +442,9 @@ def main():
               "got --gpus %d" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
+    if args.cpu_all_cores > 0:
+        cpu_all_cores(10, args.cpu_all_cores)
+        return
     if args.calibrate_copy > 0:
         calibrate_copy(args.calibrate_copy)
         return
@@ -350,6 +473,12 @@ def main():
         return
     if args.profile_leg == "unrolled":
         print(json.dumps(bench_backward(dc, synth, np, torch, only_fwd_bwd=True)))
+        return
+    if args.profile_leg == "tensor":
+        print(json.dumps(bench_tensor(dc, synth, np, torch)))
+        return
+    if args.profile_leg == "variants":
+        print(json.dumps(bench_variants(dc, synth, np, torch)))
         return
     cfg = synth.CONFIGS["learn"]
     b, d0 = synth.make_inputs(cfg)
@@ -483,6 +612,10 @@ def main():
         out["batched"] = bench_batched(dc, synth, np, torch, args.batched_images)
     if not args.no_backward:
         out["backward"] = bench_backward(dc, synth, np, torch)
+    if not args.no_tensor:
+        out["tensor"] = bench_tensor(dc, synth, np, torch)
+    if not args.no_variants:
+        out["variants"] = bench_variants(dc, synth, np, torch)
 
     if not args.no_cpu_baseline:
         import oracle
@@ -500,7 +633,24 @@ def main():
             "kind": "oracle",
             "sample": "first %d of the 10 images, one outer step (10 ADMM iterations + learning 10x10 + "
                       "objective), numpy float64, single thread; %.1f s" % (n_cpu, t_cpu),
+            "cpu_model": cpu_model(),
+            "host_cpus": os.cpu_count(),
         }
+        # all cores: the coding half of the step, images in parallel, in a
+        # child process (it forks workers; this process has initialised the GPU)
+        import subprocess
+        procs = max(1, min(16, os.cpu_count() or 1, N))
+        try:
+            res = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-all-cores", str(procs)],
+                                 capture_output=True, text=True, timeout=300)
+            allc = json.loads(res.stdout.strip().splitlines()[-1])
+            out["cpu_baseline"]["all_cores_coding"] = {
+                "value": allc["value"], "unit": "code-pixel-iterations/s", "cores": procs,
+                "sample": "oracle coding of all 10 images (10 adaptive ADMM iterations each), one image per "
+                          "worker process; %.1f s" % allc["seconds"],
+            }
+        except (subprocess.SubprocessError, ValueError, KeyError, IndexError) as exc:
+            out["cpu_baseline"]["all_cores_coding"] = {"error": str(exc)[:200]}
     print(json.dumps(out))
 
 

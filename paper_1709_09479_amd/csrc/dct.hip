@@ -444,14 +444,20 @@ size_t carve_dct(const Plan& pl, void* base, DctWs* w) {
     else hipLaunchKernelGGL(KERNEL<3>, grid, block, 0, st, __VA_ARGS__);               \
   } while (0)
 
+// e0, e1: events to launch with (an own-launch TraceScope's), or null
 template <int J, int MODE>
-bool tile_launch(const Plan& pl, DctWs& w, float* z, float* theta, float beta, const float* img, hipStream_t st) {
+bool tile_launch(const Plan& pl, DctWs& w, float* z, float* theta, float beta, const float* img, hipStream_t st,
+                 hipEvent_t e0, hipEvent_t e1) {
   const int h = pl.g[1], wd = pl.g[2];
   const dim3 grid(MODE == kDctImage ? unsigned(pl.n * pl.j) : unsigned(w.ng * pl.n));
 #define TL(HH, WW)                                                                                                 \
   if (h == HH && wd == WW) {                                                                                       \
-    hipLaunchKernelGGL((k_dct_tile<HH, WW, J, MODE>), grid, dim3(dct_threads(HH * WW)), 0, st, w.E, w.lam, z,     \
-                       theta, w.rho, beta, w.part, w.rpri, pl.k, pl.p, w.ppg, w.ng, img, w.xh);                     \
+    if (e0)                                                                                                        \
+      hipExtLaunchKernelGGL((k_dct_tile<HH, WW, J, MODE>), grid, dim3(dct_threads(HH * WW)), 0, st, e0, e1, 0,    \
+                            w.E, w.lam, z, theta, w.rho, beta, w.part, w.rpri, pl.k, pl.p, w.ppg, w.ng, img, w.xh); \
+    else                                                                                                           \
+      hipLaunchKernelGGL((k_dct_tile<HH, WW, J, MODE>), grid, dim3(dct_threads(HH * WW)), 0, st, w.E, w.lam, z,   \
+                         theta, w.rho, beta, w.part, w.rpri, pl.k, pl.p, w.ppg, w.ng, img, w.xh);                   \
     return true;                                                                                                   \
   }
   TL(8, 8) TL(8, 16) TL(8, 32) TL(8, 64) TL(8, 128)
@@ -464,10 +470,11 @@ bool tile_launch(const Plan& pl, DctWs& w, float* z, float* theta, float beta, c
 }
 
 template <int MODE>
-bool tile_dispatch(const Plan& pl, DctWs& w, float* z, float* theta, float beta, const float* img, hipStream_t st) {
-  if (pl.j == 1) return tile_launch<1, MODE>(pl, w, z, theta, beta, img, st);
-  if (pl.j == 2) return tile_launch<2, MODE>(pl, w, z, theta, beta, img, st);
-  return tile_launch<3, MODE>(pl, w, z, theta, beta, img, st);
+bool tile_dispatch(const Plan& pl, DctWs& w, float* z, float* theta, float beta, const float* img, hipStream_t st,
+                   hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+  if (pl.j == 1) return tile_launch<1, MODE>(pl, w, z, theta, beta, img, st, e0, e1);
+  if (pl.j == 2) return tile_launch<2, MODE>(pl, w, z, theta, beta, img, st, e0, e1);
+  return tile_launch<3, MODE>(pl, w, z, theta, beta, img, st, e0, e1);
 }
 
 int dct_setup(const Plan& pl, const float* b, const float* q, DctWs& w, hipStream_t st) {
@@ -519,7 +526,14 @@ int run_code_dct(const Plan& pl, const float* b, const float* q, float beta, flo
   const bool need_rho = adaptive || resid != nullptr;
   for (int it = 0; it < iters; ++it) {
     const bool last = it == iters - 1;
-    if (!tile_dispatch<kDctIter>(pl, w, z, last ? theta : nullptr, beta, nullptr, st)) return CSC_EUNSUPPORTED;
+    {
+      // the coding map kernel, timed at its own start and end when traced
+      TraceScope trace(kTraceCodeMaps, st, true);
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      trace.events(&e0, &e1);
+      if (!tile_dispatch<kDctIter>(pl, w, z, last ? theta : nullptr, beta, nullptr, st, e0, e1))
+        return CSC_EUNSUPPORTED;
+    }
     const int solve_next = (!last && !adaptive) ? 1 : 0;
     DLAUNCH_J(k_dct_spec, pl.j, gspec, dim3(kDE), st, w.part, w.G, w.xh, w.yh, w.Th, w.lam, w.rho, w.rdual, w.ng,
               W, D, solve_next, (float*)nullptr);
