@@ -21,7 +21,9 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     # packed FP32 instructions stay disabled for all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-ffp-contract=fast", "-Wno-unused-result",
+    # multiply-adds are fused where the source writes them in one expression,
+    # so a device function gives the same bits in every kernel it is inlined in
+    "-ffp-contract=on", "-Wno-unused-result",
     "-I" + os.path.join(os.path.dirname(PKG), "include"),
 ]
 

@@ -24,47 +24,12 @@
 
 #include "common.hpp"
 #include "internal.hpp"
+#include "tiles.hpp"
 
 namespace dcsc {
 
 constexpr int kEW = 256;  // threads of the elementwise kernels
 
-// Index of -f on the grid (T, H, W all powers of two).
-__device__ __forceinline__ int64_t neg_index(int64_t fl, int T, int H, int W) {
-  const int f = (int)fl;
-  const int lw = __builtin_ctz(W), lh = __builtin_ctz(H);
-  const int w = f & (W - 1), h = (f >> lw) & (H - 1), t = f >> (lw + lh);
-  return (((((T - t) & (T - 1)) << lh) | ((H - h) & (H - 1))) << lw) | ((W - w) & (W - 1));
-}
-
-// Y(f) and Y(-f) for Y = sum_g part[n][g][j] (groups added in a fixed order
-// by four interleaved accumulators, so that the loads overlap).
-__device__ __forceinline__ void group_sums(const float2* __restrict__ part, int64_t stride_g, int ng, int64_t f,
-                                           int64_t fn, float2& y, float2& ym) {
-  constexpr int U = 8;  // independent partial sums (loads in flight)
-  float2 a[U], m[U];
-#pragma unroll
-  for (int u = 0; u < U; ++u) a[u] = m[u] = make_float2(0.f, 0.f);
-  int g = 0;
-  for (; g + U <= ng; g += U) {
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const float2* pp = part + (g + u) * stride_g;
-      a[u] = cadd(a[u], pp[f]);
-      m[u] = cadd(m[u], pp[fn]);
-    }
-  }
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    if (g + u < ng) {
-      const float2* pp = part + (g + u) * stride_g;
-      a[u] = cadd(a[u], pp[f]);
-      m[u] = cadd(m[u], pp[fn]);
-    }
-  }
-  y = cadd(cadd(cadd(a[0], a[1]), cadd(a[2], a[3])), cadd(cadd(a[4], a[5]), cadd(a[6], a[7])));
-  ym = cadd(cadd(cadd(m[0], m[1]), cadd(m[2], m[3])), cadd(cadd(m[4], m[5]), cadd(m[6], m[7])));
-}
 
 
 // ------------------------------------------------------------------ set-up
@@ -217,71 +182,17 @@ __global__ void k_solve(const float2* __restrict__ G, const float2* __restrict__
   for (int j = 0; j < J; ++j) lam[(int64_t(n) * J + j) * D + f] = l[j];
 }
 
-// After the forward pass of iteration i: yhat' = sym(sum_g part), Thhat' =
-// G lam + (yhat' - yhat)/rho_i, partial sums of |Thhat' - Thhat|^2 (the dual
-// residual by Parseval) and, when the step size is fixed, the next lam.  The
-// thread of the lower index of each pair (f, -f) does both frequencies, so
-// part is read once.
 template <int J>
-__global__ __launch_bounds__(kEW) void k_spec(const float2* __restrict__ part, const float2* __restrict__ G,
-                                              const float2* __restrict__ xh, float2* __restrict__ yh,
-                                              float2* __restrict__ Th, float2* __restrict__ lam,
-                                              const float* __restrict__ rho_cur, double* __restrict__ rdual,
-                                              int ng, int T, int H, int W, int solve_next,
-                                              const int* __restrict__ stop) {
+__global__ __launch_bounds__(kSpecT) void k_spec(const float2* __restrict__ part, const float2* __restrict__ G,
+                                                 const float2* __restrict__ xh, float2* __restrict__ yh,
+                                                 float2* __restrict__ Th, float2* __restrict__ lam,
+                                                 const float* __restrict__ rho_cur, double* __restrict__ rdual,
+                                                 int ng, int T, int H, int W, int solve_next,
+                                                 const int* __restrict__ stop) {
   if (stop && stop[0]) return;
-  __shared__ double red[kEW / 64];
-  const int64_t D = int64_t(T) * H * W;
-  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int n = blockIdx.y;
-  double ds = 0.0;
-  const int64_t fn = f < D ? neg_index(f, T, H, W) : 0;
-  if (f < D && fn >= f) {  // the pair (f, -f) is handled once, by its lower index
-    const float rho = rho_cur[n], inv_rho = 1.0f / rho;
-    float2 ys[J];  // yhat' at f; at -f it is the conjugate
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-      float2 y, ym;
-      group_sums(part + (int64_t(n) * ng * J + j) * D, int64_t(J) * D, ng, f, fn, y, ym);
-      ys[j] = make_float2(0.5f * (y.x + ym.x), 0.5f * (y.y - ym.y));
-    }
-    for (int side = 0; side < (fn == f ? 1 : 2); ++side) {
-      const int64_t ff = side ? fn : f;
-      const float2* Gf = G + ff * J * J;
-      float2 ynew[J], l[J], thn[J];
-#pragma unroll
-      for (int j = 0; j < J; ++j) {
-        ynew[j] = side ? cconj(ys[j]) : ys[j];
-        l[j] = lam[(int64_t(n) * J + j) * D + ff];
-      }
-#pragma unroll
-      for (int j = 0; j < J; ++j) {
-        float2 gl = make_float2(0.f, 0.f);
-#pragma unroll
-        for (int c = 0; c < J; ++c) gl = cadd(gl, cmul(Gf[j * J + c], l[c]));
-        const int64_t o = (int64_t(n) * J + j) * D + ff;
-        const float2 yo = yh[o], tho = Th[o];
-        thn[j] = make_float2(gl.x + (ynew[j].x - yo.x) * inv_rho, gl.y + (ynew[j].y - yo.y) * inv_rho);
-        const double dx = (double)thn[j].x - tho.x, dy = (double)thn[j].y - tho.y;
-        ds += dx * dx + dy * dy;
-        yh[o] = ynew[j];
-        Th[o] = thn[j];
-      }
-      if (solve_next) {
-        float2 r[J];
-#pragma unroll
-        for (int j = 0; j < J; ++j) {
-          const float2 x = xh[(int64_t(n) * J + j) * D + ff];
-          r[j] = make_float2(thn[j].x + (ynew[j].x - x.x) * inv_rho, thn[j].y + (ynew[j].y - x.y) * inv_rho);
-        }
-        dual_solve<J>(Gf, inv_rho, r, l);
-#pragma unroll
-        for (int j = 0; j < J; ++j) lam[(int64_t(n) * J + j) * D + ff] = l[j];
-      }
-    }
-  }
-  const double t = block_sum(ds, red);
-  if (threadIdx.x == 0) rdual[int64_t(n) * gridDim.x + blockIdx.x] = t;
+  __shared__ double red[kSpecT / 64];
+  spec_item<J>(red, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, part, G, xh, yh, Th, lam, rho_cur, rdual, ng,
+               T, H, W, solve_next);
 }
 
 // Residual norms per image (Boyd et al. 2011, Sec. 3.3) and the residual
@@ -351,28 +262,9 @@ __global__ void k_fill_i(int* __restrict__ out, int v) {
 
 // ------------------------------------------------------- fused tile kernel
 
-// Threads per workgroup of the fused kernel: 32 elements per thread (512
-// threads for the largest tiles).  J = 1 keeps its accumulator in
-// registers; J > 1 accumulates into its partial slice in global memory.
-constexpr int fused_threads(int t, int j) {
-  return j == 1 ? (t >= 16384 ? 1024 : (t / 32 < 64 ? 64 : t / 32))
-                : (t >= 16384 ? 1024 : (t / 16 < 64 ? 64 : t / 16));
-}
-
-enum { kModeIter = 0, kModeForward = 1 };
-
-// One workgroup per (pair group g, image n), handed out by xcd_item so that
-// the workgroups of one XCD share pair groups (and their filter spectra in
-// that XCD's L2) across the images.  kModeIter: for every pair p of
-// the group, back-project lam (V = sum_j lam_j E_jp), inverse 2-D FFT, soft
-// threshold step on the two maps (z updated in place, optional theta),
-// forward 2-D FFT, and accumulate Y_j += C conj(E_jp).  kModeForward: only
-// the forward FFT and accumulation of the given maps (plus l1 sums).
-// The first pass of the inverse transform takes V straight from global
-// memory, its last pass leaves D^T lam in registers for the soft threshold,
-// whose result feeds the first forward pass from registers; the last forward
-// pass leaves the spectrum in registers for the accumulation.
-// part [N][ng][J][D]; rpart [N][ng] (sum (z'-z)^2, or sum |z| when forward).
+// The kernel: one workgroup per (pair group g, image n), handed out by
+// xcd_item so that the workgroups of one XCD share pair groups (and their
+// filter spectra in that XCD's L2) across the images.
 template <int H, int W, int J, int MODE>
 __global__ __launch_bounds__(fused_threads(H * W, J)) void k_fused(
     const float2* __restrict__ E, const float2* __restrict__ lam, float* __restrict__ z,
@@ -380,161 +272,14 @@ __global__ __launch_bounds__(fused_threads(H * W, J)) void k_fused(
     float2* __restrict__ part, double* __restrict__ rpart, int K, int P, int ppg, int ng,
     const int* __restrict__ stop) {
   if (stop && stop[0]) return;
-  constexpr int D = H * W, NT = fused_threads(D, J), WP = tile_stride(W);
-  using PL = TilePlan<H, W, NT, WP>;
-  using P1 = typename PL::InvRow0;
-  using P4 = typename PL::InvColL;
-  using P6 = typename PL::FwdCol0;
-  using P8 = typename PL::FwdRowL;
-  static_assert(P4::JPT == P6::JPT && P4::R == P6::R, "register hand-off mismatch");
-  static_assert(P1::JPT == P8::JPT && P1::R == P8::R, "register hand-off mismatch");
-  constexpr bool kRegAcc = J == 1;
+  constexpr int NT = fused_threads(H * W, J), WP = tile_stride(W);
   __shared__ float2 tile[H * WP];
   __shared__ float2 tw[256];
   __shared__ double red[NT / 64];
   const int N = (int)(gridDim.x / ng), item = xcd_item((int)blockIdx.x, (int)gridDim.x);
-  const int g = item / N, n = item % N;
   load_twiddles(tw);
-  float2 acc[kRegAcc ? P8::JPT : 1][kRegAcc ? P8::R : 1];
-  if constexpr (kRegAcc) {
-#pragma unroll
-    for (int q = 0; q < P8::JPT; ++q)
-#pragma unroll
-      for (int r = 0; r < P8::R; ++r) acc[q][r] = make_float2(0.f, 0.f);
-  }
-  double rsum = 0.0;
-  const float rho = (MODE == kModeIter) ? rho_cur[n] : 1.0f;
-  const float thr = rho * beta, inv_rho = 1.0f / rho, invD = 1.0f / (float)D;
-  const int p0 = g * ppg, p1 = min(P, p0 + ppg);
-  float2* mypart = part + (int64_t(n) * ng + g) * J * D;
-  const float2* lamn = lam + int64_t(n) * J * D;
-  for (int p = p0; p < p1; ++p) {
-    const int tid = opaque_tid();
-    const int ka = 2 * p, kb = 2 * p + 1;
-    const bool hb = kb < K;
-    const int64_t zbase = map_base(zoff, n, K, D);
-    float* za = z + zbase + int64_t(ka) * D;
-    float* zb = z + zbase + int64_t(hb ? kb : ka) * D;
-    const float2* Ep[J];
-#pragma unroll
-    for (int c = 0; c < J; ++c) Ep[c] = E + (int64_t(c) * P + p) * D;
-    float2 v4[P4::JPT][P4::R];
-    if constexpr (MODE == kModeIter) {
-      // first inverse row pass straight from global memory, one job at a time
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < P1::JPT; ++q) {
-        int b, j;
-        if (!P1::job(tid, q, b, j)) continue;
-        __builtin_amdgcn_sched_barrier(0);
-        float2 v1[1][P1::R];
-#pragma unroll
-        for (int r = 0; r < P1::R; ++r) {
-          const int f = b * W + P1::in_pos(j, r);
-          float2 v = make_float2(0.f, 0.f);
-#pragma unroll
-          for (int c = 0; c < J; ++c) v = cadd(v, cmul(lamn[c * D + f], Ep[c][f]));
-          v1[0][r] = v;
-        }
-        dft<P1::R, 1>(v1[0]);
-#pragma unroll
-        for (int r = 0; r < P1::R; ++r) tile[P1::addr(b, P1::out_pos(j, r))] = v1[0][r];
-      }
-      __syncthreads();
-      if constexpr (PL::NA == 2) pass_lds<typename PL::InvRow1>(tile, tw);
-      if constexpr (PL::NB == 2) pass_lds<typename PL::InvCol0>(tile, tw);
-      pass_to_regs<P4>(tid, tile, tw, v4);
-      float* tha = theta ? theta + zbase + int64_t(ka) * D : nullptr;
-      float* thb = theta ? theta + zbase + int64_t(hb ? kb : ka) * D : nullptr;
-#pragma unroll
-      for (int q = 0; q < P4::JPT; ++q) {
-        int b, j;
-        if (!P4::job(tid, q, b, j)) continue;
-        __builtin_amdgcn_sched_barrier(0);
-        float rs = 0.f;
-#pragma unroll
-        for (int r = 0; r < P4::R; ++r) {
-          const int f = P4::out_pos(j, r) * W + b;
-          const float va = v4[q][r].x * invD, vb = v4[q][r].y * invD;
-          const float a0 = za[f], b0 = hb ? zb[f] : 0.f;
-          const float a1 = soft_thresh(fmaf(-rho, va, a0), thr);
-          const float b1 = hb ? soft_thresh(fmaf(-rho, vb, b0), thr) : 0.f;
-          const float da = a1 - a0, db = b1 - b0;
-          rs = fmaf(da, da, fmaf(db, db, rs));
-          za[f] = a1;
-          if (hb) zb[f] = b1;
-          if (tha) {
-            tha[f] = va + da * inv_rho;
-            if (hb) thb[f] = vb + db * inv_rho;
-          }
-          v4[q][r] = make_float2(a1, b1);
-        }
-        rsum += (double)rs;
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < P6::JPT; ++q) {
-        int b, j;
-        if (!P6::job(tid, q, b, j)) continue;
-#pragma unroll
-        for (int r = 0; r < P6::R; ++r) {
-          const int f = P6::in_pos(j, r) * W + b;
-          const float a0 = za[f], b0 = hb ? zb[f] : 0.f;
-          rsum += (double)fabsf(a0) + (double)fabsf(b0);
-          v4[q][r] = make_float2(a0, b0);
-        }
-      }
-    }
-    pass_from_regs<P6>(tid, tile, v4);
-    if constexpr (PL::NB == 2) pass_lds<typename PL::FwdCol1>(tile, tw);
-    if constexpr (PL::NA == 2) pass_lds<typename PL::FwdRow0>(tile, tw);
-    float2 v8[P8::JPT][P8::R];
-    if constexpr (kRegAcc) {
-      pass_to_regs<P8>(tid, tile, tw, v8);
-#pragma unroll
-      for (int q = 0; q < P8::JPT; ++q) {
-        int b, j;
-        if (!P8::job(tid, q, b, j)) continue;
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int r = 0; r < P8::R; ++r)
-          acc[q][r] = cadd(acc[q][r], cmulc(v8[q][r], Ep[0][b * W + P8::out_pos(j, r)]));
-      }
-    } else {
-      pass_to_regs<P8>(tid, tile, tw, v8);
-#pragma unroll
-      for (int q = 0; q < P8::JPT; ++q) {
-        int b, j;
-        if (!P8::job(tid, q, b, j)) continue;
-#pragma unroll
-        for (int r = 0; r < P8::R; ++r) {
-          __builtin_amdgcn_sched_barrier(0);
-          const int f = b * W + P8::out_pos(j, r);
-#pragma unroll
-          for (int c = 0; c < J; ++c) {
-            const float2 y = cmulc(v8[q][r], Ep[c][f]);
-            float2* dst = mypart + c * D + f;
-            *dst = (p == p0) ? y : cadd(*dst, y);
-          }
-        }
-      }
-    }
-  }
-  if constexpr (kRegAcc) {
-    const int tid = opaque_tid();
-#pragma unroll
-    for (int q = 0; q < P8::JPT; ++q) {
-      int b, j;
-      if (!P8::job(tid, q, b, j)) continue;
-#pragma unroll
-      for (int r = 0; r < P8::R; ++r) mypart[b * W + P8::out_pos(j, r)] = acc[q][r];
-    }
-  } else if (p0 >= p1) {
-    for (int f = threadIdx.x; f < D; f += NT)
-      for (int c = 0; c < J; ++c) mypart[int64_t(c) * D + f] = make_float2(0.f, 0.f);
-  }
-  const double tot = block_sum(rsum, red);
-  if (threadIdx.x == 0) rpart[int64_t(n) * ng + g] = tot;
+  fused_item<H, W, J, MODE, NT>(tile, tw, red, item % N, item / N, E, lam, z, theta, zoff, rho_cur, beta, part,
+                                rpart, K, P, ppg, ng);
 }
 
 // ------------------------------------------------ global path (large grids)
@@ -815,6 +560,33 @@ static hipError_t iterate_maps(const Plan& pl, CodeWs& w, float* z, float* theta
   e = fft_grids(w.buf, int64_t(pl.n) * pl.p, pl.g, -1, st);
   if (e != hipSuccess) return e;
   LAUNCH_J(k_accum, pl.j, dim3(nblk(D), pl.n), dim3(kEW), st, w.buf, w.E, w.part, pl.p, D, stop);
+  return hipGetLastError();
+}
+
+hipError_t code_prepare(const Plan& pl, const float* b, const float* d, const float* rho, unsigned flags, float* z,
+                        const float* theta, bool solve, CodeWs& w, hipStream_t st) {
+  const int64_t D = pl.dsz, N = pl.n, J = pl.j;
+  const int T = pl.g[0], H = pl.g[1], W = pl.g[2];
+  const bool z_zero = (flags & CSC_Z_ZERO) != 0;
+  const bool th_zero = theta == nullptr || (flags & CSC_THETA_ZERO) != 0;
+  const int64_t ns = N * J * D;
+  hipError_t e;
+  if ((e = setup_spectra(pl, b, d, w, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_copy_f, dim3(nblk(N)), dim3(kEW), 0, st, w.rho, rho, N);
+  if (z_zero) {
+    hipLaunchKernelGGL(k_zero_maps, dim3(nblk(int64_t(pl.k) * D), N), dim3(kEW), 0, st, z, pl.zoff, pl.k, D);
+    hipLaunchKernelGGL(k_fill_f2, dim3(nblk(ns)), dim3(kEW), 0, st, w.yh, ns);
+  } else {
+    if ((e = forward_maps(pl, z, w, w.rpri, st)) != hipSuccess) return e;
+    LAUNCH_J(k_sym_reduce, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.part, w.yh, w.ngp, T, H, W);
+  }
+  if (th_zero) {
+    hipLaunchKernelGGL(k_fill_f2, dim3(nblk(ns)), dim3(kEW), 0, st, w.Th, ns);
+  } else {
+    if ((e = forward_maps(pl, theta, w, w.rpri, st)) != hipSuccess) return e;
+    LAUNCH_J(k_sym_reduce, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.part, w.Th, w.ngp, T, H, W);
+  }
+  if (solve) LAUNCH_J(k_solve, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.G, w.xh, w.yh, w.Th, w.rho, w.lam, D, nullptr);
   return hipGetLastError();
 }
 

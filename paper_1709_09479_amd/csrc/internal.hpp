@@ -98,6 +98,11 @@ struct CodeWs {
 size_t carve_code(const Plan& pl, void* base, CodeWs* w);
 // Filter pair spectra E, Gram blocks G and image spectra xhat.
 hipError_t setup_spectra(const Plan& pl, const float* b, const float* d, CodeWs& w, hipStream_t st);
+// Everything run_code does before its iteration loop: set-up spectra, rho,
+// z zeroed (CSC_Z_ZERO) or its spectra, theta's spectra (zero when theta is
+// null or CSC_THETA_ZERO), and with `solve` the first lam.
+hipError_t code_prepare(const Plan& pl, const float* b, const float* d, const float* rho, unsigned flags, float* z,
+                        const float* theta, bool solve, CodeWs& w, hipStream_t st);
 // ADMM coding of eq:Inference_solution (csc_code / csc_code_tol).  tol > 0
 // selects the stopping rule; iters_done receives the count.  With `ckpt`
 // (dense maps, fixed steps and count only) the state after 0, every,

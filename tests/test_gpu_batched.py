@@ -97,3 +97,36 @@ def test_batched_rejects_bad_tables(lib):
     bt = pb.struct((11, 11))
     bt.k = 0
     assert lib.load().csc_batch_workspace_bytes(ctypes.byref(bt)) == 0
+
+
+def test_batched_autotune_stays_in_workspace(lib):
+    """The autotuner times each class alone with candidate groupings; one
+    with fewer pairs per group needs more partial spectra than the batch's
+    own layout gives that class.  Every candidate must stay inside the
+    workspace the batch asks for: a guard region after it is unchanged.
+    (3 images 256x256 with K = 64 default to two pairs per group, so one
+    pair per group would need twice the class's partial spectra.)"""
+    import ctypes
+    import torch
+    rng = np.random.default_rng(23)
+    imgs = [(synth.contrast_normalize(synth.one_over_f(rng, (256, 256))) * 30.0)[None].astype(np.float32)
+            for _ in range(3)]
+    imgs.append((synth.contrast_normalize(synth.one_over_f(rng, (64, 64))) * 30.0)[None].astype(np.float32))
+    d = synth.unit_filters(64, 1, (11, 11), 24)
+    pb = lib.PackedBatch([T(im) for im in imgs], d.shape[0])
+    so = lib.load()
+    bt = pb.struct((11, 11))
+    need = so.csc_batch_workspace_bytes(ctypes.byref(bt))
+    guard = 64 << 20
+    buf = torch.full((need + 256 + guard,), 0x5A, dtype=torch.uint8, device="cuda")
+    base = buf.data_ptr() + (-buf.data_ptr()) % 256
+    start = base - buf.data_ptr() + need
+    z = torch.empty(pb.z_numel, dtype=torch.float32, device="cuda")
+    ncls = len(pb.classes((11, 11)))
+    out = (ctypes.c_int32 * ncls)()
+    rc = so.csc_batch_autotune(ctypes.byref(bt), pb.b.data_ptr(), T(d).data_ptr(), 1.0, 10.0, 2, z.data_ptr(),
+                               ctypes.c_void_p(base), need, torch.cuda.current_stream().cuda_stream, out, ncls)
+    assert rc == 0, so.csc_strerror(rc)
+    torch.cuda.synchronize()
+    assert bool((buf[start:start + guard] == 0x5A).all())
+    assert all(v >= 1 for v in out)
