@@ -37,6 +37,30 @@ constexpr int svt_lp(int NR, int NC) {
   return std::min(64, std::min(NR, kSvtT / (NC / 2 > 0 ? NC / 2 : 1)));
 }
 
+// x + the value of lane (lane ^ m) within rows of 16 lanes, through the
+// data-parallel-primitive lane moves of one 32-bit half at a time (no LDS):
+// CTRL 0xB1 (quad xor 1), 0x4E (quad xor 2), 0x141 (half-row mirror),
+// 0x140 (row mirror).  Each lane adds the same two values as its partner,
+// so after the steps every lane of the group holds the same sum.
+template <int CTRL>
+__device__ __forceinline__ double dpp_add(double x) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, false);
+  return x + __hiloint2double(hi, lo);
+}
+
+// Sum over the LP lanes of a group (LP a power of two, groups aligned).
+template <int LP>
+__device__ __forceinline__ double group_sum(double x) {
+  if constexpr (LP >= 2) x = dpp_add<0xB1>(x);
+  if constexpr (LP >= 4) x = dpp_add<0x4E>(x);
+  if constexpr (LP >= 8) x = dpp_add<0x141>(x);
+  if constexpr (LP >= 16) x = dpp_add<0x140>(x);
+#pragma unroll
+  for (int off = 16; off < LP; off <<= 1) x += __shfl_xor(x, off, LP);
+  return x;
+}
+
 // Pair q of round t of the circle ordering of NC columns: column 0 stays,
 // the others rotate; over the NC - 1 rounds every pair meets once.
 __device__ __forceinline__ void svt_pair(int t, int q, int NC, int& a, int& b) {
@@ -117,12 +141,9 @@ __global__ __launch_bounds__(kSvtT) void k_svt(float2* __restrict__ buf, float* 
           bb = fma(y[i], y[i], bb);
           ab = fma(x[i], y[i], ab);
         }
-#pragma unroll
-        for (int off = LP / 2; off > 0; off >>= 1) {
-          aa += __shfl_xor(aa, off, LP);
-          bb += __shfl_xor(bb, off, LP);
-          ab += __shfl_xor(ab, off, LP);
-        }
+        aa = group_sum<LP>(aa);
+        bb = group_sum<LP>(bb);
+        ab = group_sum<LP>(ab);
         if (ab != 0.0 && fabs(ab) > kSvtTol * sqrt(aa * bb)) {
           const double zeta = (bb - aa) / (2.0 * ab);
           const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
@@ -149,8 +170,7 @@ __global__ __launch_bounds__(kSvtT) void k_svt(float2* __restrict__ buf, float* 
       const double x = Bm[c * LDB + sub + i * LP];
       s = fma(x, x, s);
     }
-#pragma unroll
-    for (int off = LP / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, LP);
+    s = group_sum<LP>(s);
     if (sub == 0) coef[c] = sqrt(s);
   }
   __syncthreads();
