@@ -107,3 +107,27 @@ def test_unrolled_gradient_floor(grid, k):
     print("grid %s K=%d: float32 floor of the filter gradient %.2e of max, beta %.2e" % (grid, k, ed, eb))
     assert 5e-5 < ed < 1e-3, ed
     assert eb < 1e-5, eb
+
+
+def test_unrolled_gradient_regrouping():
+    """How far a regrouping of float32 sums alone moves the unrolled filter
+    gradient (2 images 128^2, K = 32, 30 iterations, beta 1, rho 10, images
+    times 30): the float32 solve with its filters in three shuffled orders
+    against the float32 solve in the given order.  A different grouping
+    moves some codes across the clipping kinks, and the gradient by more
+    than 1e-3 of its maximum; gradients of batches of different sizes (which
+    the GPU groups differently) are therefore not compared with each other."""
+    rng = np.random.default_rng(21)
+    b = np.stack([synth.contrast_normalize(synth.one_over_f(rng, (128, 128)))[None] * 30 for _ in range(2)])
+    b = b.astype(np.float32)
+    d = synth.unit_filters(32, 1, (11, 11), 5)
+    _, gd, gb = f32.code_loss_grad(b, d, 1.0, 10.0, 30)
+    worst = 0.0
+    for seed in range(3):
+        perm = np.random.default_rng(seed).permutation(d.shape[0])
+        _, gdp, gbp = f32.code_loss_grad(b, d[perm], 1.0, 10.0, 30)
+        gdp = gdp[np.argsort(perm)]
+        worst = max(worst, float(np.abs(gd - gdp).max() / np.abs(gd).max()))
+        assert abs(gb - gbp) < 1e-4 * abs(gb)
+    print("regrouped float32 sums move the filter gradient by %.2e of its max" % worst)
+    assert 1e-3 < worst < 1e-2, worst
