@@ -272,14 +272,14 @@ __global__ __launch_bounds__(fused_threads(H * W, J)) void k_fused(
     float2* __restrict__ part, double* __restrict__ rpart, int K, int P, int ppg, int ng,
     const int* __restrict__ stop) {
   if (stop && stop[0]) return;
-  constexpr int NT = fused_threads(H * W, J), WP = tile_stride(W);
+  constexpr int D = H * W, NT = fused_threads(D, J), WP = tile_stride(W);
   __shared__ float2 tile[H * WP];
   __shared__ float2 tw[256];
   __shared__ double red[NT / 64];
   const int N = (int)(gridDim.x / ng), item = xcd_item((int)blockIdx.x, (int)gridDim.x);
+  const int g = item / N, n = item % N;
   load_twiddles(tw);
-  fused_item<H, W, J, MODE, NT>(tile, tw, red, item % N, item / N, E, lam, z, theta, zoff, rho_cur, beta, part,
-                                rpart, K, P, ppg, ng);
+#include "fused_body.inc"
 }
 
 // ------------------------------------------------ global path (large grids)

@@ -48,8 +48,13 @@ __global__ __launch_bounds__(kSplitNT) void k_split_cols(float2* __restrict__ bu
   __shared__ float2 tw[256];
   __shared__ double red[kSplitNT / 64];
   load_twiddles(tw);
-  cols_item<H, MODE>(tile, tw, red, (int)blockIdx.z, (int)blockIdx.y, (int)blockIdx.x, (int)gridDim.x, buf, z, zin,
-                     theta, zoff, rho_cur, beta, rpart, K, P, W);
+  // column blocks fastest, in contiguous ranges per XCD: the two halves of
+  // a 128-byte line of a map row (16 columns of 4 bytes each when H = 256)
+  // are read by neighbouring blocks of one XCD, so the second finds the
+  // line in that XCD's L2
+  const int ncb = W / CB, item = xcd_item((int)blockIdx.x, (int)gridDim.x);
+  cols_item<H, MODE>(tile, tw, red, item / ncb / P, (item / ncb) % P, item % ncb, ncb, buf, z, zin, theta, zoff,
+                     rho_cur, beta, rpart, K, P, W);
 }
 
 template <int W, int J>
@@ -86,7 +91,7 @@ static hipError_t split_iter_j(const Plan& pl, const float2* E, const float2* la
     if (W == 256) hipLaunchKernelGGL((k_split_rows_inv<256, J>), g1, blk, 0, st, E, lam, buf, pl.p, H, stop);
     else hipLaunchKernelGGL((k_split_rows_inv<128, J>), g1, blk, 0, st, E, lam, buf, pl.p, H, stop);
   }
-  const dim3 g2(split_col_blocks(pl), pl.p, pl.n);
+  const dim3 g2(split_col_blocks(pl) * pl.p * pl.n);
   if (mode == 0) {
     if (H == 256)
       hipLaunchKernelGGL((k_split_cols<256, 0>), g2, blk, 0, st, buf, z, zin, theta, pl.zoff, rho, beta, rpart, pl.k,

@@ -149,154 +149,7 @@ __device__ __forceinline__ void fused_item(float2* tile, const float2* tw, doubl
                                            float beta, float2* __restrict__ part, double* __restrict__ rpart, int K,
                                            int P, int ppg, int ng) {
   constexpr int D = H * W, WP = tile_stride(W);
-  using PL = TilePlan<H, W, NT, WP>;
-  using P1 = typename PL::InvRow0;
-  using P4 = typename PL::InvColL;
-  using P6 = typename PL::FwdCol0;
-  using P8 = typename PL::FwdRowL;
-  static_assert(P4::JPT == P6::JPT && P4::R == P6::R, "register hand-off mismatch");
-  static_assert(P1::JPT == P8::JPT && P1::R == P8::R, "register hand-off mismatch");
-  constexpr bool kRegAcc = J == 1;
-  float2 acc[kRegAcc ? P8::JPT : 1][kRegAcc ? P8::R : 1];
-  if constexpr (kRegAcc) {
-#pragma unroll
-    for (int q = 0; q < P8::JPT; ++q)
-#pragma unroll
-      for (int r = 0; r < P8::R; ++r) acc[q][r] = make_float2(0.f, 0.f);
-  }
-  double rsum = 0.0;
-  const float rho = (MODE == kModeIter) ? rho_cur[n] : 1.0f;
-  const float thr = rho * beta, inv_rho = 1.0f / rho, invD = 1.0f / (float)D;
-  const int p0 = g * ppg, p1 = min(P, p0 + ppg);
-  float2* mypart = part + (int64_t(n) * ng + g) * J * D;
-  const float2* lamn = lam + int64_t(n) * J * D;
-  for (int p = p0; p < p1; ++p) {
-    const int tid = opaque_tid();
-    const int ka = 2 * p, kb = 2 * p + 1;
-    const bool hb = kb < K;
-    const int64_t zbase = map_base(zoff, n, K, D);
-    float* za = z + zbase + int64_t(ka) * D;
-    float* zb = z + zbase + int64_t(hb ? kb : ka) * D;
-    const float2* Ep[J];
-#pragma unroll
-    for (int c = 0; c < J; ++c) Ep[c] = E + (int64_t(c) * P + p) * D;
-    float2 v4[P4::JPT][P4::R];
-    if constexpr (MODE == kModeIter) {
-      // first inverse row pass straight from global memory, one job at a time
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < P1::JPT; ++q) {
-        int b, j;
-        if (!P1::job(tid, q, b, j)) continue;
-        __builtin_amdgcn_sched_barrier(0);
-        float2 v1[1][P1::R];
-#pragma unroll
-        for (int r = 0; r < P1::R; ++r) {
-          const int f = b * W + P1::in_pos(j, r);
-          float2 v = make_float2(0.f, 0.f);
-#pragma unroll
-          for (int c = 0; c < J; ++c) v = cadd(v, cmul(lamn[c * D + f], Ep[c][f]));
-          v1[0][r] = v;
-        }
-        dft<P1::R, 1>(v1[0]);
-#pragma unroll
-        for (int r = 0; r < P1::R; ++r) tile[P1::addr(b, P1::out_pos(j, r))] = v1[0][r];
-      }
-      __syncthreads();
-      if constexpr (PL::NA == 2) pass_lds<typename PL::InvRow1>(tile, tw);
-      if constexpr (PL::NB == 2) pass_lds<typename PL::InvCol0>(tile, tw);
-      pass_to_regs<P4>(tid, tile, tw, v4);
-      float* tha = theta ? theta + zbase + int64_t(ka) * D : nullptr;
-      float* thb = theta ? theta + zbase + int64_t(hb ? kb : ka) * D : nullptr;
-#pragma unroll
-      for (int q = 0; q < P4::JPT; ++q) {
-        int b, j;
-        if (!P4::job(tid, q, b, j)) continue;
-        __builtin_amdgcn_sched_barrier(0);
-        float rs = 0.f;
-#pragma unroll
-        for (int r = 0; r < P4::R; ++r) {
-          const int f = P4::out_pos(j, r) * W + b;
-          const float va = v4[q][r].x * invD, vb = v4[q][r].y * invD;
-          const float a0 = za[f], b0 = hb ? zb[f] : 0.f;
-          const float a1 = soft_thresh(fmaf(-rho, va, a0), thr);
-          const float b1 = hb ? soft_thresh(fmaf(-rho, vb, b0), thr) : 0.f;
-          const float da = a1 - a0, db = b1 - b0;
-          rs = fmaf(da, da, fmaf(db, db, rs));
-          za[f] = a1;
-          if (hb) zb[f] = b1;
-          if (tha) {
-            tha[f] = va + da * inv_rho;
-            if (hb) thb[f] = vb + db * inv_rho;
-          }
-          v4[q][r] = make_float2(a1, b1);
-        }
-        rsum += (double)rs;
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < P6::JPT; ++q) {
-        int b, j;
-        if (!P6::job(tid, q, b, j)) continue;
-#pragma unroll
-        for (int r = 0; r < P6::R; ++r) {
-          const int f = P6::in_pos(j, r) * W + b;
-          const float a0 = za[f], b0 = hb ? zb[f] : 0.f;
-          rsum += (double)fabsf(a0) + (double)fabsf(b0);
-          v4[q][r] = make_float2(a0, b0);
-        }
-      }
-    }
-    pass_from_regs<P6>(tid, tile, v4);
-    if constexpr (PL::NB == 2) pass_lds<typename PL::FwdCol1>(tile, tw);
-    if constexpr (PL::NA == 2) pass_lds<typename PL::FwdRow0>(tile, tw);
-    float2 v8[P8::JPT][P8::R];
-    if constexpr (kRegAcc) {
-      pass_to_regs<P8>(tid, tile, tw, v8);
-#pragma unroll
-      for (int q = 0; q < P8::JPT; ++q) {
-        int b, j;
-        if (!P8::job(tid, q, b, j)) continue;
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int r = 0; r < P8::R; ++r)
-          acc[q][r] = cadd(acc[q][r], cmulc(v8[q][r], Ep[0][b * W + P8::out_pos(j, r)]));
-      }
-    } else {
-      pass_to_regs<P8>(tid, tile, tw, v8);
-#pragma unroll
-      for (int q = 0; q < P8::JPT; ++q) {
-        int b, j;
-        if (!P8::job(tid, q, b, j)) continue;
-#pragma unroll
-        for (int r = 0; r < P8::R; ++r) {
-          __builtin_amdgcn_sched_barrier(0);
-          const int f = b * W + P8::out_pos(j, r);
-#pragma unroll
-          for (int c = 0; c < J; ++c) {
-            const float2 y = cmulc(v8[q][r], Ep[c][f]);
-            float2* dst = mypart + c * D + f;
-            *dst = (p == p0) ? y : cadd(*dst, y);
-          }
-        }
-      }
-    }
-  }
-  if constexpr (kRegAcc) {
-    const int tid = opaque_tid();
-#pragma unroll
-    for (int q = 0; q < P8::JPT; ++q) {
-      int b, j;
-      if (!P8::job(tid, q, b, j)) continue;
-#pragma unroll
-      for (int r = 0; r < P8::R; ++r) mypart[b * W + P8::out_pos(j, r)] = acc[q][r];
-    }
-  } else if (p0 >= p1) {
-    for (int f = threadIdx.x; f < D; f += NT)
-      for (int c = 0; c < J; ++c) mypart[int64_t(c) * D + f] = make_float2(0.f, 0.f);
-  }
-  const double tot = block_sum(rsum, red);
-  if (threadIdx.x == 0) rpart[int64_t(n) * ng + g] = tot;
+#include "fused_body.inc"
 }
 
 // ------------------------------------------------ split path (large 2-D grids)
@@ -465,16 +318,35 @@ __device__ __forceinline__ void rows_fwd_item(float2* tile, const float2* tw, in
     for (int q = 0; q < Q1::JPT; ++q)
 #pragma unroll
       for (int r = 0; r < Q1::R; ++r) acc[c][q][r] = make_float2(0.f, 0.f);
-  for (int p = p0; p < p1; ++p) {
+  // The tile of the next pair and the filter spectra of this pair (J = 1)
+  // are loaded before this pair's row transform, so that their latency
+  // overlaps the transform instead of following it.
+  auto load_tile = [&](int p, float2 (&v)[Q0::JPT][Q0::R]) {
     const int tid = opaque_tid();
     const float2* g = buf + (int64_t(n) * P + p) * D;
-    float2 v[Q0::JPT][Q0::R];
 #pragma unroll
     for (int q = 0; q < Q0::JPT; ++q) {
       int b, j;
       if (!Q0::job(tid, q, b, j)) continue;
 #pragma unroll
       for (int r = 0; r < Q0::R; ++r) v[q][r] = g[(row0 + b) * W + Q0::in_pos(j, r)];
+    }
+  };
+  float2 v[Q0::JPT][Q0::R];
+  if (p0 < p1) load_tile(p0, v);
+  for (int p = p0; p < p1; ++p) {
+    const int tid = opaque_tid();
+    float2 e[J == 1 ? Q1::JPT : 1][J == 1 ? Q1::R : 1];
+    float2 vn[J == 1 ? Q0::JPT : 1][J == 1 ? Q0::R : 1];
+    if constexpr (J == 1) {
+#pragma unroll
+      for (int q = 0; q < Q1::JPT; ++q) {
+        int b, j;
+        if (!Q1::job(tid, q, b, j)) continue;
+#pragma unroll
+        for (int r = 0; r < Q1::R; ++r) e[q][r] = E[int64_t(p) * D + (row0 + b) * W + Q1::out_pos(j, r)];
+      }
+      if (p + 1 < p1) load_tile(p + 1, vn);
     }
     pass_from_regs<Q0>(tid, tile, v);
     float2 u[Q1::JPT][Q1::R];
@@ -485,10 +357,23 @@ __device__ __forceinline__ void rows_fwd_item(float2* tile, const float2* tw, in
       if (!Q1::job(tid, q, b, j)) continue;
 #pragma unroll
       for (int r = 0; r < Q1::R; ++r) {
-        const int64_t f = (row0 + b) * W + Q1::out_pos(j, r);
+        if constexpr (J == 1) {
+          acc[0][q][r] = cadd(acc[0][q][r], cmulc(u[q][r], e[q][r]));
+        } else {
+          const int64_t f = (row0 + b) * W + Q1::out_pos(j, r);
 #pragma unroll
-        for (int c = 0; c < J; ++c) acc[c][q][r] = cadd(acc[c][q][r], cmulc(u[q][r], E[(int64_t(c) * P + p) * D + f]));
+          for (int c = 0; c < J; ++c)
+            acc[c][q][r] = cadd(acc[c][q][r], cmulc(u[q][r], E[(int64_t(c) * P + p) * D + f]));
+        }
       }
+    }
+    if constexpr (J == 1) {
+#pragma unroll
+      for (int q = 0; q < Q0::JPT; ++q)
+#pragma unroll
+        for (int r = 0; r < Q0::R; ++r) v[q][r] = vn[q][r];
+    } else if (p + 1 < p1) {
+      load_tile(p + 1, v);
     }
   }
   const int tid = opaque_tid();
