@@ -234,6 +234,67 @@ __global__ __launch_bounds__(64) void k_rho(const double* __restrict__ rpri, int
   }
 }
 
+// k_rho and k_solve in one launch (adaptive rho between two iterations):
+// every wavefront of a block reduces image n's residual partials in k_rho's
+// order, takes the residual-balancing step from rho_cur, and solves for
+// lam with the new rho; block (0, n) records the residuals and writes the
+// new rho to rho_next (a separate buffer, since the other blocks still read
+// rho_cur).  Results equal k_rho followed by k_solve bit for bit.
+template <int J>
+__global__ __launch_bounds__(kEW) void k_solve_rho(const float2* __restrict__ G, const float2* __restrict__ xh,
+                                                    const float2* __restrict__ yh, const float2* __restrict__ Th,
+                                                    const double* __restrict__ rpri, int npri,
+                                                    const double* __restrict__ rdual, int ndual,
+                                                    const float* __restrict__ rho_cur, float* __restrict__ rho_next,
+                                                    double* __restrict__ resid, int it, int N, float2* __restrict__ lam,
+                                                    int64_t D) {
+  const int n = blockIdx.y, lane = threadIdx.x & 63;
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  // the spectra do not depend on rho: their loads go out first
+  float2 y[J], x[J], th[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int64_t o = (int64_t(n) * J + j) * D + (f < D ? f : 0);
+    y[j] = yh[o];
+    x[j] = xh[o];
+    th[j] = Th[o];
+  }
+  double sp = 0.0, sd = 0.0;
+  for (int i = lane; i < npri; i += 64) sp += rpri[int64_t(n) * npri + i];
+  for (int i = lane; i < ndual; i += 64) sd += rdual[int64_t(n) * ndual + i];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    sp += __shfl_down(sp, off, 64);
+    sd += __shfl_down(sd, off, 64);
+  }
+  sp = __shfl(sp, 0, 64);
+  sd = __shfl(sd, 0, 64);
+  const float rho = rho_cur[n];
+  const double r_pri = sqrt(sp) / (double)rho;
+  const double r_dual = (double)rho * sqrt(sd / (double)D);
+  float nr = rho;
+  if (r_pri > 10.0 * r_dual) nr = rho * 2.0f;
+  else if (r_dual > 10.0 * r_pri) nr = rho * 0.5f;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    rho_next[n] = nr;
+    if (resid) {
+      double* o = resid + (int64_t(it) * N + n) * 3;
+      o[0] = r_pri;
+      o[1] = r_dual;
+      o[2] = (double)rho;
+    }
+  }
+  if (f >= D) return;
+  const float inv_rho = 1.0f / nr;
+  float2 r[J], l[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j)
+    r[j] = make_float2(th[j].x + (y[j].x - x[j].x) * inv_rho, th[j].y + (y[j].y - x[j].y) * inv_rho);
+  dual_solve<J>(G + f * J * J, inv_rho, r, l);
+#pragma unroll
+  for (int j = 0; j < J; ++j) lam[(int64_t(n) * J + j) * D + f] = l[j];
+}
+
 // Stopping rule of the tolerance mode (Boyd et al. 2011, Sec. 3.3.1 with a
 // zero relative tolerance): every image has r_pri <= thr_pri and r_dual <=
 // thr_dual (the RMS residuals times sqrt of the entry counts).  stop[0] is
@@ -478,6 +539,7 @@ size_t carve_code(const Plan& pl, void* base, CodeWs* w) {
   w->rdual = c.take<double>(N * w->ndual);
   w->opart = c.take<double>(N * w->ndual);
   w->rho = c.take<float>(N);
+  w->rho2 = c.take<float>(N);
   w->rres = c.take<double>(2 * N);
   w->stop = c.take<int>(2);
   w->rmap = pl.nuclear ? c.take<double>(N * int64_t(pl.k)) : nullptr;
@@ -668,6 +730,15 @@ int run_code(const Plan& pl, const float* b, const float* d, float beta, float* 
                w.rdual, w.ngp, T, H, W, solve_next, stop);
     }
     if (rec) save_spec(rec);
+    if (adaptive && !last && !tol_mode) {
+      // residual-balancing step and the next solve in one launch; the new
+      // rho goes to the other buffer, which the next iteration reads
+      LAUNCH_J(k_solve_rho, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.G, w.xh, w.yh, w.Th,
+               pl.nuclear ? w.rmap : w.rpri, pl.nuclear ? pl.k : w.npri, w.rdual, w.ndual, w.rho, w.rho2, resid, it,
+               (int)N, w.lam, D);
+      std::swap(w.rho, w.rho2);
+      continue;
+    }
     if (need_rho)
       hipLaunchKernelGGL(k_rho, dim3((unsigned)N), dim3(64), 0, st, pl.nuclear ? w.rmap : w.rpri,
                          pl.nuclear ? pl.k : w.npri, w.rdual, w.ndual, w.rho, resid, it, (int)N, D, adaptive ? 1 : 0,

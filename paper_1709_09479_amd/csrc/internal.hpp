@@ -93,6 +93,7 @@ struct CodeWs {
   double* rmap;  // nuclear-norm plans: per-map partials [N][K]
   int* stop;     // tolerance mode: [0] converged flag, [1] iterations carried out
   float* rho;
+  float* rho2;   // adaptive rho: the other buffer (k_solve_rho reads one, writes the other)
   int npri, ndual, ngp;  // partial counts per image; pair groups written to part
 };
 size_t carve_code(const Plan& pl, void* base, CodeWs* w);
