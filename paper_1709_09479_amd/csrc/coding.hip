@@ -152,7 +152,7 @@ __global__ void k_sym_reduce(const float2* __restrict__ part, float2* __restrict
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     float2 y, ym;
-    group_sums(part + (int64_t(n) * ng * J + j) * D, int64_t(J) * D, ng, f, fn, y, ym);
+    group_sums<8>(part + (int64_t(n) * ng * J + j) * D, int64_t(J) * D, ng, f, fn, y, ym);
     const float2 s = make_float2(0.5f * (y.x + ym.x), 0.5f * (y.y - ym.y));
     dst[(int64_t(n) * J + j) * D + f] = s;
     dst[(int64_t(n) * J + j) * D + fn] = cconj(s);
@@ -434,7 +434,7 @@ __global__ __launch_bounds__(kEW) void k_obj_spec(const float2* __restrict__ par
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       float2 y, ym;
-      group_sums(part + (int64_t(n) * ng * J + j) * D, int64_t(J) * D, ng, f, fn, y, ym);
+      group_sums<8>(part + (int64_t(n) * ng * J + j) * D, int64_t(J) * D, ng, f, fn, y, ym);
       const double sx = 0.5 * ((double)y.x + ym.x), sy = 0.5 * ((double)y.y - ym.y);  // yhat at f
       const float2 x = xh[(int64_t(n) * J + j) * D + f];
       double rx = (double)x.x - sx, ry = (double)x.y - sy;

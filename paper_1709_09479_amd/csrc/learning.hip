@@ -626,25 +626,6 @@ __global__ __launch_bounds__(64 * kBW) void l_passB_c(const float2* __restrict__
   }
 }
 
-// Fixed-order sums of two arrays of `cnt` partials by one block, read in one
-// pass (thread t adds elements t, t + blockDim.x, ..., then block_sum); every
-// thread gets both totals.  bcast holds two values.
-__device__ __forceinline__ void sum_partials2(const double* __restrict__ a, const double* __restrict__ b, int cnt,
-                                              double* red, double* bcast, double& sa, double& sb) {
-  double u = 0.0, v = 0.0;
-  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-    u += a[i];
-    v += b[i];
-  }
-  const double ta = block_sum(u, red);
-  if (threadIdx.x == 0) bcast[0] = ta;
-  const double tb = block_sum(v, red);
-  if (threadIdx.x == 0) bcast[1] = tb;
-  __syncthreads();
-  sa = bcast[0];
-  sb = bcast[1];
-}
-
 // One conjugate-gradient step in the arrangement of Chronopoulos and Gear
 // (1989), which needs a single reduction phase per step: after the operator
 // has produced w = A r, with gamma = |r|^2 and delta = Re<r, w> (partials of
@@ -665,8 +646,6 @@ __global__ __launch_bounds__(kLW) void l_cg_cg(float2* __restrict__ x, float2* _
                                                int first, int64_t D, int* __restrict__ cgf,
                                                const double* __restrict__ bb, double tol2, int* __restrict__ count) {
   if (cgf && cgf[0]) return;
-  __shared__ double red[kLW / 64];
-  __shared__ double bc[2];
   const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int n = blockIdx.y;
   const bool lead = blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0;
@@ -690,10 +669,23 @@ __global__ __launch_bounds__(kLW) void l_cg_cg(float2* __restrict__ x, float2* _
   }
   double al[J], be[J];
   bool conv = cgf != nullptr;
+  const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int j = 0; j < J; ++j) {
-    double gam, del;
-    sum_partials2(gpart + int64_t(j) * npart, dpart + int64_t(j) * npart, npart, red, bc, gam, del);
+    // every wavefront sums the partials itself (same order everywhere), so
+    // no block-wide barrier stands between the loads and the update
+    double gam = 0.0, del = 0.0;
+    for (int i = lane; i < npart; i += 64) {
+      gam += gpart[int64_t(j) * npart + i];
+      del += dpart[int64_t(j) * npart + i];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      gam += __shfl_down(gam, off, 64);
+      del += __shfl_down(del, off, 64);
+    }
+    gam = __shfl(gam, 0, 64);
+    del = __shfl(del, 0, 64);
     const double gp = first ? 0.0 : sc_in[j], ap = first ? 0.0 : sc_in[J + j];
     const double b = gp > 0.0 ? gam / gp : 0.0;
     const double den = ap > 0.0 ? del - b * gam / ap : del;

@@ -25,10 +25,10 @@ __device__ __forceinline__ int64_t neg_index(int64_t fl, int T, int H, int W) {
 }
 
 // Y(f) and Y(-f) for Y = sum_g part[n][g][j] (groups added in a fixed order
-// by four interleaved accumulators, so that the loads overlap).
+// by U interleaved accumulators, so that 2 U loads are in flight).
+template <int U>
 __device__ __forceinline__ void group_sums(const float2* __restrict__ part, int64_t stride_g, int ng, int64_t f,
                                            int64_t fn, float2& y, float2& ym) {
-  constexpr int U = 8;  // independent partial sums (loads in flight)
   float2 a[U], m[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) a[u] = m[u] = make_float2(0.f, 0.f);
@@ -49,8 +49,15 @@ __device__ __forceinline__ void group_sums(const float2* __restrict__ part, int6
       m[u] = cadd(m[u], pp[fn]);
     }
   }
-  y = cadd(cadd(cadd(a[0], a[1]), cadd(a[2], a[3])), cadd(cadd(a[4], a[5]), cadd(a[6], a[7])));
-  ym = cadd(cadd(cadd(m[0], m[1]), cadd(m[2], m[3])), cadd(cadd(m[4], m[5]), cadd(m[6], m[7])));
+#pragma unroll
+  for (int h = U / 2; h > 0; h /= 2)
+#pragma unroll
+    for (int u = 0; u < h; ++u) {
+      a[u] = cadd(a[u], a[u + h]);
+      m[u] = cadd(m[u], m[u + h]);
+    }
+  y = a[0];
+  ym = m[0];
 }
 
 // One block of kSpecT frequencies of image n after the forward pass of
@@ -71,11 +78,19 @@ __device__ __forceinline__ void spec_item(double* red, int blk, int n, int nblk,
   const int64_t fn = f < D ? neg_index(f, T, H, W) : 0;
   if (f < D && fn >= f) {  // the pair (f, -f) is handled once, by its lower index
     const float rho = rho_cur[n], inv_rho = 1.0f / rho;
+    // the per-image spectra at f and -f do not depend on the group sums:
+    // (for J = 1) their loads go out first
+    float2 l0[J == 1 ? 2 : 1], y0[J == 1 ? 2 : 1], t0[J == 1 ? 2 : 1];
+    if constexpr (J == 1) {
+      const int64_t o = int64_t(n) * D;
+      l0[0] = lam[o + f], y0[0] = yh[o + f], t0[0] = Th[o + f];
+      l0[1] = lam[o + fn], y0[1] = yh[o + fn], t0[1] = Th[o + fn];
+    }
     float2 ys[J];  // yhat' at f; at -f it is the conjugate
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       float2 y, ym;
-      group_sums(part + (int64_t(n) * ng * J + j) * D, int64_t(J) * D, ng, f, fn, y, ym);
+      group_sums<J == 1 ? 16 : 8>(part + (int64_t(n) * ng * J + j) * D, int64_t(J) * D, ng, f, fn, y, ym);
       ys[j] = make_float2(0.5f * (y.x + ym.x), 0.5f * (y.y - ym.y));
     }
     for (int side = 0; side < (fn == f ? 1 : 2); ++side) {
@@ -85,7 +100,8 @@ __device__ __forceinline__ void spec_item(double* red, int blk, int n, int nblk,
 #pragma unroll
       for (int j = 0; j < J; ++j) {
         ynew[j] = side ? cconj(ys[j]) : ys[j];
-        l[j] = lam[(int64_t(n) * J + j) * D + ff];
+        if constexpr (J == 1) l[j] = l0[side];
+        else l[j] = lam[(int64_t(n) * J + j) * D + ff];
       }
 #pragma unroll
       for (int j = 0; j < J; ++j) {
@@ -93,7 +109,14 @@ __device__ __forceinline__ void spec_item(double* red, int blk, int n, int nblk,
 #pragma unroll
         for (int c = 0; c < J; ++c) gl = cadd(gl, cmul(Gf[j * J + c], l[c]));
         const int64_t o = (int64_t(n) * J + j) * D + ff;
-        const float2 yo = yh[o], tho = Th[o];
+        float2 yo, tho;
+        if constexpr (J == 1) {
+          yo = y0[side];
+          tho = t0[side];
+        } else {
+          yo = yh[o];
+          tho = Th[o];
+        }
         thn[j] = make_float2(gl.x + (ynew[j].x - yo.x) * inv_rho, gl.y + (ynew[j].y - yo.y) * inv_rho);
         const double dx = (double)thn[j].x - tho.x, dy = (double)thn[j].y - tho.y;
         ds += dx * dx + dy * dy;
