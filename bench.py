@@ -20,9 +20,10 @@ the same step.
 
 ``--calibrate-copy MIB`` only runs a plain device copy of that size (the
 reference kernel for scaling the FETCH_SIZE / WRITE_SIZE counters);
-``--profile-leg`` runs only the timed calls of the batched leg, of the
-plain solver of the differentiable leg, or of that leg's forward + backward
-(``unrolled``), for kernel traces and counter collection.
+``--profile-leg`` runs only the timed calls of one leg (the step's coding
+call, the batched leg, the plain solver of the differentiable leg or that
+leg's forward + backward, the tensor or the variant legs), for kernel
+traces and counter collection.
 """
 import argparse
 import json
@@ -112,6 +113,19 @@ def calibrate_copy(mib):
         y.copy_(x)
     torch.cuda.synchronize()
     print(json.dumps({"calibrate_copy_mib": mib, "bytes_each_way": n * 4}))
+
+
+def bench_coding(dc, synth, np, torch, calls=20):
+    """The step's coding call alone (10 images 128^2, K = 100, beta = 1,
+    adaptive rho from 10, 10 iterations from zero codes): one warm-up call
+    and `calls` timed ones, for kernel traces and counter collection."""
+    cfg = synth.CONFIGS["learn"]
+    b, d0 = synth.make_inputs(cfg)
+    bt = torch.from_numpy(b).cuda()
+    d = torch.from_numpy(d0).cuda()
+    run = lambda: dc.code(bt, d, cfg.beta, cfg.rho0, cfg.t_in, adaptive=True)
+    return {"workload": "coding of the learning step's images: N=10 128x128, K=100 11x11, beta=1, adaptive rho "
+                        "from 10, 10 iterations", "ms_per_call": timed_ms(torch, run, calls)}
 
 
 def bench_batched(dc, synth, np, torch, n_images, plain=True, tune=True):
@@ -443,7 +457,7 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-all-cores", type=int, default=0, metavar="PROCS", help=argparse.SUPPRESS)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB")
-    ap.add_argument("--profile-leg", choices=["batched", "unrolled-plain", "unrolled", "tensor", "variants"],
+    ap.add_argument("--profile-leg", choices=["coding", "batched", "unrolled-plain", "unrolled", "tensor", "variants"],
                     default=None,
                     help="run only the timed calls of one leg (for counter collection)")
     ap.add_argument("--sweep", default=None, metavar="NAMES",
@@ -478,6 +492,9 @@ def main():
     import synth
 
     dc.load()
+    if args.profile_leg == "coding":
+        print(json.dumps(bench_coding(dc, synth, np, torch)))
+        return
     if args.profile_leg == "batched":
         print(json.dumps(bench_batched(dc, synth, np, torch, args.batched_images, plain=False, tune=False)))
         return
