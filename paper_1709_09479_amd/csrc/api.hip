@@ -82,6 +82,7 @@ int make_plan(const csc_shape* s, Plan* pl) {
   p.msz = int64_t(p.fs[0]) * p.fs[1] * p.fs[2];
   p.lds = (p.g[0] == 1) && tile_supported(p.g[1], p.g[2]);
   p.split = !p.lds && split_supported(p.g[0], p.g[1], p.g[2]);
+  p.vol = !p.lds && !p.split && vol_supported(p.g[0], p.g[1], p.g[2]);
   set_grouping(&p, 0);
   *pl = p;
   return CSC_OK;

@@ -609,8 +609,14 @@ static hipError_t iterate_maps(const Plan& pl, CodeWs& w, float* z, float* theta
     return hipGetLastError();
   }
   if (pl.split) return split_maps(pl, w.E, w.lam, w.buf, z, theta, w.rho, beta, w.part, w.rpri, 0, st, stop, zin);
+  hipError_t e;
+  if (pl.vol) {
+    if ((e = vol_maps(pl, w.E, w.lam, w.buf, z, theta, w.rho, beta, w.rpri, st, stop)) != hipSuccess) return e;
+    LAUNCH_J(k_accum, pl.j, dim3(nblk(D), pl.n), dim3(kEW), st, w.buf, w.E, w.part, pl.p, D, stop);
+    return hipGetLastError();
+  }
   LAUNCH_J(k_make_v, pl.j, dim3(nblk(D), pl.p, pl.n), dim3(kEW), st, w.E, w.lam, w.buf, pl.p, D, stop);
-  hipError_t e = fft_grids(w.buf, int64_t(pl.n) * pl.p, pl.g, +1, st);
+  e = fft_grids(w.buf, int64_t(pl.n) * pl.p, pl.g, +1, st);
   if (e != hipSuccess) return e;
   if (pl.nuclear) {
     // z holds the input codes (copied from zin above when given)

@@ -24,6 +24,7 @@ struct Plan {
   bool lds = false;                // whole grid fits one LDS tile (fused path)
   bool split = false;              // 2-D grid beyond one tile: row / column / row phases
   bool nuclear = false;            // nuclear-norm regulariser (maps through the global path)
+  bool vol = false;                // 3-D grid, T <= 16 frames of a single-tile plane (volume.hip)
   int ng = 1;                      // pair groups per image in the fused kernel
   int ppg = 1;                     // pairs per group
   // Optional device tables (batched form): element offset of image n's
@@ -63,6 +64,14 @@ int split_row_blocks(const Plan& pl);
 hipError_t split_maps(const Plan& pl, const float2* E, const float2* lam, float2* buf, float* z, float* theta,
                       const float* rho, float beta, float2* part, double* rpart, int mode, hipStream_t st,
                       const int* stop, const float* zin = nullptr);
+
+// 3-D grids with 2 <= T <= 16 frames of a plane that fits one LDS tile: the
+// coding map work in three launches per iteration (volume.hip).  Residual
+// partials go to rpart [N][P * nblk(D)] (one slot per 256 grid points of a
+// pair, as on the axis-pass path; the unused slots hold zeros).
+bool vol_supported(int T, int H, int W);
+hipError_t vol_maps(const Plan& pl, const float2* E, const float2* lam, float2* buf, float* z, float* theta,
+                    const float* rho, float beta, double* rpart, hipStream_t st, const int* stop);
 
 // Workspace carving: aligned sub-buffers of one caller-provided block.
 struct Carver {
