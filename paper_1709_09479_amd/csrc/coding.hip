@@ -524,7 +524,10 @@ static bool fused_dispatch(const Plan& pl, const float2* E, const float2* lam, f
 size_t carve_code(const Plan& pl, void* base, CodeWs* w) {
   Carver c(base);
   const int64_t D = pl.dsz, N = pl.n, J = pl.j, P = pl.p;
-  w->ngp = (pl.lds || pl.split) ? pl.ng : 1;
+  // single-tile plans with J > 1 write pair spectra to buf and reduce them
+  // with k_accum into one partial per image
+  const bool tile1 = pl.lds && pl.j == 1;
+  w->ngp = (tile1 || pl.split) ? pl.ng : 1;
   w->npri = pl.lds ? pl.ng : pl.split ? int(P * split_col_blocks(pl)) : int(P * nblk(D));
   w->ndual = (int)nblk(D);
   w->E = c.take<float2>(J * P * D);
@@ -534,7 +537,7 @@ size_t carve_code(const Plan& pl, void* base, CodeWs* w) {
   w->Th = c.take<float2>(N * J * D);
   w->lam = c.take<float2>(N * J * D);
   w->part = c.take<float2>(N * w->ngp * J * D);
-  w->buf = pl.lds ? nullptr : c.take<float2>(N * P * D);
+  w->buf = tile1 ? nullptr : c.take<float2>(N * P * D);
   w->rpri = c.take<double>(N * w->npri);
   w->rdual = c.take<double>(N * w->ndual);
   w->opart = c.take<double>(N * w->ndual);
@@ -571,9 +574,10 @@ hipError_t setup_spectra(const Plan& pl, const float* b, const float* d, CodeWs&
 hipError_t forward_maps(const Plan& pl, const float* maps, CodeWs& w, double* l1, hipStream_t st) {
   const int64_t D = pl.dsz;
   if (pl.lds) {
-    if (!fused_dispatch<kModeForward>(pl, w.E, w.lam, const_cast<float*>(maps), nullptr, w.rho, 0.f, w.part, l1,
-                                      st))
+    if (!fused_dispatch<kModeForward>(pl, w.E, w.lam, const_cast<float*>(maps), nullptr, w.rho, 0.f,
+                                      pl.j == 1 ? w.part : w.buf, l1, st))
       return hipErrorInvalidValue;
+    if (pl.j > 1) LAUNCH_J(k_accum, pl.j, dim3(nblk(D), pl.n), dim3(kEW), st, w.buf, w.E, w.part, pl.p, D, nullptr);
     return hipGetLastError();
   }
   if (pl.split)
@@ -604,8 +608,10 @@ static hipError_t iterate_maps(const Plan& pl, CodeWs& w, float* z, float* theta
   if (pl.lds) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     trace.events(&e0, &e1);
-    if (!fused_dispatch<kModeIter>(pl, w.E, w.lam, z, theta, w.rho, beta, w.part, w.rpri, st, stop, e0, e1))
+    if (!fused_dispatch<kModeIter>(pl, w.E, w.lam, z, theta, w.rho, beta, pl.j == 1 ? w.part : w.buf, w.rpri, st,
+                                   stop, e0, e1))
       return hipErrorInvalidValue;
+    if (pl.j > 1) LAUNCH_J(k_accum, pl.j, dim3(nblk(D), pl.n), dim3(kEW), st, w.buf, w.E, w.part, pl.p, D, stop);
     return hipGetLastError();
   }
   if (pl.split) return split_maps(pl, w.E, w.lam, w.buf, z, theta, w.rho, beta, w.part, w.rpri, 0, st, stop, zin);

@@ -144,7 +144,7 @@ __device__ __forceinline__ void spec_item(double* red, int blk, int n, int nblk,
 
 // Threads per workgroup of the fused kernel: 32 elements per thread (512
 // threads for the largest tiles).  J = 1 keeps its accumulator in
-// registers; J > 1 accumulates into its partial slice in global memory.
+// registers; J > 1 writes each pair's spectrum, which k_accum reduces.
 constexpr int fused_threads(int t, int j) {
   return j == 1 ? (t >= 16384 ? 1024 : (t / 32 < 64 ? 64 : t / 32))
                 : (t >= 16384 ? 1024 : (t / 16 < 64 ? 64 : t / 16));
@@ -163,7 +163,9 @@ enum { kModeIter = 0, kModeForward = 1 };
 // memory, its last pass leaves D^T lam in registers for the soft threshold,
 // whose result feeds the first forward pass from registers; the last forward
 // pass leaves the spectrum in registers for the accumulation.
-// part [N][ng][J][D]; rpart [N][ng] (sum (z'-z)^2, or sum |z| when forward).
+// part: J = 1 [N][ng][D] (the group's sum over its pairs); J > 1 [N][P][D]
+// (each pair's spectrum C, reduced over the pairs by k_accum);
+// rpart [N][ng] (sum (z'-z)^2, or sum |z| when forward).
 template <int H, int W, int J, int MODE, int NT>
 __device__ __forceinline__ void fused_item(float2* tile, const float2* tw, double* red, int n, int g,
                                            const float2* __restrict__ E, const float2* __restrict__ lam,
