@@ -282,8 +282,14 @@ __global__ __launch_bounds__(kSpecT) void kb_spec(ItemLaunch L) {
   while (next_item(L, &slot, c, local) >= 0) {
     const ItemCls& C = L.c[c];
     const int nblk = (C.h * C.w + kSpecT - 1) / kSpecT;
-    spec_item<1>(red, local % nblk, local / nblk, nblk, C.part, C.G, C.xh, C.yh, C.Th, C.lam, C.rho, C.rdual, C.ng,
-                 1, C.h, C.w, L.solve_next);
+    // the accumulator count of the plain solver's choice for this class
+    // (k_spec or k_spec_wide), so the batch equals it bit for bit
+    if (C.ng > 8)
+      spec_item<1, 16>(red, local % nblk, local / nblk, nblk, C.part, C.G, C.xh, C.yh, C.Th, C.lam, C.rho, C.rdual,
+                       C.ng, 1, C.h, C.w, L.solve_next);
+    else
+      spec_item<1, 8>(red, local % nblk, local / nblk, nblk, C.part, C.G, C.xh, C.yh, C.Th, C.lam, C.rho, C.rdual,
+                      C.ng, 1, C.h, C.w, L.solve_next);
   }
 }
 

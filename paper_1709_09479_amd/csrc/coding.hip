@@ -182,18 +182,24 @@ __global__ void k_solve(const float2* __restrict__ G, const float2* __restrict__
   for (int j = 0; j < J; ++j) lam[(int64_t(n) * J + j) * D + f] = l[j];
 }
 
-template <int J>
-__global__ __launch_bounds__(kSpecT) void k_spec(const float2* __restrict__ part, const float2* __restrict__ G,
-                                                 const float2* __restrict__ xh, float2* __restrict__ yh,
-                                                 float2* __restrict__ Th, float2* __restrict__ lam,
-                                                 const float* __restrict__ rho_cur, double* __restrict__ rdual,
-                                                 int ng, int T, int H, int W, int solve_next,
-                                                 const int* __restrict__ stop) {
-  if (stop && stop[0]) return;
-  __shared__ double red[kSpecT / 64];
-  spec_item<J>(red, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, part, G, xh, yh, Th, lam, rho_cur, rdual, ng,
-               T, H, W, solve_next);
-}
+#define SPEC_KERNEL(NAME, U)                                                                                   \
+  template <int J>                                                                                             \
+  __global__ __launch_bounds__(kSpecT) void NAME(                                                              \
+      const float2* __restrict__ part, const float2* __restrict__ G, const float2* __restrict__ xh,           \
+      float2* __restrict__ yh, float2* __restrict__ Th, float2* __restrict__ lam,                              \
+      const float* __restrict__ rho_cur, double* __restrict__ rdual, int ng, int T, int H, int W,             \
+      int solve_next, const int* __restrict__ stop) {                                                          \
+    if (stop && stop[0]) return;                                                                               \
+    __shared__ double red[kSpecT / 64];                                                                        \
+    spec_item<J, U>(red, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, part, G, xh, yh, Th, lam, rho_cur,  \
+                    rdual, ng, T, H, W, solve_next);                                                           \
+  }
+// k_spec sums the group partials with 8 accumulators; k_spec_wide, for
+// single-tile plans with many groups, with 16 (more loads in flight, more
+// registers)
+SPEC_KERNEL(k_spec, 8)
+SPEC_KERNEL(k_spec_wide, 16)
+#undef SPEC_KERNEL
 
 // Residual norms per image (Boyd et al. 2011, Sec. 3.3) and the residual
 // balancing rule (Sec. 3.4.1): r_pri = ||z' - z|| / rho, r_dual = rho
@@ -738,8 +744,12 @@ int run_code(const Plan& pl, const float* b, const float* d, float beta, float* 
     const int solve_next = (!last && !adaptive) ? 1 : 0;
     {
       TraceScope trace(kTraceCodeSpec, st, true);
-      LAUNCH_J_TRACED(trace, k_spec, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.part, w.G, w.xh, w.yh, w.Th, w.lam, w.rho,
-               w.rdual, w.ngp, T, H, W, solve_next, stop);
+      if (pl.j == 1 && w.ngp > 8)
+        LAUNCH_J_TRACED(trace, k_spec_wide, 1, dim3(nblk(D), N), dim3(kEW), st, w.part, w.G, w.xh, w.yh, w.Th,
+                        w.lam, w.rho, w.rdual, w.ngp, T, H, W, solve_next, stop);
+      else
+        LAUNCH_J_TRACED(trace, k_spec, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.part, w.G, w.xh, w.yh, w.Th, w.lam,
+                        w.rho, w.rdual, w.ngp, T, H, W, solve_next, stop);
     }
     if (rec) save_spec(rec);
     if (adaptive && !last && !tol_mode) {
@@ -787,8 +797,15 @@ hipError_t replay_code(const Plan& pl, CodeWs& w, const float* rho, float beta, 
     hipError_t e = iterate_maps(pl, w, zi, zi + nz, beta, st, nullptr, zprev);
     if (e != hipSuccess) return e;
     if (i < nstates - 1)
-      LAUNCH_J(k_spec, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.part, w.G, w.xh, w.yh, w.Th, w.lam, w.rho, w.rdual,
-               w.ngp, T, H, W, 1, nullptr);
+      {
+        // the same kernel as the forward loop, so the states agree bit for bit
+        if (pl.j == 1 && w.ngp > 8)
+          LAUNCH_J(k_spec_wide, 1, dim3(nblk(D), N), dim3(kEW), st, w.part, w.G, w.xh, w.yh, w.Th, w.lam, w.rho,
+                   w.rdual, w.ngp, T, H, W, 1, nullptr);
+        else
+          LAUNCH_J(k_spec, pl.j, dim3(nblk(D), N), dim3(kEW), st, w.part, w.G, w.xh, w.yh, w.Th, w.lam, w.rho,
+                   w.rdual, w.ngp, T, H, W, 1, nullptr);
+      }
   }
   return hipGetLastError();
 }

@@ -66,7 +66,9 @@ __device__ __forceinline__ void group_sums(const float2* __restrict__ part, int6
 // residual by Parseval) and, when the step size is fixed, the next lam.  The
 // thread of the lower index of each pair (f, -f) does both frequencies, so
 // part is read once.
-template <int J>
+// U: group accumulators (2 U loads in flight); 16 pays where there are many
+// groups (single-tile plans), 8 keeps registers low otherwise.
+template <int J, int U>
 __device__ __forceinline__ void spec_item(double* red, int blk, int n, int nblk, const float2* __restrict__ part,
                                           const float2* __restrict__ G, const float2* __restrict__ xh,
                                           float2* __restrict__ yh, float2* __restrict__ Th, float2* __restrict__ lam,
@@ -90,7 +92,7 @@ __device__ __forceinline__ void spec_item(double* red, int blk, int n, int nblk,
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       float2 y, ym;
-      group_sums<J == 1 ? 16 : 8>(part + (int64_t(n) * ng * J + j) * D, int64_t(J) * D, ng, f, fn, y, ym);
+      group_sums<U>(part + (int64_t(n) * ng * J + j) * D, int64_t(J) * D, ng, f, fn, y, ym);
       ys[j] = make_float2(0.5f * (y.x + ym.x), 0.5f * (y.y - ym.y));
     }
     for (int side = 0; side < (fn == f ? 1 : 2); ++side) {
