@@ -37,6 +37,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 TRACE_EVERY = 32  # timed steps time every 32nd launch of a traced kernel (from the first)
 FP32_VECTOR_TFLOPS = 157.3     # MI355X fp32 vector (packed); 78.6 unpacked
+FP64_VECTOR_TFLOPS = 78.6      # MI355X fp64 vector (and fp64 matrix)
 
 
 def alg_bytes_per_iter(n, j, k, d):
@@ -62,6 +63,24 @@ def alg_bytes_pass_b(n, j, k, h, w):
     (H/2+1) W), the CG vector read and the result written (16 N J D)."""
     p = (k + 1) // 2
     return 8 * n * p * h * w + 16 * j * p * (h // 2 + 1) * w + 16 * n * j * h * w
+
+
+def span_apply_flops(j, k, m1, m2):
+    """Float64 flops of one product with the correlation table in the span
+    form of the learning CG: every output tap of every filter sums over all
+    filters and taps, (M w)_k(q) = sum_l sum_q' C_kl(q - q') w_l(q'), i.e.
+    J K^2 (M1 M2)^2 multiply-adds."""
+    return 2.0 * j * k * k * (m1 * m2) ** 2
+
+
+def span_rows_flops(n, j, k, h, w, m2):
+    """Float64 flops of the row stage of the correlation table for the pairs
+    the learning call uses (code-code k <= l, code-x and code-gamma per
+    channel, three per channel among x and gamma): per pair and frequency of
+    the H/2+1 canonical rows, N complex multiply-adds for the sum over
+    images and 2 M2 real multiply-adds per output lag pair (+-delta2)."""
+    pairs = k * (k + 1) // 2 + 2 * j * k + 3 * j
+    return 8.0 * pairs * (h // 2 + 1) * w * (n + m2)
 
 
 def csrc_digest():
@@ -549,6 +568,8 @@ def main():
     spec_ms, spec_cnt = dc.trace_read(dc.TRACE_CODE_SPEC)
     la_ms, la_cnt = dc.trace_read(dc.TRACE_LEARN_A)
     lb_ms, lb_cnt = dc.trace_read(dc.TRACE_LEARN_B)
+    sr_ms, sr_cnt = dc.trace_read(dc.TRACE_LEARN_SPAN_ROWS)
+    sa_ms, sa_cnt = dc.trace_read(dc.TRACE_LEARN_SPAN_APPLY)
 
     cpit_step = N * K * D * cfg.t_in
     value = cpit_step / (ms_step / 1e3)
@@ -577,23 +598,20 @@ def main():
 
     def hbm_roofline(kernel, alg_bytes, ms_total, count, traffic):
         avg = ms_total / max(1, count)
-        ach = alg_bytes / (avg / 1e3) / 1e9
+        ach = alg_bytes / (avg / 1e3) / 1e9 if count else 0.0
         return {"kernel": kernel, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "avg_launch_ms": avg, "launches": count,
                 "alg_bytes_per_launch": alg_bytes}
 
-    roof_a = hbm_roofline("l_passA_rows<1> (learning pass A: sum over images of conj(zhat) p, row stage of "
-                          "the support projection)", alg_bytes_pass_a(N, J, K, H, W, cfg.fsupp[0], cfg.fsupp[1]), la_ms,
-                          la_cnt, counter_traffic("l_passA_rows<1>"))
-    # the learning passes stream the N K D code spectra, which stay in the
-    # Infinity Cache across the step: the HBM peak bounds them from above,
-    # a plain copy of such a set is the practical ceiling
-    cache_note = ("working set %.1f MB of code spectra, resident in the 256 MB Infinity Cache across the step; "
-                  "a plain copy of a set that size reaches ~6.9 TB/s" % (4e-6 * N * K * D))
-    roof_a["working_set"] = cache_note
-    roof_b = hbm_roofline("l_passB_c<1> (learning pass B: p + sum over filters of zhat U)",
-                          alg_bytes_pass_b(N, J, K, H, W), lb_ms, lb_cnt, counter_traffic("l_passB_c<1>"))
-    roof_b["working_set"] = cache_note
+    def alu_roofline(kernel, flops, ms_total, count, traffic):
+        avg = ms_total / max(1, count)
+        ach = flops / (avg / 1e3) / 1e12 if count else 0.0
+        return {"kernel": kernel, "bound": "alu", "achieved": ach, "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / FP64_VECTOR_TFLOPS, "traffic": traffic, "avg_launch_ms": avg, "launches": count,
+                "flops_per_launch": flops,
+                "peak_note": "fp64 vector peak of MI355X (256 CUs x 2.4 GHz x 128 flop/clk); the kernel is "
+                             "float64 multiply-adds on LDS-staged operands"}
+
     roof_fused = {
         "kernel": "k_fused<128,128,1,iter> (back-projection + inverse FFT + soft threshold + forward FFT)",
         "bound": "hbm",
@@ -607,6 +625,44 @@ def main():
         "alg_bytes_per_launch": bytes_launch,
         "alu_tflops": flop_launch / (fused_avg_ms / 1e3) / 1e12,
     }
+    # per-step time of each candidate for the headline entry: the kernel the
+    # step spends most time in
+    steps_learn = cfg.learn_inner * (cfg.learn_cg + 1)
+    share = {"coding_fused": fused_avg_ms * cfg.t_in}
+    extra = {"coding_fused": roof_fused}
+    if sa_cnt:
+        M1, M2 = cfg.fsupp
+        extra["learning_span_apply"] = alu_roofline(
+            "l_cc_apply<11, 11> (learning CG step in the span form: filter-space vector times the float64 lag "
+            "correlations of the code maps)", span_apply_flops(J, K, M1, M2), sa_ms, sa_cnt,
+            counter_traffic("l_cc_apply<11,11>"))
+        share["learning_span_apply"] = sa_ms / sa_cnt * steps_learn
+        extra["learning_span_rows"] = alu_roofline(
+            "l_cc_rows (row stage of the code-map correlation table, once per learning call)",
+            span_rows_flops(N, J, K, H, W, M2), sr_ms, sr_cnt, counter_traffic("l_cc_rows"))
+        share["learning_span_rows"] = sr_ms / max(1, sr_cnt)
+    if la_cnt:
+        # the learning passes stream the N K D code spectra, which stay in the
+        # Infinity Cache across the step: the HBM peak bounds them from above,
+        # a plain copy of such a set is the practical ceiling
+        cache_note = ("working set %.1f MB of code spectra, resident in the 256 MB Infinity Cache across the "
+                      "step; a plain copy of a set that size reaches ~6.9 TB/s" % (4e-6 * N * K * D))
+        extra["learning_pass_a"] = hbm_roofline(
+            "l_passA_rows<1> (learning pass A: sum over images of conj(zhat) p, row stage of the support "
+            "projection)", alg_bytes_pass_a(N, J, K, H, W, cfg.fsupp[0], cfg.fsupp[1]), la_ms, la_cnt,
+            counter_traffic("l_passA_rows<1>"))
+        extra["learning_pass_a"]["working_set"] = cache_note
+        share["learning_pass_a"] = la_ms / la_cnt * steps_learn
+    if lb_cnt:
+        extra["learning_pass_b"] = hbm_roofline(
+            "l_passB_c<1> (learning pass B: p + sum over filters of zhat U)", alg_bytes_pass_b(N, J, K, H, W),
+            lb_ms, lb_cnt, counter_traffic("l_passB_c<1>"))
+        share["learning_pass_b"] = lb_ms / lb_cnt * (steps_learn if la_cnt else 1)
+    head = max(share, key=share.get)
+    roof = dict(extra.pop(head))
+    roof["ms_per_step_in_kernel"] = share[head]
+    for key in extra:
+        extra[key]["ms_per_step_in_kernel"] = share.get(key)
 
     out = {
         "metric": "ADMM coding iters/sec (N·K·pixels/s) + HBM GB/s; batched & backward vs plain",
@@ -629,8 +685,9 @@ def main():
             "n": N, "j": J, "k": K, "grid": [H, W], "fsupp": list(cfg.fsupp), "t_in": cfg.t_in,
             "learn_inner": cfg.learn_inner, "learn_cg": cfg.learn_cg,
         },
-        "roofline": roof_a,
-        "roofline_extra": {"learning_pass_b": roof_b, "coding_fused": roof_fused},
+        "roofline": roof,
+        "roofline_kernel": head,
+        "roofline_extra": extra,
         "coding_only": {
             "ms_per_call": code_ms,
             "cp_it_per_s": cpit_step / (code_ms / 1e3),
@@ -641,6 +698,8 @@ def main():
             "coding_spectral": spec_ms / max(1, spec_cnt),
             "learning_pass_a": la_ms / max(1, la_cnt),
             "learning_pass_b": lb_ms / max(1, lb_cnt),
+            "learning_span_rows": sr_ms / max(1, sr_cnt),
+            "learning_span_apply": sa_ms / max(1, sa_cnt),
         },
         "objective_last": float(state["obj"][-1].item()),
     }

@@ -82,6 +82,13 @@ extern "C" {
                                  otherwise); theta, resid, adaptive rho and the stopping rule
                                  keep their meaning. */
 
+#define CSC_LEARN_DIRECT 0x40u /* csc_learn: apply the operator of eq:Learning_gamma to the
+                                  full CG vectors in every step (two passes over the code
+                                  spectra), instead of carrying the CG in the span of x, the
+                                  warm start and the code-filter products, which is otherwise
+                                  chosen where it is modelled to be cheaper; both give the
+                                  same iterates up to rounding. */
+
 typedef struct csc_shape {
   int32_t abi_version; /* must equal CSC_ABI_VERSION */
   int32_t n;           /* images N */
@@ -224,7 +231,12 @@ int csc_code_tol(const csc_shape* shape, const float* b, const float* d, float b
  *   mu     [K] in/out multipliers (> 0 on entry).
  *   gamma  [N][J][grid] in/out dual variable (warm start unless
  *          CSC_GAMMA_ZERO).
- *   flags  CSC_GAMMA_ZERO, CSC_USE_GRAPH.
+ *   flags  CSC_GAMMA_ZERO, CSC_USE_GRAPH, CSC_LEARN_DIRECT.
+ * On 2-D grids (up to 256 x 256, supports up to 16 x 16) the CG is carried,
+ * where that is modelled to be cheaper, in the span of x, the warm start and
+ * the products Z S^T w (w a filter-support vector): a CG step is then one
+ * product of the filter-space vector with the lag correlations of the code
+ * maps, in float64, and gamma is formed once at the end.
  *   Errors: CSC_EINVAL for a bad shape, inner_iters < 1, cg_iters < 0, NULL
  *           pointers; CSC_EWORKSPACE; CSC_EHIP.
  */
@@ -393,7 +405,11 @@ int csc_batch_autotune(const csc_batch* batch, const float* b, const float* d,
  *   2 = learning pass A kernel (sum over images of conj(zhat) times the CG
  *       vector, eq:Learning_gamma; one record per launch),
  *   3 = learning pass B kernel (sum over filters of zhat times the projected
- *       filter spectra; one record per launch).
+ *       filter spectra; one record per launch),
+ *   4 = learning span form, row stage of the code-map correlation table
+ *       (one launch per learning call),
+ *   5 = learning span form, product of a filter-space vector with the
+ *       correlation table (one launch per CG step and per multiplier step).
  * Calls captured into a hipGraph (CSC_USE_GRAPH) record nothing.
  * Errors: CSC_EINVAL (bad class or NULL outputs), CSC_EHIP.
  */

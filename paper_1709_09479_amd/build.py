@@ -14,7 +14,7 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libdualcsc.so")
 BUILD = os.path.join(PKG, "_build")
 SOURCES = ["api.hip", "coding.hip", "split.hip", "learning.hip", "fftops.hip", "batched.hip", "diff.hip",
-           "nuclear.hip", "dct.hip", "volume.hip"]
+           "nuclear.hip", "dct.hip", "volume.hip", "learnspan.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

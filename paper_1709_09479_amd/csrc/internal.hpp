@@ -94,6 +94,22 @@ hipError_t fft_grids(float2* data, int64_t count, const int g[3], int dir, hipSt
 // Whether the fused single-tile kernels exist for this (H, W).
 bool tile_supported(int h, int w);
 
+// Learning in the span form (learnspan.hip): the CG vectors of a learning
+// call carried as coordinates on {x, gamma_0} plus a filter-space vector,
+// the operator applied through the lag correlations of the code maps.
+// Eligible plans: 2-D grids up to 256 x 256, supports up to 16 x 16.
+bool span_eligible(const Plan& pl);
+// Whether the span form's modelled cost is below the direct form's.
+bool span_preferred(const Plan& pl, int inner_iters, int cg_iters);
+size_t span_ws_bytes(const Plan& pl);
+// From the code, image and warm-start spectra (Zh pair-packed, xh, gh full
+// grids): inner_iters multiplier steps of cg_iters CG steps each; writes d,
+// mu, and for the final gamma the spectrum a xhat + b gammahat_0 to vout and
+// the pair-unpacked canonical spectra of its filter-space part to Uc (pass B
+// of Uc onto vout then gives gammahat).
+hipError_t run_span(const Plan& pl, const float2* Zh, const float2* xh, const float2* gh, float2* vout, float4* Uc,
+                    float* d, float* mu, int inner_iters, int cg_iters, void* span_ws, hipStream_t st);
+
 // Workspace of the coding / objective paths (carved from the caller's block).
 struct CodeWs {
   float2 *E, *G, *xh, *yh, *Th, *lam, *part, *buf;
@@ -174,7 +190,15 @@ hipError_t launch_check_finite(const float* x, int64_t n, int* flag, hipStream_t
 // launches with hipExtLaunchKernelGGL and the scope's events (events()):
 // the runtime then stamps them at that kernel's own start and end, so the
 // time excludes the dispatch around it.
-enum TraceClass { kTraceCodeMaps = 0, kTraceCodeSpec = 1, kTraceLearnA = 2, kTraceLearnB = 3, kTraceClasses = 4 };
+enum TraceClass {
+  kTraceCodeMaps = 0,
+  kTraceCodeSpec = 1,
+  kTraceLearnA = 2,
+  kTraceLearnB = 3,
+  kTraceLearnSpanRows = 4,
+  kTraceLearnSpanApply = 5,
+  kTraceClasses = 6
+};
 struct TraceScope {
   TraceScope(int cls, hipStream_t st, bool own_launch = false);
   ~TraceScope();

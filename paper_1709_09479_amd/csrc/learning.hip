@@ -825,6 +825,7 @@ struct LearnWs {
   int* cgf;           // tolerance mode: CG stop flag of the current multiplier step
   int nB;  // pruned path: pass-B partials per channel (one per workgroup)
   int npartB, npartS;  // partial counts per channel: pass B, vector-update kernel
+  void* span;          // span-form workspace (eligible plans), else NULL
 };
 
 static size_t carve_learn(const Plan& pl, void* base, LearnWs* w) {
@@ -847,6 +848,7 @@ static size_t carve_learn(const Plan& pl, void* base, LearnWs* w) {
   w->bb = c.take<double>(J);
   w->cgf = c.take<int>(1);
   w->nB = (int)canon_blocks(pl) * passb_chunks(pl);
+  w->span = span_eligible(pl) ? c.take<char>(span_ws_bytes(pl)) : nullptr;
   return c.off;
 }
 
@@ -973,6 +975,15 @@ int run_learn(const Plan& pl, const float* b, const float* z, float* d, float* m
   const double tol2 = (double)cg_tol * (double)cg_tol;
   if (tol_mode) hipLaunchKernelGGL(l_norm2, dim3((unsigned)J), dim3(kLW), 0, st, w.xh, w.bb, (int)N, (int)J, D);
   const int npB = pruned ? w.nB : w.npartB;
+  // span form (fixed CG counts, no per-step counts asked for): gamma ends in
+  // gh as pass B of its filter-space part onto a xhat + b gammahat_0
+  const bool span = pruned && w.span && !tol_mode && !cg_counts && !(flags & CSC_LEARN_DIRECT) &&
+                    span_preferred(pl, inner_iters, cg_iters);
+  if (span) {
+    if (run_span(pl, w.Zh, w.xh, w.gh, w.rh, w.Uc, d, mu, inner_iters, cg_iters, w.span, st) != hipSuccess)
+      return CSC_EHIP;
+    pruned_passB(pl, w, w.rh, w.gh, nullptr, w.dots, nullptr, st, nullptr);
+  }
   // the operator A v = v + sum_k 1/(2 mu_k) Z_k S^T S Z_k^T v into q (with xh:
   // q = -x - A v), dot partials as pruned_passB
   auto apply_A = [&](const float2* v, float2* q, const float2* xh, double* part, double* vpart,
@@ -987,7 +998,7 @@ int run_learn(const Plan& pl, const float* b, const float* z, float* d, float* m
     }
     return hipGetLastError();
   };
-  for (int it = 0; it < inner_iters; ++it) {
+  for (int it = 0; !span && it < inner_iters; ++it) {
     int* cnt = cg_counts ? cg_counts + it : nullptr;
     if (tol_mode) hipLaunchKernelGGL(l_cg_reset, dim3(1), dim3(64), 0, st, cgf, cnt);
     else if (cnt) hipLaunchKernelGGL(l_cg_reset, dim3(1), dim3(64), 0, st, w.cgf, cnt);

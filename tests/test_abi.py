@@ -130,7 +130,7 @@ def test_trace_argument_errors():
     lib = dc.load()
     assert lib.csc_trace_enable(-1) == -1
     ms, cnt = ctypes.c_double(), ctypes.c_int()
-    assert lib.csc_trace_read(4, ctypes.byref(ms), ctypes.byref(cnt)) == -1
+    assert lib.csc_trace_read(6, ctypes.byref(ms), ctypes.byref(cnt)) == -1
     assert lib.csc_trace_read(-1, ctypes.byref(ms), ctypes.byref(cnt)) == -1
     assert lib.csc_trace_read(0, None, ctypes.byref(cnt)) == -1
     with pytest.raises(ValueError):
