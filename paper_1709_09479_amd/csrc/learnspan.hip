@@ -66,14 +66,20 @@ __device__ __forceinline__ void tile_pair(int t, int LT, int& A, int& B) {
 //   Tr_ab(f1, delta2) = sum_f2 R_ab(f1, f2) e^{+2 pi i f2 delta2 / W}
 // for |delta2| < M2 (both signs from one set of products).  The spectra go
 // through LDS a chunk of kFC frequencies x kNC images at a time; the loads of
-// the next chunk are in flight while the current one is summed.
+// the next chunk are in flight while the current one is summed.  The chunk's
+// R and its twiddles e^{2 pi i f2 delta2 / W} (delta2 < 16) take the LDS of
+// the staged spectra once those are summed.
 __global__ __launch_bounds__(256) void l_cc_rows(const float2* __restrict__ Zh, const float2* __restrict__ xh,
                                                  const float2* __restrict__ gh, double2* __restrict__ Tr, int N,
                                                  int K, int P, int J, int H, int W, int M2, int LT, int NTP) {
   static_assert(2 * kNC * kFC == 256, "one (tile, image, frequency) of the chunk per thread");
-  __shared__ double2 ys[2][kTL][kNC][kFC];
-  __shared__ double2 rh[kNP][kFC + 1];
+  constexpr int kYs = 2 * kTL * kNC * kFC;  // staged spectra (double2)
+  static_assert(kNP * (kFC + 1) + kFC * 16 <= kYs, "R and the chunk twiddles fit the staging LDS");
+  __shared__ double2 lds[kYs];
   __shared__ double2 tw[256];
+  auto ys = [&](int side, int m, int nl, int fl) -> double2& { return lds[((side * kTL + m) * kNC + nl) * kFC + fl]; };
+  double2* rh = lds;                        // [kNP][kFC + 1]
+  double2* twc = lds + kNP * (kFC + 1);     // [kFC][16]
   const int tid = threadIdx.x;
   const int item = xcd_item((int)blockIdx.x, (int)gridDim.x);
   const int f1 = item / NTP, tpi = item % NTP;
@@ -89,45 +95,63 @@ __global__ __launch_bounds__(256) void l_cc_rows(const float2* __restrict__ Zh, 
   const int nnc = (N + kNC - 1) / kNC, nfc = (W + kFC - 1) / kFC, nchunk = nnc * nfc;
   // A thread stages one (tile, image, frequency) of the chunk for the tile's
   // 8 maps, as 4 slots of two maps (2s, 2s + 1): code maps come as one pair
-  // spectrum and its mirror, x and gamma_0 maps one value each.
+  // spectrum and its mirror, x and gamma_0 maps one value each.  Per slot:
+  // the row bases and the image stride.
   const int sl_side = tid / (kNC * kFC), sl_n = (tid / kFC) % kNC, sl_f = tid % kFC;
   const int sl_base = (sl_side ? B : A) * kTL;
-  float2 pc[4], pm[4], p1[4];
-  auto xg = [&](int a, int n, int64_t f) -> float2 {
-    return a < K + J ? xh[(int64_t(n) * J + (a - K)) * D + f] : gh[(int64_t(n) * J + (a - K - J)) * D + f];
+  const float2* bc[4];
+  const float2* bm[4];
+  const float2* b1[4];
+  int64_t st0[4];
+  int kind0[4];  // 0 none, 1 code pair, 2 x or gamma_0
+  bool has1[4];
+  const int64_t JD = int64_t(J) * D, PD = int64_t(P) * D;
+  auto xg_row = [&](int a, int64_t row) -> const float2* {
+    return (a < K + J ? xh + (a - K) * D : gh + (a - K - J) * D) + row;
   };
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int a0 = sl_base + 2 * u, a1 = a0 + 1;
+    bc[u] = bm[u] = b1[u] = Zh;
+    st0[u] = 0;
+    kind0[u] = a0 < K ? 1 : (a0 < K + 2 * J ? 2 : 0);
+    has1[u] = a1 >= K && a1 < K + 2 * J;
+    if (kind0[u] == 1) {
+      bc[u] = Zh + (a0 >> 1) * D + int64_t(f1) * W;
+      bm[u] = Zh + (a0 >> 1) * D + int64_t(fm1) * W;
+      st0[u] = PD;
+    } else if (kind0[u] == 2) {
+      bc[u] = xg_row(a0, int64_t(f1) * W);
+      st0[u] = JD;
+    }
+    if (has1[u]) b1[u] = xg_row(a1, int64_t(f1) * W);
+  }
+  float2 pc[4], pm[4], p1[4];
   auto issue = [&](int ci) {
     const int n = (ci % nnc) * kNC + sl_n, f2 = (ci / nnc) * kFC + sl_f;
     const bool ok = n < N && f2 < W;
-    const int64_t f = int64_t(f1) * W + f2, fm = int64_t(fm1) * W + ((W - f2) & (W - 1));
+    const int fn = (W - f2) & (W - 1);
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int a0 = sl_base + 2 * u, a1 = a0 + 1;
       pc[u] = pm[u] = p1[u] = make_float2(0.f, 0.f);
       if (!ok) continue;
-      if (a0 < K) {
-        const float2* zp = Zh + (int64_t(n) * P + (a0 >> 1)) * D;
-        pc[u] = zp[f];
-        pm[u] = zp[fm];
-      } else if (a0 < K + 2 * J) {
-        pc[u] = xg(a0, n, f);
-      }
-      if (a1 >= K && a1 < K + 2 * J) p1[u] = xg(a1, n, f);
+      if (kind0[u] != 0) pc[u] = bc[u][n * st0[u] + f2];
+      if (kind0[u] == 1) pm[u] = bm[u][n * st0[u] + fn];
+      if (has1[u]) p1[u] = b1[u][n * JD + f2];
     }
   };
   auto commit = [&]() {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int a0 = sl_base + 2 * u, a1 = a0 + 1;
       float2 v0 = pc[u], v1 = p1[u];
-      if (a0 < K) {
+      if (kind0[u] == 1) {
         // zhat_2p = (C + conj(C(-f)))/2, zhat_2p+1 = -i (C - conj(C(-f)))/2
         const float2 c = pc[u], cm = pm[u];
         v0 = make_float2(0.5f * (c.x + cm.x), 0.5f * (c.y - cm.y));
-        if (a1 < K) v1 = make_float2(0.5f * (c.y + cm.y), -0.5f * (c.x - cm.x));
+        if (!has1[u]) v1 = make_float2(0.5f * (c.y + cm.y), -0.5f * (c.x - cm.x));
       }
-      ys[sl_side][2 * u][sl_n][sl_f] = make_double2(v0.x, v0.y);
-      ys[sl_side][2 * u + 1][sl_n][sl_f] = make_double2(v1.x, v1.y);
+      ys(sl_side, 2 * u, sl_n, sl_f) = make_double2(v0.x, v0.y);
+      ys(sl_side, 2 * u + 1, sl_n, sl_f) = make_double2(v1.x, v1.y);
     }
   };
   // product tasks: a 2 x 2 block of pairs at one frequency of the chunk
@@ -143,52 +167,67 @@ __global__ __launch_bounds__(256) void l_cc_rows(const float2* __restrict__ Zh, 
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = make_double2(0.0, 0.0);
+  auto product = [&](int nl) {
+    const double2 a0 = ys(0, ai, nl, fl), a1 = ys(0, ai + 1, nl, fl);
+    const double2 b0 = ys(1, bi, nl, fl), b1v = ys(1, bi + 1, nl, fl);
+    // conj(a) b; the spectra are float32 values, whose products are exact
+    acc[0][0].x += a0.x * b0.x + a0.y * b0.y;
+    acc[0][0].y += a0.x * b0.y - a0.y * b0.x;
+    acc[0][1].x += a0.x * b1v.x + a0.y * b1v.y;
+    acc[0][1].y += a0.x * b1v.y - a0.y * b1v.x;
+    acc[1][0].x += a1.x * b0.x + a1.y * b0.y;
+    acc[1][0].y += a1.x * b0.y - a1.y * b0.x;
+    acc[1][1].x += a1.x * b1v.x + a1.y * b1v.y;
+    acc[1][1].y += a1.x * b1v.y - a1.y * b1v.x;
+  };
   issue(0);
   for (int ci = 0; ci < nchunk; ++ci) {
     const int f2c = (ci / nnc) * kFC, n0 = (ci % nnc) * kNC;
-    __syncthreads();  // earlier readers of ys are done
+    __syncthreads();  // earlier readers of the staging LDS are done
     commit();
     if (ci + 1 < nchunk) issue(ci + 1);
     __syncthreads();
     const int nn = min(kNC, N - n0);
-    for (int nl = 0; nl < nn; ++nl) {
-      const double2 a0 = ys[0][ai][nl][fl], a1 = ys[0][ai + 1][nl][fl];
-      const double2 b0 = ys[1][bi][nl][fl], b1 = ys[1][bi + 1][nl][fl];
-      // conj(a) b; the spectra are float32 values, whose products are exact
-      acc[0][0].x += a0.x * b0.x + a0.y * b0.y;
-      acc[0][0].y += a0.x * b0.y - a0.y * b0.x;
-      acc[0][1].x += a0.x * b1.x + a0.y * b1.y;
-      acc[0][1].y += a0.x * b1.y - a0.y * b1.x;
-      acc[1][0].x += a1.x * b0.x + a1.y * b0.y;
-      acc[1][0].y += a1.x * b0.y - a1.y * b0.x;
-      acc[1][1].x += a1.x * b1.x + a1.y * b1.y;
-      acc[1][1].y += a1.x * b1.y - a1.y * b1.x;
+    if (nn == kNC) {
+#pragma unroll
+      for (int nl = 0; nl < kNC; ++nl) product(nl);
+    } else {
+      for (int nl = 0; nl < nn; ++nl) product(nl);
     }
     if (ci % nnc != nnc - 1) continue;
-    // the chunk's frequencies are complete: lag sums over them
+    // the chunk's frequencies are complete: R and the twiddles replace the
+    // staged spectra, then the lag sums over the chunk
+    __syncthreads();
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
       for (int y = 0; y < 2; ++y) {
-        rh[(ai + x) * kTL + bi + y][fl] = acc[x][y];
+        rh[((ai + x) * kTL + bi + y) * (kFC + 1) + fl] = acc[x][y];
         acc[x][y] = make_double2(0.0, 0.0);
       }
+    twc[tid] = tw[((f2c + (tid >> 4)) * (tid & 15)) & (W - 1)];
     __syncthreads();
     const int nf = min(kFC, W - f2c);
-    for (int e = 0; e < nf; ++e) {
-      const int f2 = f2c + e;
-      const double2 r = rh[pi][e];
+    const double2* rp = rh + pi * (kFC + 1);
+    const double2* tp = twc + g;
+    auto lag_step = [&](int e) {
+      const double2 r = rp[e];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int dl = g + 4 * v;
-        if (dl < M2) {
-          const double2 c = tw[(f2 * dl) & (W - 1)];
+        if (g + 4 * v < M2) {
+          const double2 c = tp[e * 16 + 4 * v];
           trc[v] += r.x * c.x;
           tis[v] += r.y * c.y;
           trs[v] += r.x * c.y;
           tic[v] += r.y * c.x;
         }
       }
+    };
+    if (nf == kFC) {
+#pragma unroll
+      for (int e = 0; e < kFC; ++e) lag_step(e);
+    } else {
+      for (int e = 0; e < nf; ++e) lag_step(e);
     }
   }
   const int E2 = 2 * M2 - 1;
