@@ -832,18 +832,19 @@ bool span_eligible(const Plan& pl) {
   return tr < 2147483648.0 && cc < 2147483648.0;
 }
 
-// Modelled time of one learning call in each form (seconds), from the work
-// each does: the direct form streams the code spectra twice per operator
-// product (about 4 TB/s on cache-resident sets) plus four launches; the span
-// form builds the correlation table once (float64 multiply-adds at about
-// 15 T/s) and then costs one product with M plus two launches per step.
+// Modelled time of one learning call in each form (seconds), with rates
+// measured on the benchmark's call: the direct form streams the code
+// spectra twice per CG step (about 4 TB/s on cache-resident sets) plus ~15 us
+// of small launches; the span form builds the correlation table once (about
+// 8e12 float64 multiply-adds/s, ~70 us for the column stage) and then costs
+// one product with M (about 6e12 multiply-adds/s) and ~8 us per step.
 bool span_preferred(const Plan& pl, int inner_iters, int cg_iters) {
   const SpanDims s = span_dims(pl);
   const double steps = double(inner_iters) * (cg_iters + 1);
   const double D = double(pl.g[1]) * pl.g[2];
-  const double direct = steps * (2.0 * pl.n * pl.p * D * 8.0 / 4e12 + 4 * 3e-6);
-  const double table = double(s.Hc) * pl.g[2] * s.NTP * kNP * (pl.n + 2.0 * s.M2) * 4.0 / 1.5e13;
-  const double span = table + steps * (double(s.K) * s.K * s.MM * s.MM * s.J / 1.5e13 + 2 * 3e-6);
+  const double direct = steps * (2.0 * pl.n * pl.p * D * 8.0 / 4e12 + 15e-6);
+  const double table = double(s.Hc) * pl.g[2] * s.NTP * kNP * (pl.n + s.M2) * 4.0 / 8e12 + 70e-6;
+  const double span = table + steps * (double(s.J) * s.K * s.K * s.MM * s.MM / 6e12 + 8e-6);
   return span < direct;
 }
 
