@@ -50,6 +50,15 @@ constexpr int kSpanLds = 80 * 1024;  // LDS budget of one product workgroup (byt
 enum { kAX, kBX, kAR, kBR, kAP, kBP, kAS, kBS, kGP, kALP, kNS };
 enum { kModeSetup = 0, kModeInit = 1, kModeStep = 2, kModeDrec = 3 };
 
+// Stride (doubles) of one (k, l) lag table, in memory and in the product
+// kernel's LDS: at least E1 E2 and = M1 E2 mod 16, so that thread (l, q1) reads row
+// entries at E2 (M1 l + q1) + const mod 16, i.e. consecutive threads hit
+// distinct 8-byte bank pairs (E2 is odd).
+__host__ __device__ constexpr int span_lag_stride(int M1, int M2) {
+  const int E2 = 2 * M2 - 1, EE = (2 * M1 - 1) * E2;
+  return EE + (((M1 * E2 - EE) % 16) + 16) % 16;
+}
+
 // Tile pair index t (A <= B, row-major over the upper triangle) -> (A, B).
 __device__ __forceinline__ void tile_pair(int t, int LT, int& A, int& B) {
   A = 0;
@@ -255,7 +264,7 @@ __global__ __launch_bounds__(256) void l_cc_lags(const double2* __restrict__ Tr,
                                                  double* __restrict__ s0, int K, int J, int H, int W, int M1,
                                                  int M2, int LT, int NTP) {
   __shared__ double2 tw[256];
-  const int E1 = 2 * M1 - 1, E2 = 2 * M2 - 1, EE = E1 * E2, MM = M1 * M2;
+  const int E2 = 2 * M2 - 1, MM = M1 * M2, EP = span_lag_stride(M1, M2);
   const int per = kNP * E2, bpt = (per + 255) / 256;
   const int tpi = blockIdx.x / bpt, idx = (blockIdx.x % bpt) * 256 + threadIdx.x;
   for (int i = threadIdx.x; i < H; i += 256) {
@@ -303,11 +312,11 @@ __global__ __launch_bounds__(256) void l_cc_lags(const double2* __restrict__ Tr,
     for (int v = 0; v < 16; ++v) {
       if (v < M1) {
         const double cp = (sc[v] - ss[v]) * invD, cn = (sc[v] + ss[v]) * invD;  // delta1 = +v, -v
-        C[(int64_t(a) * K + b) * EE + (M1 - 1 + v) * E2 + e2] = cp;
-        if (v > 0) C[(int64_t(a) * K + b) * EE + (M1 - 1 - v) * E2 + e2] = cn;
+        C[(int64_t(a) * K + b) * EP + (M1 - 1 + v) * E2 + e2] = cp;
+        if (v > 0) C[(int64_t(a) * K + b) * EP + (M1 - 1 - v) * E2 + e2] = cn;
         if (a != b) {
-          C[(int64_t(b) * K + a) * EE + (M1 - 1 - v) * E2 + (E2 - 1 - e2)] = cp;
-          if (v > 0) C[(int64_t(b) * K + a) * EE + (M1 - 1 + v) * E2 + (E2 - 1 - e2)] = cn;
+          C[(int64_t(b) * K + a) * EP + (M1 - 1 - v) * E2 + (E2 - 1 - e2)] = cp;
+          if (v > 0) C[(int64_t(b) * K + a) * EP + (M1 - 1 + v) * E2 + (E2 - 1 - e2)] = cn;
         }
       }
     }
@@ -319,15 +328,6 @@ __global__ __launch_bounds__(256) void l_cc_lags(const double2* __restrict__ Tr,
   } else {
     s0[(kind - 4) * J + j] = (sc[0] - ss[0]) * invD;
   }
-}
-
-// LDS stride (doubles) of one input filter's lag table in the product
-// kernel: at least E1 E2 and = M1 E2 mod 16, so that thread (l, q1) reads row
-// entries at E2 (M1 l + q1) + const mod 16, i.e. consecutive threads hit
-// distinct 8-byte bank pairs (E2 is odd).
-__host__ __device__ constexpr int span_lag_stride(int M1, int M2) {
-  const int E2 = 2 * M2 - 1, EE = (2 * M1 - 1) * E2;
-  return EE + (((M1 * E2 - EE) % 16) + 16) % 16;
 }
 
 // dst[(i / seg) * dstride + i % seg] = src[i], i < count, by the workgroup:
@@ -364,14 +364,14 @@ __global__ __launch_bounds__(256) void l_cc_apply(const double* __restrict__ C, 
   extern __shared__ double smem[];
   constexpr int E2 = 2 * M2 - 1;
   const int M1 = MR > 0 ? MR : M1r;
-  const int E1 = 2 * M1 - 1, EE = E1 * E2, MM = M1 * M2, EP = span_lag_stride(M1, M2);
+  const int MM = M1 * M2, EP = span_lag_stride(M1, M2);
   const int item = xcd_item((int)blockIdx.x, (int)gridDim.x);
   const int k = item / LC, lc = item % LC;
   const int l0 = lc * LCH, nl = min(LCH, K - l0);
   const int tid = threadIdx.x, bd = blockDim.x;
   double* Cs = smem;                   // [nl][EP]
   double* ts = Cs + LCH * EP;          // [J][LCH][MM], then the row sums [nl][J][MM]
-  stage_block(Cs, C + (int64_t(k) * K + l0) * EE, nl * EE, EE, EP);
+  stage_block(Cs, C + (int64_t(k) * K + l0) * EP, nl * EP);
   for (int j = 0; j < J; ++j) stage_block(ts + j * LCH * MM, t + (int64_t(j) * K + l0) * MM, nl * MM);
   __syncthreads();
   const int ntask = nl * J * M1;
@@ -806,7 +806,7 @@ size_t carve_span(const Plan& pl, void* base, SpanWs* w) {
   Carver c(base);
   const int64_t JKM = int64_t(s.J) * s.K * s.MM;
   w->Tr = c.take<double2>(int64_t(s.Hc) * s.NTP * kNP * s.E2);
-  w->C = c.take<double>(int64_t(s.K) * s.K * s.EE);
+  w->C = c.take<double>(int64_t(s.K) * s.K * span_lag_stride(s.M1, s.M2));
   w->gx = c.take<double>(JKM);
   w->g0 = c.take<double>(JKM);
   w->s0 = c.take<double>(3 * s.J);

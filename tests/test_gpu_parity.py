@@ -170,7 +170,7 @@ def learn_tol(d_ref):
 
 
 @pytest.mark.parametrize("direct", [False, True], ids=["span", "direct"])
-@pytest.mark.parametrize("grid,j,k", [((64, 64), 1, 8), ((64, 64), 1, 7), ((32, 64), 3, 6),
+@pytest.mark.parametrize("grid,j,k", [((64, 64), 1, 8), ((64, 64), 1, 7), ((64, 64), 2, 6), ((32, 64), 3, 6),
                                       ((128, 128), 3, 5), ((256, 256), 1, 4)])
 def test_learn(lib, grid, j, k, direct):
     """Both forms of the learning CG (the span form the library picks for
