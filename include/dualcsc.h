@@ -88,6 +88,9 @@ extern "C" {
                                   warm start and the code-filter products, which is otherwise
                                   chosen where it is modelled to be cheaper; both give the
                                   same iterates up to rounding. */
+#define CSC_LEARN_SPAN 0x80u   /* csc_learn: the span form wherever the plan allows it (2-D
+                                  grids up to 256 x 256, supports up to 16 x 16), whatever
+                                  the cost model says; with CSC_LEARN_DIRECT, CSC_EINVAL. */
 
 typedef struct csc_shape {
   int32_t abi_version; /* must equal CSC_ABI_VERSION */
@@ -231,7 +234,7 @@ int csc_code_tol(const csc_shape* shape, const float* b, const float* d, float b
  *   mu     [K] in/out multipliers (> 0 on entry).
  *   gamma  [N][J][grid] in/out dual variable (warm start unless
  *          CSC_GAMMA_ZERO).
- *   flags  CSC_GAMMA_ZERO, CSC_USE_GRAPH, CSC_LEARN_DIRECT.
+ *   flags  CSC_GAMMA_ZERO, CSC_USE_GRAPH, CSC_LEARN_DIRECT, CSC_LEARN_SPAN.
  * On 2-D grids (up to 256 x 256, supports up to 16 x 16) the CG is carried,
  * where that is modelled to be cheaper, in the span of x, the warm start and
  * the products Z S^T w (w a filter-support vector): a CG step is then one

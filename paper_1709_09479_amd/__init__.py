@@ -32,7 +32,7 @@ OK, EINVAL, EWORKSPACE, EUNSUPPORTED, EHIP, ENONFINITE, ESCRATCH = 0, -1, -2, -3
 NOALLOC_SCRATCH_BYTES = 64 << 20
 OP_CODE, OP_LEARN, OP_OBJECTIVE, OP_DCT = 1, 2, 3, 4
 ADAPTIVE_RHO, Z_ZERO, THETA_ZERO, GAMMA_ZERO, USE_GRAPH, NUCLEAR = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
-LEARN_DIRECT = 0x40
+LEARN_DIRECT, LEARN_SPAN = 0x40, 0x80
 _REG_FLAGS = {"l1": 0, "nuclear": NUCLEAR}
 
 
@@ -284,14 +284,15 @@ def code(b, d, beta: float, rho, iters: int, z=None, theta=None, adaptive: bool 
 
 
 def learn(b, z, fsupp: Sequence[int], mu=None, gamma=None, inner_iters: int = 10, cg_iters: int = 10,
-          out=None, graph: bool = False, direct: bool = False):
+          out=None, graph: bool = False, form: str = "auto"):
     """Dual dictionary learning (eq:Learning_gamma, eq:Learning_Solution,
     eq:mu_update).  Returns (d [K][J][*fsupp], mu [K], gamma [N][J][*grid]);
     mu and gamma are updated in place when given; ``out`` receives d.  With
     ``graph`` the call is captured once and replayed when called again with
-    the same tensors.  ``direct`` keeps the operator on the full CG vectors
-    (CSC_LEARN_DIRECT) where the library would otherwise carry the CG in its
-    span form."""
+    the same tensors.  ``form`` picks the CG's form: "auto" (the library's
+    cost model), "direct" (the operator on the full CG vectors,
+    CSC_LEARN_DIRECT) or "span" (the span form wherever the plan allows it,
+    CSC_LEARN_SPAN)."""
     torch = _torch()
     lib = load()
     _need(b, "b")
@@ -311,8 +312,9 @@ def learn(b, z, fsupp: Sequence[int], mu=None, gamma=None, inner_iters: int = 10
     d = out if out is not None else torch.empty((K, J) + fsupp, dtype=torch.float32, device=dev)
     _need(d, "out")
     ws, nbytes = _workspace(shape, OP_LEARN, flags, dev)
-    if direct:
-        flags |= LEARN_DIRECT
+    if form not in ("auto", "direct", "span"):
+        raise ValueError("form must be 'auto', 'direct' or 'span'")
+    flags |= {"auto": 0, "direct": LEARN_DIRECT, "span": LEARN_SPAN}[form]
     with _GraphStream(graph) as st:
         rc = lib.csc_learn(ctypes.byref(shape), _ptr(b), _ptr(z), _ptr(d), _ptr(mu), _ptr(gamma),
                            int(inner_iters), int(cg_iters), flags | (USE_GRAPH if graph else 0), ws, nbytes, st)

@@ -360,7 +360,8 @@ int csc_learn(const csc_shape* shape, const float* b, const float* z, float* d, 
   int rc = make_plan(shape, &pl);
   if (rc != CSC_OK) return rc;
   if (!b || !z || !d || !mu || !gamma || inner_iters < 1 || cg_iters < 0) return CSC_EINVAL;
-  if (flags & ~(CSC_GAMMA_ZERO | CSC_USE_GRAPH | CSC_LEARN_DIRECT)) return CSC_EINVAL;
+  if (flags & ~(CSC_GAMMA_ZERO | CSC_USE_GRAPH | CSC_LEARN_DIRECT | CSC_LEARN_SPAN)) return CSC_EINVAL;
+  if ((flags & CSC_LEARN_DIRECT) && (flags & CSC_LEARN_SPAN)) return CSC_EINVAL;
   if ((rc = check_ws(ws, ws_bytes, run_learn_ws(pl))) != CSC_OK) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const unsigned f = flags & ~CSC_USE_GRAPH;

@@ -978,7 +978,7 @@ int run_learn(const Plan& pl, const float* b, const float* z, float* d, float* m
   // span form (fixed CG counts, no per-step counts asked for): gamma ends in
   // gh as pass B of its filter-space part onto a xhat + b gammahat_0
   const bool span = pruned && w.span && !tol_mode && !cg_counts && !(flags & CSC_LEARN_DIRECT) &&
-                    span_preferred(pl, inner_iters, cg_iters);
+                    ((flags & CSC_LEARN_SPAN) || span_preferred(pl, inner_iters, cg_iters));
   if (span) {
     if (run_span(pl, w.Zh, w.xh, w.gh, w.rh, w.Uc, d, mu, inner_iters, cg_iters, w.span, st) != hipSuccess)
       return CSC_EHIP;

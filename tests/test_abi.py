@@ -108,6 +108,7 @@ def test_learn_and_objective_argument_errors():
     assert L(inner=0) == dc.EINVAL
     assert L(cg=-1) == dc.EINVAL
     assert L(flags=dc.ADAPTIVE_RHO) == dc.EINVAL
+    assert L(flags=dc.LEARN_DIRECT | dc.LEARN_SPAN) == dc.EINVAL
     assert L(wsb=need_l - 1) == dc.EWORKSPACE
     O = lambda **kw: lib.csc_objective(ctypes.byref(s), FAKE, FAKE, FAKE, kw.get("beta", 1.0), kw.get("out", FAKE),
                                        0x100000, kw.get("wsb", need_o), None)

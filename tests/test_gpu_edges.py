@@ -71,7 +71,8 @@ def test_code_identity_dictionary_soft_threshold(lib):
     ((16, 64), 2, (1, 1), 3, 0.1, 0.01),       # 1 x 1 support (scaled, see below)
     ((128, 128), 4, (7, 11), 1, 10.0, 1.0),    # N = 1, non-square support
 ])
-def test_learn_degenerate_shapes(lib, grid, k, fs, n, amp, beta):
+@pytest.mark.parametrize("form", ["span", "direct"])
+def test_learn_degenerate_shapes(lib, grid, k, fs, n, amp, beta, form):
     """With a 1 x 1 support the learning operator is I plus a rank-K term
     whose eigenvalues are about 1 + |z_k|^2 / (2 mu_k): at the usual
     amplitude (codes ~10 over 3000 pixels) its condition number is ~4e4, and
@@ -83,7 +84,7 @@ def test_learn_degenerate_shapes(lib, grid, k, fs, n, amp, beta):
     assert np.count_nonzero(z) > 0
     mu0 = np.linspace(0.8, 1.5, k).astype(np.float32)
     d_ref, mu_ref, g_ref = oracle.learn(b, z, fs, mu0, None, 3, 6)
-    d, mu, gamma = lib.learn(T(b), T(z), fs, T(mu0), None, 3, 6)
+    d, mu, gamma = lib.learn(T(b), T(z), fs, T(mu0), None, 3, 6, form=form)
     assert np.abs(N(d) - d_ref).max() <= 1e-4 * max(1.0, float(np.abs(d_ref).max()))
     np.testing.assert_allclose(N(mu), mu_ref, rtol=1e-4)
     assert np.abs(N(gamma) - g_ref).max() <= 1e-4 * max(1.0, float(np.abs(g_ref).max()))

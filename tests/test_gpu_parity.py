@@ -169,18 +169,17 @@ def learn_tol(d_ref):
     return 1e-4 * max(1.0, float(np.abs(d_ref).max()))
 
 
-@pytest.mark.parametrize("direct", [False, True], ids=["span", "direct"])
+@pytest.mark.parametrize("form", ["span", "direct"])
 @pytest.mark.parametrize("grid,j,k", [((64, 64), 1, 8), ((64, 64), 1, 7), ((64, 64), 2, 6), ((32, 64), 3, 6),
                                       ((128, 128), 3, 5), ((256, 256), 1, 4)])
-def test_learn(lib, grid, j, k, direct):
-    """Both forms of the learning CG (the span form the library picks for
-    these shapes, and the direct form) against the oracle."""
+def test_learn(lib, grid, j, k, form):
+    """Both forms of the learning CG against the oracle."""
     b, d0 = rand_case(31 + k, 3, j, k, grid, (11, 11))
     z = oracle.code(b, d0, 1.0, 5.0, 10)["z"].astype(np.float32)
     assert density(z) > 0.005
     mu0 = np.linspace(0.8, 1.5, k)
     d_ref, mu_ref, g_ref = oracle.learn(b, z, (11, 11), mu0.astype(np.float32), None, 3, 6)
-    d, mu, gamma = lib.learn(T(b), T(z), (11, 11), T(mu0), None, 3, 6, direct=direct)
+    d, mu, gamma = lib.learn(T(b), T(z), (11, 11), T(mu0), None, 3, 6, form=form)
     assert np.abs(N(d) - d_ref).max() <= learn_tol(d_ref)
     np.testing.assert_allclose(N(mu), mu_ref, rtol=1e-4)
     assert np.abs(N(gamma) - g_ref).max() <= 1e-4 * max(1.0, np.abs(g_ref).max())
@@ -208,11 +207,29 @@ def test_learn_warm_gamma(lib):
     g1 = g1.astype(np.float32)
     mu1 = mu1.astype(np.float32)
     d_ref, mu_ref, g_ref = oracle.learn(b, z, (11, 11), mu1, g1, 2, 5)
-    for direct in (False, True):
-        d, mu, gamma = lib.learn(T(b), T(z), (11, 11), T(mu1), T(g1), 2, 5, direct=direct)
+    for form in ("span", "direct"):
+        d, mu, gamma = lib.learn(T(b), T(z), (11, 11), T(mu1), T(g1), 2, 5, form=form)
         assert np.abs(N(d) - d_ref).max() <= learn_tol(d_ref)
         np.testing.assert_allclose(N(mu), mu_ref, rtol=1e-4)
         assert np.abs(N(gamma) - g_ref).max() <= 1e-4 * max(1.0, np.abs(g_ref).max())
+
+
+@pytest.mark.parametrize("inner,cg", [(2, 0), (1, 1), (1, 3)])
+def test_learn_short_counts(lib, inner, cg):
+    """Edge counts of the learning loop in both forms: no CG step (the
+    filters follow from the warm start alone), a single step, a single
+    multiplier update."""
+    b, d0 = rand_case(61, 2, 1, 5, (64, 64), (11, 11))
+    z = oracle.code(b, d0, 1.0, 5.0, 10)["z"].astype(np.float32)
+    _, mu1, g1 = oracle.learn(b, z, (11, 11), np.ones(5), None, 1, 4)
+    g1 = g1.astype(np.float32)
+    mu1 = mu1.astype(np.float32)
+    d_ref, mu_ref, g_ref = oracle.learn(b, z, (11, 11), mu1, g1, inner, cg)
+    for form in ("span", "direct"):
+        d, mu, gamma = lib.learn(T(b), T(z), (11, 11), T(mu1), T(g1), inner, cg, form=form)
+        assert np.abs(N(d) - d_ref).max() <= learn_tol(d_ref), form
+        np.testing.assert_allclose(N(mu), mu_ref, rtol=1e-4)
+        assert np.abs(N(gamma) - g_ref).max() <= 1e-4 * max(1.0, np.abs(g_ref).max()), form
 
 
 # ------------------------------------------------------------ alternation
