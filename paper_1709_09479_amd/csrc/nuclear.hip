@@ -120,6 +120,90 @@ __global__ __launch_bounds__(kSvtT) void k_svt(float2* __restrict__ buf, float* 
     rc_of(f, r, c);
     Bm[c * LDB + r] = a_at(f);
   }
+  if (mode == 0) {
+    // ---- SVT(A, t) = 0 when every singular value is below t = rho beta,
+    // i.e. when t^2 I - A^T A is positive definite: a Cholesky factorisation
+    // of that NC x NC matrix in LDS (O(NC^3)) settles it before the Jacobi
+    // sweeps (O(sweeps NC^2 NR)).  A failed pivot (or one lost to rounding
+    // at sigma ~ t) leaves the decision to the sweeps.
+    const double t2 = (double)rho * (double)beta * (double)rho * (double)beta;
+    // G = A^T A in 4 x 4 blocks, one block per thread, in registers
+    constexpr int NB4 = NC / 4;
+    static_assert(NB4 * NB4 <= kSvtT, "one 4 x 4 block of A^T A per thread");
+    double g4[4][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) g4[x][y] = 0.0;
+    const int bi = tid / NB4, bj = tid % NB4;
+    __syncthreads();  // A is in Bm
+    if (tid < NB4 * NB4) {
+      for (int r = 0; r < NR; ++r) {
+        double a4[4], b4[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          a4[x] = Bm[(4 * bi + x) * LDB + r];
+          b4[x] = Bm[(4 * bj + x) * LDB + r];
+        }
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) g4[x][y] = fma(a4[x], b4[y], g4[x][y]);
+      }
+    }
+    __syncthreads();  // every thread is done with A
+    // Bm[i][j] <- (t^2 I - A^T A)[i][j]
+    if (tid < NB4 * NB4) {
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+          const int i = 4 * bi + x, j = 4 * bj + y;
+          Bm[i * LDB + j] = (i == j ? t2 : 0.0) - g4[x][y];
+        }
+    }
+    if (tid == 0) flag = 0;
+    for (int j = 0; j < NC; ++j) {
+      __syncthreads();  // the previous step's update (and the flag) are done
+      const double piv = Bm[j * LDB + j];
+      if (!(piv > 0.0)) {  // the same value in every thread: a uniform exit
+        if (tid == 0) flag = 1;
+        break;
+      }
+      const double inv = 1.0 / sqrt(piv);
+      for (int i = j + 1 + tid; i < NC; i += kSvtT) Bm[i * LDB + j] *= inv;
+      __syncthreads();
+      const int m = NC - j - 1;
+      for (int e = tid; e < m * m; e += kSvtT) {
+        const int i = j + 1 + e / m, c = j + 1 + e % m;
+        if (c <= i) Bm[i * LDB + c] -= Bm[i * LDB + j] * Bm[c * LDB + j];
+      }
+    }
+    __syncthreads();
+    if (flag == 0) {
+      // z' = 0: theta' = v - z/rho, the map's pair slot <- 0, rmap = sum z^2
+      const float inv_rho = 1.0f / rho;
+      double rs = 0.0;
+      for (int f = tid; f < D; f += kSvtT) {
+        const float z0 = zsrc[zbase + f];
+        const float v = bcomp[2 * int64_t(f)] * invD;
+        rs = fma((double)z0, (double)z0, rs);
+        z[zbase + f] = 0.f;
+        if (theta) theta[zbase + f] = v - z0 * inv_rho;
+        bcomp[2 * int64_t(f)] = 0.f;
+        if ((K & 1) && k == K - 1) bcomp[2 * int64_t(f) + 1] = 0.f;
+      }
+      const double tot = block_sum(rs, red);
+      if (tid == 0) rmap[int64_t(n) * K + k] = tot;
+      return;
+    }
+    // the sweeps start from A again
+    for (int f = tid; f < D; f += kSvtT) {
+      int r, c;
+      rc_of(f, r, c);
+      Bm[c * LDB + r] = a_at(f);
+    }
+  }
   // ---- one-sided Jacobi sweeps
   const int grp = tid / LP, sub = tid % LP;
   for (int sweep = 0; sweep < kSvtSweeps; ++sweep) {
