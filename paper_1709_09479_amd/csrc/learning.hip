@@ -1028,10 +1028,10 @@ int run_learn(const Plan& pl, const float* b, const float* z, float* d, float* m
       hipLaunchKernelGGL(l_mu_update, dim3(pl.k), dim3(kLW), 0, st, d, mu, int64_t(J) * pl.msz, 1, last ? 1 : 0);
     }
   }
-  // gamma back to the spatial domain
-  hipMemcpyAsync(w.rh, w.gh, sizeof(float2) * ns, hipMemcpyDeviceToDevice, st);
-  if ((e = fft_grids(w.rh, N * J, pl.g, +1, st)) != hipSuccess) return CSC_EHIP;
-  hipLaunchKernelGGL(l_complex_to_real, dim3(lblk(ns)), dim3(kLW), 0, st, w.rh, gamma, ns, 1.0f / (float)D);
+  // gamma back to the spatial domain (in place: its spectrum is not needed
+  // after this)
+  if ((e = fft_grids(w.gh, N * J, pl.g, +1, st)) != hipSuccess) return CSC_EHIP;
+  hipLaunchKernelGGL(l_complex_to_real, dim3(lblk(ns)), dim3(kLW), 0, st, w.gh, gamma, ns, 1.0f / (float)D);
   return hipGetLastError() == hipSuccess ? CSC_OK : CSC_EHIP;
 }
 

@@ -41,8 +41,8 @@ namespace {
 
 constexpr int kTL = 8;           // maps per tile of the correlation table
 constexpr int kNP = kTL * kTL;   // map pairs per tile pair
-constexpr int kFC = 16;          // row frequencies per chunk
-constexpr int kNC = 8;           // images per chunk
+constexpr int kRF = 64;          // row frequencies per chunk of the row stage
+constexpr size_t kRowsLds = size_t(kRF) * (kNP + 1) * 16;  // its R buffer (bytes)
 constexpr int kSpanLds = 80 * 1024;  // LDS budget of one product workgroup (bytes): two per CU
 
 // CG scalars per channel: the (a, b) coordinates of gamma (X), r, p, s and
@@ -69,45 +69,48 @@ __device__ __forceinline__ void tile_pair(int t, int LT, int& A, int& B) {
   B = A + t;
 }
 
+// Twiddles of the row stage, T[f2][v] = e^{+2 pi i f2 v / W} for v < 16.
+__global__ void l_cc_twiddles(double2* __restrict__ T, int W) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= W * 16) return;
+  double s, c;
+  sincospi(2.0 * (((i >> 4) * (i & 15)) & (W - 1)) / W, &s, &c);
+  T[i] = make_double2(c, s);
+}
+
 // Row stage of the correlation table.  Workgroup (row f1, tile pair A <= B)
 // forms R_ab(f1, f2) = sum_n conj(yhat_a^n) yhat_b^n for the 64 pairs of the
 // tile pair and every f2, then
 //   Tr_ab(f1, delta2) = sum_f2 R_ab(f1, f2) e^{+2 pi i f2 delta2 / W}
-// for |delta2| < M2 (both signs from one set of products).  The spectra go
-// through LDS a chunk of kFC frequencies x kNC images at a time; the loads of
-// the next chunk are in flight while the current one is summed.  The chunk's
-// R and its twiddles e^{2 pi i f2 delta2 / W} (delta2 < 16) take the LDS of
-// the staged spectra once those are summed.
+// for |delta2| < M2 (both signs from one set of products), kRF frequencies
+// at a time.  Sum over images: wavefront w holds a 4 x 4 block of pairs, lane
+// = frequency, and reads its 8 maps' spectra from memory straight into
+// registers (each load of a wavefront is 64 consecutive frequencies), the
+// next image's loads in flight while the current one is summed.  Lag sums:
+// the chunk's R goes through LDS, lane = pair, wavefront w takes a quarter
+// of the chunk's frequencies and all lags, with the twiddles the same for
+// every lane (scalar loads); the four partial sums meet in LDS at the end.
+template <int L>  // lag slots per pair: M2 <= L, L even
 __global__ __launch_bounds__(256) void l_cc_rows(const float2* __restrict__ Zh, const float2* __restrict__ xh,
-                                                 const float2* __restrict__ gh, double2* __restrict__ Tr, int N,
-                                                 int K, int P, int J, int H, int W, int M2, int LT, int NTP) {
-  static_assert(2 * kNC * kFC == 256, "one (tile, image, frequency) of the chunk per thread");
-  constexpr int kYs = 2 * kTL * kNC * kFC;  // staged spectra (double2)
-  static_assert(kNP * (kFC + 1) + kFC * 16 <= kYs, "R and the chunk twiddles fit the staging LDS");
-  __shared__ double2 lds[kYs];
-  __shared__ double2 tw[256];
-  auto ys = [&](int side, int m, int nl, int fl) -> double2& { return lds[((side * kTL + m) * kNC + nl) * kFC + fl]; };
-  double2* rh = lds;                        // [kNP][kFC + 1]
-  double2* twc = lds + kNP * (kFC + 1);     // [kFC][16]
-  const int tid = threadIdx.x;
+                                                 const float2* __restrict__ gh, const double2* __restrict__ T,
+                                                 double2* __restrict__ Tr, int N, int K, int P, int J, int H, int W,
+                                                 int M2, int LT, int NTP) {
+  static_assert(L % 2 == 0 && L <= 16, "lag slots");
+  static_assert(3 * 4 * (L / 2) * 64 <= 2 * kRF * (kNP + 1), "partial lag sums fit the R buffer");
+  extern __shared__ double2 rl[];  // [kRF][kNP + 1]
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int item = xcd_item((int)blockIdx.x, (int)gridDim.x);
   const int f1 = item / NTP, tpi = item % NTP;
   int A, B;
   tile_pair(tpi, LT, A, B);
-  for (int i = tid; i < W; i += 256) {
-    double s, c;
-    sincospi(2.0 * i / W, &s, &c);
-    tw[i] = make_double2(c, s);
-  }
   const int64_t D = int64_t(H) * W;
   const int fm1 = (H - f1) & (H - 1);
-  const int nnc = (N + kNC - 1) / kNC, nfc = (W + kFC - 1) / kFC, nchunk = nnc * nfc;
-  // A thread stages one (tile, image, frequency) of the chunk for the tile's
-  // 8 maps, as 4 slots of two maps (2s, 2s + 1): code maps come as one pair
-  // spectrum and its mirror, x and gamma_0 maps one value each.  Per slot:
-  // the row bases and the image stride.
-  const int sl_side = tid / (kNC * kFC), sl_n = (tid / kFC) % kNC, sl_f = tid % kFC;
-  const int sl_base = (sl_side ? B : A) * kTL;
+  // The wavefront's maps, as 4 slots of two maps (2s, 2s + 1): slots 0, 1
+  // are maps 4 qa .. 4 qa + 3 of tile A, slots 2, 3 maps 4 qb .. of tile B.
+  // Code maps come as one pair spectrum and its mirror, x and gamma_0 maps
+  // one value each.
+  const int qa = wv >> 1, qb = wv & 1;
   const float2* bc[4];
   const float2* bm[4];
   const float2* b1[4];
@@ -120,7 +123,7 @@ __global__ __launch_bounds__(256) void l_cc_rows(const float2* __restrict__ Zh, 
   };
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    const int a0 = sl_base + 2 * u, a1 = a0 + 1;
+    const int a0 = u < 2 ? A * kTL + 4 * qa + 2 * u : B * kTL + 4 * qb + 2 * (u - 2), a1 = a0 + 1;
     bc[u] = bm[u] = b1[u] = Zh;
     st0[u] = 0;
     kind0[u] = a0 < K ? 1 : (a0 < K + 2 * J ? 2 : 0);
@@ -135,119 +138,206 @@ __global__ __launch_bounds__(256) void l_cc_rows(const float2* __restrict__ Zh, 
     }
     if (has1[u]) b1[u] = xg_row(a1, int64_t(f1) * W);
   }
-  float2 pc[4], pm[4], p1[4];
-  auto issue = [&](int ci) {
-    const int n = (ci % nnc) * kNC + sl_n, f2 = (ci / nnc) * kFC + sl_f;
-    const bool ok = n < N && f2 < W;
-    const int fn = (W - f2) & (W - 1);
+  // A wavefront whose 4 slots are all code pairs sums, per pair of slots
+  // (A slot s, B slot t) with spectra C, C' and mirrors Cm, Cm', the four
+  // products
+  //   S0 = conj(C) C', S1 = conj(C Cm'), S2 = Cm C', S3 = Cm conj(Cm')
+  // over the images and forms the slots' four map pairs from them at the
+  // end, exactly as the half sums (C + conj(Cm))/2 and -i (C - conj(Cm))/2
+  // would give them; the other wavefronts form the maps' values per image
+  // (in float64, the same half sums to float64 rounding).
+  const bool pure = kind0[0] == 1 && kind0[1] == 1 && kind0[2] == 1 && kind0[3] == 1 && !has1[0] && !has1[1] &&
+                    !has1[2] && !has1[3];
+  double trc[L], tis[L], trs[L], tic[L];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      pc[u] = pm[u] = p1[u] = make_float2(0.f, 0.f);
-      if (!ok) continue;
-      if (kind0[u] != 0) pc[u] = bc[u][n * st0[u] + f2];
-      if (kind0[u] == 1) pm[u] = bm[u][n * st0[u] + fn];
-      if (has1[u]) p1[u] = b1[u][n * JD + f2];
-    }
-  };
-  auto commit = [&]() {
+  for (int v = 0; v < L; ++v) trc[v] = tis[v] = trs[v] = tic[v] = 0.0;
+  for (int f2c = 0; f2c < W; f2c += kRF) {
+    // lanes past W (W < kRF) repeat a frequency; their R is never read
+    const int f2 = (f2c + lane) & (W - 1), fn = (W - f2) & (W - 1);
+    double2 acc[4][4];  // R of pairs (4 qa + x, 4 qb + z)
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      float2 v0 = pc[u], v1 = p1[u];
-      if (kind0[u] == 1) {
-        // zhat_2p = (C + conj(C(-f)))/2, zhat_2p+1 = -i (C - conj(C(-f)))/2
-        const float2 c = pc[u], cm = pm[u];
-        v0 = make_float2(0.5f * (c.x + cm.x), 0.5f * (c.y - cm.y));
-        if (!has1[u]) v1 = make_float2(0.5f * (c.y + cm.y), -0.5f * (c.x - cm.x));
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int z = 0; z < 4; ++z) acc[x][z] = make_double2(0.0, 0.0);
+    if (pure) {
+      double2 S[4][4];  // [2 s + t][product]
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int z = 0; z < 4; ++z) S[x][z] = make_double2(0.0, 0.0);
+      // one base per image, advanced by P D, and per-lane byte offsets
+      // into it: the loads of the 8 spectra take no address arithmetic
+      unsigned oc[4], om[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        oc[u] = (unsigned)((bc[u] - Zh) + f2) * 8u;
+        om[u] = (unsigned)((bm[u] - Zh) + fn) * 8u;
       }
-      ys(sl_side, 2 * u, sl_n, sl_f) = make_double2(v0.x, v0.y);
-      ys(sl_side, 2 * u + 1, sl_n, sl_f) = make_double2(v1.x, v1.y);
-    }
-  };
-  // product tasks: a 2 x 2 block of pairs at one frequency of the chunk
-  const int fl = tid & 15, ab = tid >> 4;
-  const int ai = (ab >> 2) * 2, bi = (ab & 3) * 2;
-  // lag tasks: pair pi, lags delta2 = g, g + 4, g + 8, g + 12
-  const int pi = tid >> 2, g = tid & 3;
-  double trc[4], tis[4], trs[4], tic[4];
+      auto load = [&](float2(&lc)[4], float2(&lm)[4], int n) {
+        const char* zb = reinterpret_cast<const char*>(Zh + n * PD);
 #pragma unroll
-  for (int v = 0; v < 4; ++v) trc[v] = tis[v] = trs[v] = tic[v] = 0.0;
-  double2 acc[2][2];
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int y = 0; y < 2; ++y) acc[x][y] = make_double2(0.0, 0.0);
-  auto product = [&](int nl) {
-    const double2 a0 = ys(0, ai, nl, fl), a1 = ys(0, ai + 1, nl, fl);
-    const double2 b0 = ys(1, bi, nl, fl), b1v = ys(1, bi + 1, nl, fl);
-    // conj(a) b; the spectra are float32 values, whose products are exact
-    acc[0][0].x += a0.x * b0.x + a0.y * b0.y;
-    acc[0][0].y += a0.x * b0.y - a0.y * b0.x;
-    acc[0][1].x += a0.x * b1v.x + a0.y * b1v.y;
-    acc[0][1].y += a0.x * b1v.y - a0.y * b1v.x;
-    acc[1][0].x += a1.x * b0.x + a1.y * b0.y;
-    acc[1][0].y += a1.x * b0.y - a1.y * b0.x;
-    acc[1][1].x += a1.x * b1v.x + a1.y * b1v.y;
-    acc[1][1].y += a1.x * b1v.y - a1.y * b1v.x;
-  };
-  issue(0);
-  for (int ci = 0; ci < nchunk; ++ci) {
-    const int f2c = (ci / nnc) * kFC, n0 = (ci % nnc) * kNC;
-    __syncthreads();  // earlier readers of the staging LDS are done
-    commit();
-    if (ci + 1 < nchunk) issue(ci + 1);
-    __syncthreads();
-    const int nn = min(kNC, N - n0);
-    if (nn == kNC) {
-#pragma unroll
-      for (int nl = 0; nl < kNC; ++nl) product(nl);
-    } else {
-      for (int nl = 0; nl < nn; ++nl) product(nl);
-    }
-    if (ci % nnc != nnc - 1) continue;
-    // the chunk's frequencies are complete: R and the twiddles replace the
-    // staged spectra, then the lag sums over the chunk
-    __syncthreads();
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int y = 0; y < 2; ++y) {
-        rh[((ai + x) * kTL + bi + y) * (kFC + 1) + fl] = acc[x][y];
-        acc[x][y] = make_double2(0.0, 0.0);
-      }
-    twc[tid] = tw[((f2c + (tid >> 4)) * (tid & 15)) & (W - 1)];
-    __syncthreads();
-    const int nf = min(kFC, W - f2c);
-    const double2* rp = rh + pi * (kFC + 1);
-    const double2* tp = twc + g;
-    auto lag_step = [&](int e) {
-      const double2 r = rp[e];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        if (g + 4 * v < M2) {
-          const double2 c = tp[e * 16 + 4 * v];
-          trc[v] += r.x * c.x;
-          tis[v] += r.y * c.y;
-          trs[v] += r.x * c.y;
-          tic[v] += r.y * c.x;
+        for (int u = 0; u < 4; ++u) {
+          lc[u] = *reinterpret_cast<const float2*>(zb + oc[u]);
+          lm[u] = *reinterpret_cast<const float2*>(zb + om[u]);
         }
-      }
-    };
-    if (nf == kFC) {
+      };
+      auto mac = [&](const float2(&lc)[4], const float2(&lm)[4]) {
+        double2 c[4], m[4];
 #pragma unroll
-      for (int e = 0; e < kFC; ++e) lag_step(e);
+        for (int u = 0; u < 4; ++u) {
+          c[u] = make_double2(lc[u].x, lc[u].y);
+          m[u] = make_double2(lm[u].x, lm[u].y);
+        }
+        // float32 values: every product is exact in float64
+#pragma unroll
+        for (int sa = 0; sa < 2; ++sa)
+#pragma unroll
+          for (int tb = 0; tb < 2; ++tb) {
+            const double2 C = c[sa], Cm = m[sa], D2 = c[2 + tb], Dm = m[2 + tb];
+            double2* q = S[2 * sa + tb];
+            q[0].x = fma(C.y, D2.y, fma(C.x, D2.x, q[0].x));
+            q[0].y = fma(-C.y, D2.x, fma(C.x, D2.y, q[0].y));
+            q[1].x = fma(-C.y, Dm.y, fma(C.x, Dm.x, q[1].x));
+            q[1].y = fma(-C.y, Dm.x, fma(-C.x, Dm.y, q[1].y));
+            q[2].x = fma(-Cm.y, D2.y, fma(Cm.x, D2.x, q[2].x));
+            q[2].y = fma(Cm.y, D2.x, fma(Cm.x, D2.y, q[2].y));
+            q[3].x = fma(Cm.y, Dm.y, fma(Cm.x, Dm.x, q[3].x));
+            q[3].y = fma(-Cm.x, Dm.y, fma(Cm.y, Dm.x, q[3].y));
+          }
+      };
+      // Two named buffers: the next image's loads fly while one is summed.
+      // Loads and sums of the loop body are unconditional (the last batch
+      // may repeat image N - 1 and go unused): a load whose only use sits
+      // under a branch is moved next to it, and the loads then wait.
+      float2 la[4], ma[4], lb[4], mb[4];
+      load(la, ma, 0);
+      int n = 0;
+      for (; n + 1 < N; n += 2) {
+        load(lb, mb, n + 1);
+        mac(la, ma);
+        load(la, ma, min(n + 2, N - 1));
+        mac(lb, mb);
+      }
+      if (n < N) mac(la, ma);  // odd N: image N - 1 is in la
+      // with a = S0, b = S1, c = S2, d = S3 of slots s, t:
+      //   R(2s, 2t) = (a + b + c + d)/4,       R(2s, 2t+1) = -i (a - b + c - d)/4,
+      //   R(2s+1, 2t) = i (a + b - c - d)/4,   R(2s+1, 2t+1) = (a - b - c + d)/4
+#pragma unroll
+      for (int sa = 0; sa < 2; ++sa)
+#pragma unroll
+        for (int tb = 0; tb < 2; ++tb) {
+          const double2* q = S[2 * sa + tb];
+          const double2 ab = make_double2(q[0].x + q[1].x, q[0].y + q[1].y);
+          const double2 am = make_double2(q[0].x - q[1].x, q[0].y - q[1].y);
+          const double2 cd = make_double2(q[2].x + q[3].x, q[2].y + q[3].y);
+          const double2 cm = make_double2(q[2].x - q[3].x, q[2].y - q[3].y);
+          const double2 r00 = make_double2(ab.x + cd.x, ab.y + cd.y), r11 = make_double2(am.x - cm.x, am.y - cm.y);
+          const double2 t01 = make_double2(am.x + cm.x, am.y + cm.y), t10 = make_double2(ab.x - cd.x, ab.y - cd.y);
+          acc[2 * sa][2 * tb] = make_double2(0.25 * r00.x, 0.25 * r00.y);
+          acc[2 * sa][2 * tb + 1] = make_double2(0.25 * t01.y, -0.25 * t01.x);
+          acc[2 * sa + 1][2 * tb] = make_double2(-0.25 * t10.y, 0.25 * t10.x);
+          acc[2 * sa + 1][2 * tb + 1] = make_double2(0.25 * r11.x, 0.25 * r11.y);
+        }
     } else {
-      for (int e = 0; e < nf; ++e) lag_step(e);
+      float2 pc[4], pm[4], p1[4];
+      auto issue = [&](int n) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          pc[u] = pm[u] = p1[u] = make_float2(0.f, 0.f);
+          if (kind0[u] != 0) pc[u] = bc[u][n * st0[u] + f2];
+          if (kind0[u] == 1) pm[u] = bm[u][n * st0[u] + fn];
+          if (has1[u]) p1[u] = b1[u][n * JD + f2];
+        }
+      };
+      issue(0);
+      for (int n = 0; n < N; ++n) {
+        double2 y[8];  // maps 4 qa .. 4 qa + 3 of A, then 4 qb .. 4 qb + 3 of B
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          double2 v0 = make_double2(pc[u].x, pc[u].y), v1 = make_double2(p1[u].x, p1[u].y);
+          if (kind0[u] == 1) {
+            // zhat_2p = (C + conj(C(-f)))/2, zhat_2p+1 = -i (C - conj(C(-f)))/2
+            const double cx = pc[u].x, cy = pc[u].y, mx = pm[u].x, my = pm[u].y;
+            v0 = make_double2(0.5 * (cx + mx), 0.5 * (cy - my));
+            if (!has1[u]) v1 = make_double2(0.5 * (cy + my), -0.5 * (cx - mx));
+          }
+          y[2 * u] = v0;
+          y[2 * u + 1] = v1;
+        }
+        if (n + 1 < N) issue(n + 1);
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int z = 0; z < 4; ++z) {
+            const double2 a = y[x], b = y[4 + z];
+            acc[x][z].x = fma(a.y, b.y, fma(a.x, b.x, acc[x][z].x));
+            acc[x][z].y = fma(-a.y, b.x, fma(a.x, b.y, acc[x][z].y));
+          }
+      }
+    }
+    __syncthreads();  // the previous chunk's lag sums are done with rl
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int z = 0; z < 4; ++z) rl[lane * (kNP + 1) + (4 * qa + x) * kTL + 4 * qb + z] = acc[x][z];
+    __syncthreads();
+    const int nf = min(kRF, W - f2c);
+    for (int e = 0; e < kRF / 4; ++e) {
+      const int fl = wv * (kRF / 4) + e;
+      if (fl >= nf) break;
+      const double2 r = rl[fl * (kNP + 1) + lane];
+      // all L slots: the table has 16 lags per frequency, and a slot past
+      // M2 is never written out
+      const double2* tf = T + (f2c + fl) * 16;
+      double2 c[L];
+#pragma unroll
+      for (int v = 0; v < L; ++v) c[v] = tf[v];
+#pragma unroll
+      for (int v = 0; v < L; ++v) {
+        trc[v] = fma(r.x, c[v].x, trc[v]);
+        tis[v] = fma(r.y, c[v].y, tis[v]);
+        trs[v] = fma(r.x, c[v].y, trs[v]);
+        tic[v] = fma(r.y, c[v].x, tic[v]);
+      }
     }
   }
+  // the four wavefronts' partial sums, half of the lag slots at a time
   const int E2 = 2 * M2 - 1;
-  double2* out = Tr + ((int64_t(f1) * NTP + tpi) * kNP + pi) * E2;
+  double2* out = Tr + ((int64_t(f1) * NTP + tpi) * kNP + lane) * E2;
+  double* red = reinterpret_cast<double*>(rl);  // [3][4][L / 2][64]
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int dl = g + 4 * v;
-    if (dl < M2) {
-      // R e^{+i theta} and R e^{-i theta}
-      out[M2 - 1 + dl] = make_double2(trc[v] - tis[v], trs[v] + tic[v]);
-      if (dl > 0) out[M2 - 1 - dl] = make_double2(trc[v] + tis[v], tic[v] - trs[v]);
+  for (int h = 0; h < 2; ++h) {
+    __syncthreads();
+    if (wv > 0) {
+#pragma unroll
+      for (int vl = 0; vl < L / 2; ++vl) {
+        const int v = h * (L / 2) + vl;
+        double* rp = red + ((wv - 1) * 4 * (L / 2) + vl) * 64 + lane;
+        rp[0] = trc[v];
+        rp[(L / 2) * 64] = tis[v];
+        rp[2 * (L / 2) * 64] = trs[v];
+        rp[3 * (L / 2) * 64] = tic[v];
+      }
+    }
+    __syncthreads();
+    if (wv == 0) {
+#pragma unroll
+      for (int vl = 0; vl < L / 2; ++vl) {
+        const int v = h * (L / 2) + vl;
+        if (v >= M2) continue;
+        double sc = trc[v], si = tis[v], ss = trs[v], sk = tic[v];
+#pragma unroll
+        for (int w = 0; w < 3; ++w) {
+          const double* rp = red + (w * 4 * (L / 2) + vl) * 64 + lane;
+          sc += rp[0];
+          si += rp[(L / 2) * 64];
+          ss += rp[2 * (L / 2) * 64];
+          sk += rp[3 * (L / 2) * 64];
+        }
+        // R e^{+i theta} and R e^{-i theta}
+        out[M2 - 1 + v] = make_double2(sc - si, ss + sk);
+        if (v > 0) out[M2 - 1 - v] = make_double2(sc + si, sk - ss);
+      }
     }
   }
 }
@@ -711,8 +801,10 @@ __global__ __launch_bounds__(256) void l_cc_uc(const double* __restrict__ Xw, fl
                                                int J, int H, int W, int M1, int M2) {
   __shared__ float2 cs[16 * 256];
   __shared__ double2 twh[256], tww[256];
+  __shared__ double wk[16 * 16];
   const int k = blockIdx.x, j = blockIdx.y, tid = threadIdx.x;
   const int MM = M1 * M2, nc = (H / 2 + 1) * W;
+  for (int i = tid; i < MM; i += 256) wk[i] = Xw[(int64_t(j) * K + k) * MM + i];
   for (int i = tid; i < 256; i += 256) {
     double s, c;
     if (i < H) {
@@ -725,7 +817,6 @@ __global__ __launch_bounds__(256) void l_cc_uc(const double* __restrict__ Xw, fl
     }
   }
   __syncthreads();
-  const double* wk = Xw + (int64_t(j) * K + k) * MM;
   for (int e = tid; e < M1 * W; e += 256) {
     const int m1 = e / W, f2 = e % W;
     double re = 0.0, im = 0.0;
@@ -796,7 +887,7 @@ SpanDims span_dims(const Plan& pl) {
 }
 
 struct SpanWs {
-  double2* Tr;
+  double2 *Tr, *T;
   double *C, *gx, *g0, *s0, *t, *Mt, *dots, *sc, *mu64;
   SpanVecs v;
 };
@@ -806,6 +897,7 @@ size_t carve_span(const Plan& pl, void* base, SpanWs* w) {
   Carver c(base);
   const int64_t JKM = int64_t(s.J) * s.K * s.MM;
   w->Tr = c.take<double2>(int64_t(s.Hc) * s.NTP * kNP * s.E2);
+  w->T = c.take<double2>(int64_t(pl.g[2]) * 16);
   w->C = c.take<double>(int64_t(s.K) * s.K * span_lag_stride(s.M1, s.M2));
   w->gx = c.take<double>(JKM);
   w->g0 = c.take<double>(JKM);
@@ -827,9 +919,10 @@ bool span_eligible(const Plan& pl) {
   if (pl.g[0] != 1 || H < 2 || W < 2 || H > 256 || W > 256) return false;
   if (pl.fs[1] < 1 || pl.fs[2] < 1 || pl.fs[1] > 16 || pl.fs[2] > 16 || pl.fs[1] > H || pl.fs[2] > W) return false;
   const SpanDims s = span_dims(pl);
-  // the correlation tables stay below 2 GiB each
+  // the correlation tables stay below 2 GiB each, and one image's code
+  // spectra below 4 GiB (the row stage addresses them with 32-bit offsets)
   const double tr = double(s.Hc) * s.NTP * kNP * s.E2 * 16.0, cc = double(s.K) * s.K * s.EE * 8.0;
-  return tr < 2147483648.0 && cc < 2147483648.0;
+  return tr < 2147483648.0 && cc < 2147483648.0 && double(pl.p) * H * W * 8.0 < 4294967296.0;
 }
 
 // Modelled time of one learning call in each form (seconds), with rates
@@ -859,15 +952,38 @@ hipError_t run_span(const Plan& pl, const float2* Zh, const float2* xh, const fl
   carve_span(pl, span_ws, &w);
   const SpanDims s = span_dims(pl);
   const int N = pl.n, H = pl.g[1], W = pl.g[2];
+  hipLaunchKernelGGL(l_cc_twiddles, dim3((unsigned)((W * 16 + 255) / 256)), dim3(256), 0, st, w.T, W);
   {
     TraceScope trace(kTraceLearnSpanRows, st, true);
     hipEvent_t e0, e1;
+    const bool tr = trace.events(&e0, &e1);
     const dim3 grid((unsigned)(s.NTP * s.Hc)), block(256);
-    if (trace.events(&e0, &e1))
-      hipExtLaunchKernelGGL(l_cc_rows, grid, block, 0, st, e0, e1, 0, Zh, xh, gh, w.Tr, N, s.K, pl.p, s.J, H, W, s.M2,
-                            s.LT, s.NTP);
-    else
-      hipLaunchKernelGGL(l_cc_rows, grid, block, 0, st, Zh, xh, gh, w.Tr, N, s.K, pl.p, s.J, H, W, s.M2, s.LT, s.NTP);
+#define SPAN_ROWS(L)                                                                                               \
+  {                                                                                                                \
+    static bool attr_set = false;                                                                                 \
+    if (!attr_set) {                                                                                              \
+      hipFuncSetAttribute(reinterpret_cast<const void*>(&l_cc_rows<L>), hipFuncAttributeMaxDynamicSharedMemorySize, \
+                          (int)kRowsLds);                                                                         \
+      attr_set = true;                                                                                            \
+    }                                                                                                             \
+    if (tr)                                                                                                       \
+      hipExtLaunchKernelGGL(l_cc_rows<L>, grid, block, kRowsLds, st, e0, e1, 0, Zh, xh, gh, w.T, w.Tr, N, s.K,      \
+                            pl.p, s.J, H, W, s.M2, s.LT, s.NTP);                                                 \
+    else                                                                                                          \
+      hipLaunchKernelGGL(l_cc_rows<L>, grid, block, kRowsLds, st, Zh, xh, gh, w.T, w.Tr, N, s.K, pl.p, s.J, H, W,   \
+                         s.M2, s.LT, s.NTP);                                                                      \
+  }
+    switch ((s.M2 + 1) / 2) {
+      case 1: SPAN_ROWS(2) break;
+      case 2: SPAN_ROWS(4) break;
+      case 3: SPAN_ROWS(6) break;
+      case 4: SPAN_ROWS(8) break;
+      case 5: SPAN_ROWS(10) break;
+      case 6: SPAN_ROWS(12) break;
+      case 7: SPAN_ROWS(14) break;
+      default: SPAN_ROWS(16) break;
+    }
+#undef SPAN_ROWS
   }
   const int bpt = (kNP * s.E2 + 255) / 256;
   hipLaunchKernelGGL(l_cc_lags, dim3((unsigned)(s.NTP * bpt)), dim3(256), 0, st, w.Tr, w.C, w.gx, w.g0, w.s0, s.K,
