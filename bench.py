@@ -637,9 +637,10 @@ def main():
             "correlations of the code maps)", span_apply_flops(J, K, M1, M2), sa_ms, sa_cnt,
             counter_traffic("l_cc_apply<11,11>"))
         share["learning_span_apply"] = sa_ms / sa_cnt * steps_learn
+        rows_l = 2 * ((M2 + 1) // 2)  # the row kernel's lag slots (even, >= M2)
         extra["learning_span_rows"] = alu_roofline(
-            "l_cc_rows (row stage of the code-map correlation table, once per learning call)",
-            span_rows_flops(N, J, K, H, W, M2), sr_ms, sr_cnt, counter_traffic("l_cc_rows"))
+            "l_cc_rows<%d> (row stage of the code-map correlation table, once per learning call)" % rows_l,
+            span_rows_flops(N, J, K, H, W, M2), sr_ms, sr_cnt, counter_traffic("l_cc_rows<%d>" % rows_l))
         share["learning_span_rows"] = sr_ms / max(1, sr_cnt)
     if la_cnt:
         # the learning passes stream the N K D code spectra, which stay in the
