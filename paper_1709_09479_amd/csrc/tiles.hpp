@@ -34,19 +34,39 @@ __device__ __forceinline__ void group_sums(const float2* __restrict__ part, int6
   for (int u = 0; u < U; ++u) a[u] = m[u] = make_float2(0.f, 0.f);
   int g = 0;
   for (; g + U <= ng; g += U) {
+    // all 2 U loads first: left to itself the scheduler interleaves each
+    // load with its add through one register pair, one load in flight
+    float2 va[U], vm[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const float2* pp = part + (g + u) * stride_g;
-      a[u] = cadd(a[u], pp[f]);
-      m[u] = cadd(m[u], pp[fn]);
+      va[u] = pp[f];
+      vm[u] = pp[fn];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      a[u] = cadd(a[u], va[u]);
+      m[u] = cadd(m[u], vm[u]);
     }
   }
+  if (g < ng) {
+    // the remaining groups the same way: every load from a valid group
+    // (the last one for slots past ng), weighted by 1 or 0, which adds the
+    // same bits as a plain sum
+    float2 va[U], vm[U];
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    if (g + u < ng) {
-      const float2* pp = part + (g + u) * stride_g;
-      a[u] = cadd(a[u], pp[f]);
-      m[u] = cadd(m[u], pp[fn]);
+    for (int u = 0; u < U; ++u) {
+      const float2* pp = part + min(g + u, ng - 1) * stride_g;
+      va[u] = pp[f];
+      vm[u] = pp[fn];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const float w = g + u < ng ? 1.f : 0.f;
+      a[u] = make_float2(fmaf(w, va[u].x, a[u].x), fmaf(w, va[u].y, a[u].y));
+      m[u] = make_float2(fmaf(w, vm[u].x, m[u].x), fmaf(w, vm[u].y, m[u].y));
     }
   }
 #pragma unroll
