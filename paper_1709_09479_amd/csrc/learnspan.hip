@@ -562,6 +562,23 @@ __global__ __launch_bounds__(256) void l_cc_update(int mode, int first, int drec
   const int k = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int JM = J * MM;
   const bool is_step = mode == kModeStep, is_init = mode == kModeInit;
+  // ---- the previous launch's partial dots (step mode): this lane's
+  // filters kk = lane, lane + 64, .. in batches of four; the first batch's
+  // loads go out here, ahead of the entries', in every mode (dots_in is
+  // valid workspace; only the step mode uses the values; a filter past K
+  // loads the last one and adds 0)
+  double dv[4][4][J];
+  auto dots_batch = [&](int k0) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int kk = min(k0 + 64 * b + lane, K - 1);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int j = 0; j < J; ++j) dv[b][q][j] = dots_in[(int64_t(kk) * 4 + q) * J + j];
+    }
+  };
+  dots_batch(0);
   // ---- loads of this thread's entries
   double rw[kUE], rm[kUE], tv[kUE], mt[kUE], pw[kUE], pm[kUE], sw[kUE], sm[kUE], xw[kUE], xm[kUE], gxv[kUE],
       g0v[kUE];
@@ -595,16 +612,16 @@ __global__ __launch_bounds__(256) void l_cc_update(int mode, int first, int drec
     // M t summed over the input-filter chunks in chunk order
     const double* mp = Mt + (int64_t(k) * LC * J + jj[e]) * MM + (o % MM);
     const int64_t ms = int64_t(J) * MM;
+    // eight chunks' loads at a time, all in flight together (a chunk past
+    // LC loads the last one again and adds 0)
     double acc = 0.0;
-    int lc = 0;
-    for (; lc + 8 <= LC; lc += 8) {
+    for (int lc = 0; lc < LC; lc += 8) {
       double a8[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) a8[u] = mp[(lc + u) * ms];
+      for (int u = 0; u < 8; ++u) a8[u] = mp[min(lc + u, LC - 1) * ms];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) acc += a8[u];
+      for (int u = 0; u < 8; ++u) acc += lc + u < LC ? a8[u] : 0.0;
     }
-    for (; lc < LC; ++lc) acc += mp[lc * ms];
     mt[e] = acc;
   }
   // ---- scalars
@@ -632,11 +649,16 @@ __global__ __launch_bounds__(256) void l_cc_update(int mode, int first, int drec
     for (int q = 0; q < 4; ++q)
 #pragma unroll
       for (int j = 0; j < J; ++j) ds[q][j] = 0.0;
-    for (int kk = lane; kk < K; kk += 64) {
+    for (int k0 = 0; k0 < K; k0 += 256) {
+      if (k0 > 0) dots_batch(k0);
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
+      for (int b = 0; b < 4; ++b) {
+        const bool in = k0 + 64 * b + lane < K;
 #pragma unroll
-        for (int j = 0; j < J; ++j) ds[q][j] += dots_in[(int64_t(kk) * 4 + q) * J + j];
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int j = 0; j < J; ++j) ds[q][j] += in ? dv[b][q][j] : 0.0;
+      }
     }
 #pragma unroll
     for (int j = 0; j < J; ++j) {
