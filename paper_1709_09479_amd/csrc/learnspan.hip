@@ -951,15 +951,16 @@ bool span_eligible(const Plan& pl) {
 // measured on the benchmark's call: the direct form streams the code
 // spectra twice per CG step (about 4 TB/s on cache-resident sets) plus ~15 us
 // of small launches; the span form builds the correlation table once (about
-// 8e12 float64 multiply-adds/s, ~70 us for the column stage) and then costs
-// one product with M (about 6e12 multiply-adds/s) and ~8 us per step.
+// 13e12 float64 multiply-adds/s counted as below, ~70 us for the column
+// stage) and then costs one product with M (about 6e12 multiply-adds/s) and
+// ~7 us per step.
 bool span_preferred(const Plan& pl, int inner_iters, int cg_iters) {
   const SpanDims s = span_dims(pl);
   const double steps = double(inner_iters) * (cg_iters + 1);
   const double D = double(pl.g[1]) * pl.g[2];
   const double direct = steps * (2.0 * pl.n * pl.p * D * 8.0 / 4e12 + 15e-6);
-  const double table = double(s.Hc) * pl.g[2] * s.NTP * kNP * (pl.n + s.M2) * 4.0 / 8e12 + 70e-6;
-  const double span = table + steps * (double(s.J) * s.K * s.K * s.MM * s.MM / 6e12 + 8e-6);
+  const double table = double(s.Hc) * pl.g[2] * s.NTP * kNP * (pl.n + s.M2) * 4.0 / 13e12 + 70e-6;
+  const double span = table + steps * (double(s.J) * s.K * s.K * s.MM * s.MM / 6e12 + 7e-6);
   return span < direct;
 }
 
