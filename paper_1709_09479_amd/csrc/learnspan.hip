@@ -353,49 +353,80 @@ __global__ __launch_bounds__(256) void l_cc_lags(const double2* __restrict__ Tr,
                                                  double* __restrict__ gx, double* __restrict__ g0,
                                                  double* __restrict__ s0, int K, int J, int H, int W, int M1,
                                                  int M2, int LT, int NTP) {
+  // 64 (pair, delta2) items per workgroup, the canonical rows split over its
+  // four wavefronts (more wavefronts in flight than one thread per item);
+  // the partial sums meet in LDS
   __shared__ double2 tw[256];
+  __shared__ double red[3][2][8][64];
   const int E2 = 2 * M2 - 1, MM = M1 * M2, EP = span_lag_stride(M1, M2);
-  const int per = kNP * E2, bpt = (per + 255) / 256;
-  const int tpi = blockIdx.x / bpt, idx = (blockIdx.x % bpt) * 256 + threadIdx.x;
+  const int per = kNP * E2, bpt = (per + 63) / 64;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int tpi = blockIdx.x / bpt, idx = (blockIdx.x % bpt) * 64 + lane;
   for (int i = threadIdx.x; i < H; i += 256) {
     double s, c;
     sincospi(2.0 * i / H, &s, &c);
     tw[i] = make_double2(c, s);
   }
   __syncthreads();
-  if (idx >= per) return;
   int A, B;
   tile_pair(tpi, LT, A, B);
   const int pi = idx / E2, e2 = idx % E2, d2 = e2 - (M2 - 1);
   const int a = A * kTL + (pi >> 3), b = B * kTL + (pi & 7), L = K + 2 * J;
-  if (a >= L || b >= L || (A == B && a > b)) return;
   // what the pair feeds
   int kind = 0, j = 0;  // 1: C, 2: g_x, 3: g_0, 4..6: s0 rows
-  if (a < K && b < K) kind = 1;
-  else if (a < K && b < K + J) kind = 2, j = b - K;
-  else if (a < K) kind = 3, j = b - K - J;
-  else if (a < K + J && b == a) kind = 4, j = a - K;
-  else if (a < K + J && b == a + J) kind = 5, j = a - K;
-  else if (a >= K + J && b == a) kind = 6, j = a - K - J;
-  if (kind == 0 || (kind >= 2 && d2 < 0) || (kind >= 4 && d2 != 0)) return;
+  if (idx < per && a < L && b < L && !(A == B && a > b)) {
+    if (a < K && b < K) kind = 1;
+    else if (a < K && b < K + J) kind = 2, j = b - K;
+    else if (a < K) kind = 3, j = b - K - J;
+    else if (a < K + J && b == a) kind = 4, j = a - K;
+    else if (a < K + J && b == a + J) kind = 5, j = a - K;
+    else if (a >= K + J && b == a) kind = 6, j = a - K - J;
+    if ((kind >= 2 && d2 < 0) || (kind >= 4 && d2 != 0)) kind = 0;
+  }
   double sc[16], ss[16];
 #pragma unroll
   for (int v = 0; v < 16; ++v) sc[v] = ss[v] = 0.0;
-  const double2* src = Tr + int64_t(tpi) * kNP * E2 + idx;
-  const int64_t rstride = int64_t(NTP) * kNP * E2;
-  for (int f1 = 0; f1 <= H / 2; ++f1) {
-    const double2 t = src[f1 * rstride];
-    const double wt = (f1 == 0 || f1 == H / 2) ? 1.0 : 2.0;
-    const double tx = wt * t.x, ty = wt * t.y;
+  if (kind != 0) {
+    const double2* src = Tr + int64_t(tpi) * kNP * E2 + idx;
+    const int64_t rstride = int64_t(NTP) * kNP * E2;
+    for (int f1 = wv; f1 <= H / 2; f1 += 4) {
+      const double2 t = src[f1 * rstride];
+      const double wt = (f1 == 0 || f1 == H / 2) ? 1.0 : 2.0;
+      const double tx = wt * t.x, ty = wt * t.y;
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      if (v < M1) {
-        const double2 c = tw[(f1 * v) & (H - 1)];
-        sc[v] += tx * c.x;
-        ss[v] += ty * c.y;
+      for (int v = 0; v < 16; ++v) {
+        if (v < M1) {
+          const double2 c = tw[(f1 * v) & (H - 1)];
+          sc[v] += tx * c.x;
+          ss[v] += ty * c.y;
+        }
       }
     }
   }
+  // the four partial sums, eight lags at a time
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if (h) __syncthreads();  // wavefront 0 is done with the first half
+    if (wv > 0) {
+#pragma unroll
+      for (int vl = 0; vl < 8; ++vl) {
+        red[wv - 1][0][vl][lane] = sc[8 * h + vl];
+        red[wv - 1][1][vl][lane] = ss[8 * h + vl];
+      }
+    }
+    __syncthreads();
+    if (wv == 0) {
+#pragma unroll
+      for (int vl = 0; vl < 8; ++vl) {
+#pragma unroll
+        for (int w = 0; w < 3; ++w) {
+          sc[8 * h + vl] += red[w][0][vl][lane];
+          ss[8 * h + vl] += red[w][1][vl][lane];
+        }
+      }
+    }
+  }
+  if (wv > 0 || kind == 0) return;
   const double invD = 1.0 / ((double)H * (double)W);
   if (kind == 1) {
 #pragma unroll
@@ -1008,7 +1039,7 @@ hipError_t run_span(const Plan& pl, const float2* Zh, const float2* xh, const fl
     }
 #undef SPAN_ROWS
   }
-  const int bpt = (kNP * s.E2 + 255) / 256;
+  const int bpt = (kNP * s.E2 + 63) / 64;
   hipLaunchKernelGGL(l_cc_lags, dim3((unsigned)(s.NTP * bpt)), dim3(256), 0, st, w.Tr, w.C, w.gx, w.g0, w.s0, s.K,
                      s.J, H, W, s.M1, s.M2, s.LT, s.NTP);
   const size_t lds = size_t(s.LCH) * (span_lag_stride(s.M1, s.M2) + s.J * s.MM) * sizeof(double);
