@@ -847,9 +847,9 @@ __global__ void l_cc_vhat(const float2* __restrict__ xh, const float2* __restric
 
 // U_k(f) = sum_m w_k(m) e^{-2 pi i f.m / D} at the canonical rows
 // f1 = 0 .. H/2 (index f1 W + f2), written as one half (k = 2p: .x .y,
-// k = 2p + 1: .z .w) of the pair-unpacked float4 table of pass B.  One
-// workgroup per (filter, channel): the row DFT of the M1 rows of taps, then
-// the column sums.
+// k = 2p + 1: .z .w) of the pair-unpacked float4 table of pass B.  Four
+// workgroups per (filter, channel), each forming the row DFT of the M1 rows
+// of taps and a quarter of the column sums.
 __global__ __launch_bounds__(256) void l_cc_uc(const double* __restrict__ Xw, float4* __restrict__ Uc, int K, int P,
                                                int J, int H, int W, int M1, int M2) {
   __shared__ float2 cs[16 * 256];
@@ -883,7 +883,9 @@ __global__ __launch_bounds__(256) void l_cc_uc(const double* __restrict__ Xw, fl
   }
   __syncthreads();
   float2* out = reinterpret_cast<float2*>(Uc + (int64_t(j) * P + (k >> 1)) * nc) + (k & 1);
-  for (int i = tid; i < nc; i += 256) {
+  // the column stage's outputs are shared by the gridDim.z workgroups of
+  // this (k, j), 256 at a time (each forms the small row stage itself)
+  for (int i = blockIdx.z * 256 + tid; i < nc; i += 256 * gridDim.z) {
     const int f1 = i / W, f2 = i % W;
     double re = 0.0, im = 0.0;
     for (int m1 = 0; m1 < M1; ++m1) {
@@ -1103,7 +1105,7 @@ hipError_t run_span(const Plan& pl, const float2* Zh, const float2* xh, const fl
   const int64_t D = pl.dsz;
   hipLaunchKernelGGL(l_cc_vhat, dim3((unsigned)((D + 255) / 256), (unsigned)(N * s.J)), dim3(256), 0, st, xh, gh,
                      vout, w.sc + par * int64_t(kNS) * s.J, s.J, D);
-  hipLaunchKernelGGL(l_cc_uc, dim3((unsigned)s.K, (unsigned)s.J), dim3(256), 0, st, w.v.Xw, Uc, s.K, pl.p, s.J, H, W,
+  hipLaunchKernelGGL(l_cc_uc, dim3((unsigned)s.K, (unsigned)s.J, 4u), dim3(256), 0, st, w.v.Xw, Uc, s.K, pl.p, s.J, H, W,
                      s.M1, s.M2);
   if (s.K & 1) {
     const int nc = s.Hc * W;
