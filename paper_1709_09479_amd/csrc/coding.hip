@@ -101,26 +101,43 @@ __global__ void k_gram(const float2* __restrict__ E, float2* __restrict__ G, int
   for (int a = 0; a < J; ++a)
 #pragma unroll
     for (int c = 0; c < J; ++c) gr[a][c] = gi[a][c] = 0.0;
-  for (int p = 0; p < P; ++p) {
-    double ar[J], ai[J], br[J], bi[J];
+  // a batch of pairs' loads in flight at a time (8 / 4 / 3 pairs for J = 1 /
+  // 2 / 3), unconditionally (a pair past P loads pair P - 1 again with
+  // weight 0; the sums keep their order)
+  constexpr int kB = J == 1 ? 8 : (J == 2 ? 4 : 3);
+  for (int p0 = 0; p0 < P; p0 += kB) {
+    float2 le[kB][J], lm[kB][J];
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
-      const float2 e = E[(int64_t(j) * P + p) * D + f];
-      const float2 m = E[(int64_t(j) * P + p) * D + fn];
-      ar[j] = 0.5 * ((double)e.x + m.x);
-      ai[j] = 0.5 * (-(double)e.y + m.y);
-      // i (conj(e) - m) / 2 = i ((e.x - m.x) + i(-e.y - m.y)) / 2
-      br[j] = 0.5 * ((double)e.y + m.y);
-      bi[j] = 0.5 * ((double)e.x - m.x);
-    }
+    for (int u = 0; u < kB; ++u)
 #pragma unroll
-    for (int a = 0; a < J; ++a)
-#pragma unroll
-      for (int c = 0; c < J; ++c) {
-        // x conj(y) for x = a-row, y = c-row
-        gr[a][c] += ar[a] * ar[c] + ai[a] * ai[c] + br[a] * br[c] + bi[a] * bi[c];
-        gi[a][c] += ai[a] * ar[c] - ar[a] * ai[c] + bi[a] * br[c] - br[a] * bi[c];
+      for (int j = 0; j < J; ++j) {
+        const int64_t o = (int64_t(j) * P + min(p0 + u, P - 1)) * D;
+        le[u][j] = E[o + f];
+        lm[u][j] = E[o + fn];
       }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      const double w = p0 + u < P ? 0.5 : 0.0;
+      double ar[J], ai[J], br[J], bi[J];
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        const float2 e = le[u][j], m = lm[u][j];
+        ar[j] = w * ((double)e.x + m.x);
+        ai[j] = w * (-(double)e.y + m.y);
+        // i (conj(e) - m) / 2 = i ((e.x - m.x) + i(-e.y - m.y)) / 2
+        br[j] = w * ((double)e.y + m.y);
+        bi[j] = w * ((double)e.x - m.x);
+      }
+#pragma unroll
+      for (int a = 0; a < J; ++a)
+#pragma unroll
+        for (int c = 0; c < J; ++c) {
+          // x conj(y) for x = a-row, y = c-row
+          gr[a][c] += ar[a] * ar[c] + ai[a] * ai[c] + br[a] * br[c] + bi[a] * bi[c];
+          gi[a][c] += ai[a] * ar[c] - ar[a] * ai[c] + bi[a] * br[c] - br[a] * bi[c];
+        }
+    }
   }
 #pragma unroll
   for (int a = 0; a < J; ++a)
